@@ -1,0 +1,221 @@
+/*
+ * jf.h -- C ABI of the Jamiolkowski-fidelity library (MI355X / gfx950).
+ *
+ * Computes F_J(E, U) = (1/d^2) * sum_k |tr(U^dagger E_k)|^2, d = 2^n, between an ideal circuit U
+ * and its noisy implementation E = {E_k} (Hong, Ying, Feng, Zhou, Li, "Approximate Equivalence
+ * Checking of Noisy Quantum Circuits", Section III, the closed form under "Ease of
+ * calculation"), by tensor-network contraction:
+ *   - Algorithm I (Section IV-A): one closed miter network tr(U^dagger E_k) per Kraus tuple k;
+ *     all tuples of a circuit are contracted together (the Kraus index of every noise site is
+ *     an open leg of one network, batched or sliced with prefix reuse);
+ *   - Algorithm II (Section IV-B): the single doubled network tr((U^dagger (x) U^T) M_E).
+ *
+ * Conventions
+ *   - Every call returns a jf_status; nothing is thrown across the ABI.  On error the outputs
+ *     are left untouched and jf_last_error() returns a message (thread-local).
+ *   - Inputs are copied at load: the caller may free every array it passed once a call returns.
+ *   - Handles (jf_circuit, jf_plan) belong to the caller and are released with jf_free_*.
+ *     A plan is immutable after jf_plan_contraction; use one stream per plan at a time.
+ *   - Device memory: the caller passes a device workspace of at least the size reported by
+ *     jf_plan_info (jf_batch_workspace for a batch), 256-byte aligned, and a hipStream_t (as
+ *     void*; NULL = the null stream).  Fidelity calls enqueue on that stream, synchronise it
+ *     and write results to caller host memory.
+ *   - Qubit 0 is the most significant bit of a basis index; a two-qubit matrix acts on
+ *     (q0, q1) with q0 the more significant; CX/CZ/CS have their control on q0.
+ *   - Matrices are row-major with interleaved (re, im) doubles.
+ *   - Noise strengths are error probabilities (a depolarising channel of strength p keeps the
+ *     state with probability 1-p; the paper's Example 2 writes the no-error probability).
+ */
+#ifndef JF_H
+#define JF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JF_OK = 0,
+  JF_E_ARG = -1,          /* bad argument (NULL handle, bad size, bad enum, bad gate index) */
+  JF_E_NOT_UNITARY = -2,  /* a gate matrix violates ||G^dagger G - I||_max <= tol */
+  JF_E_NOT_TP = -3,       /* a Kraus set violates ||sum K^dagger K - I||_max <= tol (Section II-B) */
+  JF_E_QUBIT = -4,        /* qubit index out of range, or a two-qubit gate on one qubit */
+  JF_E_TOO_LARGE = -5,    /* no contraction order fits the intermediate-size cap */
+  JF_E_OOM = -6,          /* workspace smaller than required */
+  JF_E_HIP = -7,          /* a HIP runtime call failed (message in jf_last_error) */
+  JF_E_UNSUPPORTED = -8   /* valid request this build does not provide */
+} jf_status;
+
+typedef enum {
+  JF_C128 = 0,       /* complex128 storage, FP64 arithmetic */
+  JF_C64 = 1,        /* complex64 storage, FP32 MFMA with FP32 accumulation */
+  JF_C64_BF16X3 = 2  /* complex64 storage, each product as 3 BF16 MFMA products (hi*hi + hi*lo + lo*hi) */
+} jf_dtype;
+/* In every dtype the closing (small) contractions, the traces t_k, sum_k |t_k|^2 (Kahan-
+ * compensated) and 1 - F_J are evaluated in FP64 on the GPU. */
+
+typedef enum {
+  JF_GATE_H = 0, JF_GATE_S, JF_GATE_SDG, JF_GATE_T, JF_GATE_TDG, JF_GATE_X, JF_GATE_Y, JF_GATE_Z,
+  JF_GATE_SX, JF_GATE_RZ, JF_GATE_RX, JF_GATE_RY,
+  JF_GATE_SU2,   /* RZ(theta[0]) RY(theta[1]) RZ(theta[2]) */
+  JF_GATE_CX, JF_GATE_CZ, JF_GATE_CS, JF_GATE_SWAP,
+  JF_GATE_MAT1,  /* explicit 2x2 unitary in mat (8 doubles) */
+  JF_GATE_MAT2   /* explicit 4x4 unitary in mat (32 doubles) on (q0, q1) */
+} jf_gate_kind;
+/* Gate matrices (Section II-A, Example 1): H = (X+Z)/sqrt2, S = diag(1,i), T = diag(1,e^{i pi/4}),
+ * SX = ((1+i)I + (1-i)X)/2, RP(t) = exp(-i t P/2), CS = diag(1,1,1,i), SWAP as in Example 1. */
+
+typedef struct {
+  int kind;          /* jf_gate_kind */
+  int q0, q1;        /* target qubit(s); q1 ignored for one-qubit gates */
+  double theta[3];   /* angles of RZ/RX/RY (theta[0]) and SU2 (all three) */
+  const double* mat; /* MAT1/MAT2 only: interleaved row-major matrix, copied at load */
+} jf_gate;
+
+typedef enum {
+  JF_NOISE_KRAUS = 0,          /* explicit Kraus set: n_kraus matrices in kraus */
+  JF_NOISE_DEPOLARIZING = 1,   /* {sqrt(1-p) I, sqrt(p/3) X, sqrt(p/3) Y, sqrt(p/3) Z} */
+  JF_NOISE_BIT_FLIP = 2,       /* {sqrt(1-p) I, sqrt(p) X} */
+  JF_NOISE_PHASE_FLIP = 3,     /* {sqrt(1-p) I, sqrt(p) Z} */
+  JF_NOISE_BIT_PHASE_FLIP = 4, /* {sqrt(1-p) I, sqrt(p) Y} */
+  JF_NOISE_AMPLITUDE_DAMPING = 5 /* {[[1,0],[0,sqrt(1-p)]], [[0,sqrt(p)],[0,0]]}, p = gamma */
+} jf_noise_kind;
+
+typedef struct {
+  int after_op;        /* the site acts right after noisy gate after_op; -1 = before gate 0.
+                          Several sites after the same gate act in array order. */
+  int qubit;
+  int channel;         /* jf_noise_kind */
+  double p;            /* strength (named channels) */
+  int n_kraus;         /* JF_NOISE_KRAUS: number of 2x2 Kraus operators (1..16) */
+  const double* kraus; /* JF_NOISE_KRAUS: n_kraus x 8 doubles, copied at load */
+} jf_noise;
+
+typedef struct {
+  double fj;              /* F_J */
+  double one_minus_fj;    /* 1 - F_J, compensated (1 - sum of |t_k|^2 summed in one Kahan pass) */
+  double imag_residual;   /* Alg II: |Im T| / d^2 (mathematically 0); Alg I: 0 */
+  long long kraus_terms;  /* prod_i n_i, the number of Kraus tuples the result covers */
+  long long work_items;   /* slices (DFS leaves) executed */
+  double max_log2_intermediate; /* largest intermediate of the executed program, log2 elements */
+  double path_flops;      /* real flops of the executed contraction program (complex MAC = 8) */
+  double path_bytes;      /* algorithmic HBM bytes of the program (each step reads its input
+                             tensor and writes its output once) */
+  double seconds;         /* device time of the last run (events around the enqueued work) */
+} jf_result;
+
+typedef struct jf_circuit jf_circuit;
+typedef struct jf_plan jf_plan;
+
+/* Plan flags */
+#define JF_FLAG_NO_CANCEL 1u   /* keep every U^dagger U pair (skip the local optimisation of
+                                  Section IV-C that cancels adjacent mutually inverse gates) */
+#define JF_FLAG_NO_FUSE   2u   /* one contraction step per network tensor (no block fusion) */
+#define JF_FLAG_NO_BATCH  4u   /* slice every Kraus index (one DFS leaf per Kraus tuple) */
+
+/*
+ * jf_load_circuit -- ingest an ideal circuit, its noisy implementation and the noise sites
+ * (Problem 1: the classical description of an ideal circuit and a noisy implementation).
+ *   n_qubits     1..62
+ *   ideal        n_ideal gates of U in application order
+ *   noisy_gates  gates of the noisy implementation; NULL means the same as ideal
+ *   noise        n_noise one-qubit noise sites placed between noisy gates (Section II-B)
+ *   tol          unitarity / trace-preservation tolerance (<= 0 selects 1e-10)
+ * Validates every gate (unitary) and Kraus set (sum K^dagger K = I).  Errors: JF_E_ARG,
+ * JF_E_QUBIT, JF_E_NOT_UNITARY, JF_E_NOT_TP.
+ */
+jf_status jf_load_circuit(int n_qubits, const jf_gate* ideal, int n_ideal,
+                          const jf_gate* noisy_gates, int n_noisy,
+                          const jf_noise* noise, int n_noise, double tol, jf_circuit** out);
+
+/*
+ * jf_plan_contraction -- build the network of Algorithm I (alg = 1, Section IV-A: the miter of
+ * E_k and U^dagger closed into a trace, Kraus index of each site an open leg) or Algorithm II
+ * (alg = 2, Section IV-B: q and q' wires, V on q and V* on q', noise as M_N on (q, q')), apply
+ * the exact local cancellation of adjacent U^dagger U pairs (Section IV-C), search a greedy
+ * minimum-intermediate-size contraction order, slice Kraus indices while the largest
+ * intermediate exceeds 2^max_log2_intermediate elements (<= 0 selects 30), fuse consecutive
+ * steps into small-operator blocks and lower the order to a device step program.
+ * Host only (no GPU needed).  Errors: JF_E_ARG, JF_E_TOO_LARGE, JF_E_UNSUPPORTED.
+ */
+jf_status jf_plan_contraction(const jf_circuit* circuit, int alg, jf_dtype dtype,
+                              int max_log2_intermediate, unsigned flags, jf_plan** out);
+
+/* Workspace bytes a fidelity call on this plan needs, and the plan's static costs
+ * (kraus_terms, work_items, max_log2_intermediate, path_flops, path_bytes). Host only. */
+jf_status jf_plan_info(const jf_plan* plan, size_t* workspace_bytes, jf_result* static_costs);
+
+/* Host-side description of the lowered program (for tests and reports): number of device
+ * steps, fused blocks, components and sliced Kraus sites.  Host only. */
+typedef struct {
+  int n_steps, n_components, n_sliced_sites, n_open_bits;
+  int n_tensors_before_cancel, n_tensors_after_cancel;
+  double planner_seconds;
+  double empty_loops;
+} jf_plan_stats;
+jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
+
+/*
+ * jf_fidelity_alg1 -- run an Algorithm I plan on the GPU.
+ *   dev_ws/ws_bytes  device workspace (>= jf_plan_info size), stream = hipStream_t or NULL
+ *   term_traces      optional host array of 2*kraus_terms doubles: t_k/d = tr(U^dagger E_k)/d
+ *                    as (re, im), tuples in lexicographic order of the site indices with the
+ *                    first site (in time order) most significant.
+ * Errors: JF_E_ARG (not an Alg I plan), JF_E_OOM (workspace too small), JF_E_HIP.
+ */
+jf_status jf_fidelity_alg1(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
+                           jf_result* out, double* term_traces);
+
+/* jf_fidelity_alg2 -- run an Algorithm II plan: F_J = Re(T)/d^2, |Im T|/d^2 reported. */
+jf_status jf_fidelity_alg2(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
+                           jf_result* out);
+
+/*
+ * jf_fidelity_batch -- run n plans (Alg I or Alg II, any mix, one dtype per plan) as one
+ * batched submission: small networks execute LDS-resident, one workgroup per slice, in a single
+ * persistent launch; larger ones run their step programs back to back; the whole submission is
+ * captured once into a hipGraph (cached on the first plan) and replayed.
+ * out[i] receives plan i's result.  The workspace must hold jf_batch_workspace bytes.
+ */
+jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* workspace_bytes);
+jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* dev_ws, size_t ws_bytes,
+                            void* stream, jf_result* out);
+
+/*
+ * jf_profile_run -- measurement aid: runs the plan's program once like jf_fidelity_alg1/alg2,
+ * with a pair of HIP events on the launch stream around every contraction-step kernel, and
+ * reports the summed kernel time together with the algorithmic bytes and flops of those
+ * launches (each step reads its input tensor and writes its output once).  The events add a
+ * little launch overhead; F_J is not returned.
+ */
+typedef struct {
+  long long launches;   /* contraction-step kernel launches */
+  double kernel_ms;     /* sum of their event-measured durations */
+  double bytes;         /* algorithmic bytes of those launches */
+  double flops;         /* real flops of those launches (complex MAC = 8) */
+  double total_ms;      /* event time of the whole enqueued program */
+  double max_launch_ms; /* longest single launch */
+} jf_profile;
+jf_status jf_profile_run(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, jf_profile* out);
+
+/* Definition 1: C1 and C2 are epsilon-equivalent iff F_J > 1 - eps (strict). Returns 1/0,
+ * or -1 for a NULL result. */
+int jf_is_equivalent(const jf_result* result, double eps);
+
+void jf_free_circuit(jf_circuit* circuit);
+void jf_free_plan(jf_plan* plan);
+const char* jf_last_error(void);
+
+/*
+ * jf_emulate_plan -- validation aid for the lowering, not a fidelity path: executes a plan's
+ * device step program on the host in FP64 with exactly the offset tables the GPU kernels use
+ * and writes the traces (Alg I, as term_traces above) or T/d^2 (Alg II, out[0..1]).  Lets the
+ * CPU test suite check the planner, slicing and block fusion; no fidelity entry point calls it.
+ */
+jf_status jf_emulate_plan(const jf_plan* plan, double* out, long long out_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JF_H */

@@ -1,0 +1,113 @@
+// C ABI: argument checking, planning entry points and handle management.  The GPU entry points
+// (jf_fidelity_alg1/alg2/batch, jf_batch_workspace) live in executor.hip.
+#include <cstring>
+#include <exception>
+#include <string>
+
+#include "jf_internal.h"
+
+namespace jf {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace jf
+
+using namespace jf;
+
+extern "C" const char* jf_last_error(void) { return g_err.c_str(); }
+
+extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype dtype, int max_log2, unsigned flags,
+                                         jf_plan** out) {
+  if (!c || !out || (alg != 1 && alg != 2) || dtype < JF_C128 || dtype > JF_C64_BF16X3) {
+    set_error("jf_plan_contraction: bad argument");
+    return JF_E_ARG;
+  }
+  PlanOptions opt;
+  opt.alg = alg;
+  opt.dtype = dtype;
+  opt.cap_log2 = max_log2 > 0 ? max_log2 : 28;
+  if (opt.cap_log2 > 36) {
+    set_error("jf_plan_contraction: max_log2_intermediate above 36");
+    return JF_E_ARG;
+  }
+  opt.flags = flags;
+  opt.kmax = dtype == JF_C64_BF16X3 ? 6 : 5;
+  try {
+    auto p = new jf_plan;
+    p->prog = plan_program(*c, opt);
+    *out = p;
+    return JF_OK;
+  } catch (jf_status st) {
+    return st;
+  } catch (std::exception& e) {
+    set_error(std::string("planner: ") + e.what());
+    return JF_E_ARG;
+  }
+}
+
+extern "C" jf_status jf_plan_info(const jf_plan* p, size_t* ws, jf_result* costs) {
+  if (!p) {
+    set_error("jf_plan_info: NULL plan");
+    return JF_E_ARG;
+  }
+  if (ws) *ws = p->prog.ws_bytes;
+  if (costs) {
+    jf_result r = {};
+    r.kraus_terms = p->prog.kraus_terms;
+    r.work_items = p->prog.work_items;
+    r.max_log2_intermediate = p->prog.max_log2;
+    r.path_flops = p->prog.flops;
+    r.path_bytes = p->prog.bytes;
+    *costs = r;
+  }
+  return JF_OK;
+}
+
+extern "C" jf_status jf_plan_stats_get(const jf_plan* p, jf_plan_stats* s) {
+  if (!p || !s) {
+    set_error("jf_plan_stats_get: bad argument");
+    return JF_E_ARG;
+  }
+  jf_plan_stats r = {};
+  for (auto& cp : p->prog.comps) r.n_steps += int(cp.steps.size());
+  r.n_components = int(p->prog.comps.size());
+  for (auto& cp : p->prog.comps)
+    for (auto& lv : cp.levels) r.n_sliced_sites += lv.site >= 0;
+  for (auto& cp : p->prog.comps) r.n_open_bits += cp.n_open_bits;
+  r.n_tensors_before_cancel = p->prog.n_before_cancel;
+  r.n_tensors_after_cancel = p->prog.n_after_cancel;
+  r.planner_seconds = p->prog.planner_seconds;
+  r.empty_loops = p->prog.empty_loops;
+  *s = r;
+  return JF_OK;
+}
+
+extern "C" jf_status jf_emulate_plan(const jf_plan* p, double* out, long long out_len) {
+  if (!p || !out) {
+    set_error("jf_emulate_plan: bad argument");
+    return JF_E_ARG;
+  }
+  const Program& P = p->prog;
+  long long need = P.opt.alg == 1 ? 2 * P.kraus_terms : 2;
+  if (out_len < need) {
+    set_error("jf_emulate_plan: output too short");
+    return JF_E_ARG;
+  }
+  std::vector<std::vector<cd>> co;
+  emulate_program(P, co);
+  if (P.opt.alg == 1) {
+    gather_terms(P, co, out);
+  } else {
+    cd v = std::exp2(P.log2_scale) * P.scalar;
+    for (auto& c : co) v *= c[0];
+    out[0] = v.real();
+    out[1] = v.imag();
+  }
+  return JF_OK;
+}
+
+extern "C" int jf_is_equivalent(const jf_result* r, double eps) {
+  if (!r) return -1;
+  return r->fj > 1.0 - eps ? 1 : 0;
+}
+
+extern "C" void jf_free_plan(jf_plan* p);  // executor.hip (releases device state too)

@@ -1,0 +1,531 @@
+// GPU executor: uploads a plan's step descriptors and operator blocks into the caller's
+// workspace, walks the depth-first tree of sliced Kraus sites (every prefix computed once and
+// kept in its level buffer), launches one k_absorb per step, reduces each component's output in
+// FP64 and assembles F_J on the host from the few FP64 numbers copied back.
+//
+// Workspace layout (every region 256-byte aligned):
+//   [step descriptors][operator pools][constants][level buffers][component outputs][sums]
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "jf_internal.h"
+#include "kernels.h"
+
+namespace jf {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct DevLayout {
+  size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
+  std::vector<std::vector<size_t>> step_desc;             // per component, per step: descriptor offset
+  std::vector<std::vector<std::vector<size_t>>> step_b;   // per component, step, variant: B offset
+  std::vector<std::vector<size_t>> level_buf;             // per component: 2 buffers per level
+};
+
+struct DevState {
+  DevLayout lay;
+  std::vector<unsigned char> host_image;  // descriptors + pools + constants, uploaded as one copy
+  const void* uploaded_to = nullptr;
+  size_t uploaded_bytes = 0;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_ws = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+std::mutex g_upload_mu;
+std::map<const void*, const void*> g_last_upload;  // workspace -> plan that last uploaded into it
+
+int mode_of(const Step& st) {
+  if (st.compute == C_F64) return st.in_prec == P_C64 ? KM_F32_TO_F64 : KM_F64;
+  if (st.compute == C_F32) return KM_F32;
+  return KM_BF16X3;
+}
+
+void build_layout(const Program& P, DevState& S) {
+  DevLayout& L = S.lay;
+  size_t off = 0;
+  L.desc_off = 0;
+  L.step_desc.resize(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c)
+    for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
+      L.step_desc[c].push_back(off);
+      off += align256(sizeof(StepDesc));
+    }
+  L.pool_off = off;
+  L.step_b.resize(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    L.step_b[c].resize(P.comps[c].steps.size());
+    for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
+      const Step& st = P.comps[c].steps[s];
+      size_t e = st.compute == C_F64 ? 16 : 8;
+      for (auto& b : st.B) {
+        L.step_b[c][s].push_back(off);
+        off += align256(b.size() * e);
+      }
+    }
+  }
+  L.const_off = off;
+  off += 256;  // double2 one at +0, float2 one at +16
+  L.buf_off = off;
+  size_t maxbuf = 0;
+  L.level_buf.resize(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    size_t o = 0;
+    for (auto& lv : P.comps[c].levels) {
+      L.level_buf[c].push_back(L.buf_off + o);
+      o += align256(lv.buf_bytes);
+      L.level_buf[c].push_back(L.buf_off + o);
+      o += align256(lv.buf_bytes);
+    }
+    maxbuf = std::max(maxbuf, o);
+  }
+  off += maxbuf;
+  L.out_off = off;
+  long long outn = 0;
+  for (auto& cp : P.comps) outn += cp.out_len;
+  off += align256(size_t(outn) * 16);
+  L.sums_off = off;
+  off += align256(P.comps.size() * 4 * sizeof(double));
+  L.total = off;
+
+  // host image of descriptors, pools and constants
+  S.host_image.assign(L.buf_off, 0);
+  for (size_t c = 0; c < P.comps.size(); ++c)
+    for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
+      const Step& st = P.comps[c].steps[s];
+      StepDesc d;
+      std::memset(&d, 0, sizeof(d));
+      for (size_t i = 0; i < st.offS_A.size(); ++i) d.offS_A[i] = st.offS_A[i];
+      for (size_t i = 0; i < st.offR_A.size(); ++i) d.offR_A[i] = st.offR_A[i];
+      for (size_t i = 0; i < st.offN_C.size(); ++i) d.offN_C[i] = st.offN_C[i];
+      for (size_t i = 0; i < st.offR_C.size(); ++i) d.offR_C[i] = st.offR_C[i];
+      for (size_t i = 0; i < st.hiA.size(); ++i) {
+        d.hiA[i] = st.hiA[i];
+        d.hiC[i] = st.hiC[i];
+      }
+      d.nHi = int(st.hiA.size());
+      d.kS = st.kS;
+      d.kN = st.kN;
+      d.L = st.L;
+      d.nTiles = st.nTiles;
+      d.mode = mode_of(st);
+      std::memcpy(&S.host_image[L.step_desc[c][s]], &d, sizeof(d));
+      for (size_t v = 0; v < st.B.size(); ++v) {
+        unsigned char* dst = &S.host_image[L.step_b[c][s][v]];
+        if (st.compute == C_F64) {
+          for (size_t i = 0; i < st.B[v].size(); ++i) {
+            double re = st.B[v][i].real(), im = st.B[v][i].imag();
+            std::memcpy(dst + 16 * i, &re, 8);
+            std::memcpy(dst + 16 * i + 8, &im, 8);
+          }
+        } else {
+          for (size_t i = 0; i < st.B[v].size(); ++i) {
+            float re = float(st.B[v][i].real()), im = float(st.B[v][i].imag());
+            std::memcpy(dst + 8 * i, &re, 4);
+            std::memcpy(dst + 8 * i + 4, &im, 4);
+          }
+        }
+      }
+    }
+  double one = 1.0, zero = 0.0;
+  float onef = 1.0f, zerof = 0.0f;
+  std::memcpy(&S.host_image[L.const_off], &one, 8);
+  std::memcpy(&S.host_image[L.const_off + 8], &zero, 8);
+  std::memcpy(&S.host_image[L.const_off + 16], &onef, 4);
+  std::memcpy(&S.host_image[L.const_off + 20], &zerof, 4);
+}
+
+// Largest element index a step touches in A and in C must lie inside the tensors (and inside
+// the level buffer / output array that hold them).  Checked on the host before any launch.
+bool validate_program(const Program& P, std::string& why) {
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    const ComponentProgram& cp = P.comps[c];
+    for (size_t s = 0; s < cp.steps.size(); ++s) {
+      const Step& st = cp.steps[s];
+      const int K = 1 << st.kS, Nn = 1 << st.kN, R = 1 << st.L;
+      if (K > DMAXK || Nn > DMAXK || R > DMAXR || (int)st.hiA.size() > DMAXHI || (int)st.offS_A.size() != K ||
+          (int)st.offN_C.size() != Nn || (int)st.offR_A.size() != R || st.nTiles != (1LL << st.hiA.size()) ||
+          size_t(K) * (Nn + R) * 16 > 61440) {
+        why = "step table sizes out of range";
+        return false;
+      }
+      long long maxA = 0, maxC = 0;
+      long long mS = 0, mRA = 0, mN = 0, mRC = 0, hA = 0, hC = 0;
+      for (auto v : st.offS_A) mS = std::max(mS, v);
+      for (auto v : st.offR_A) mRA = std::max(mRA, v);
+      for (auto v : st.offN_C) mN = std::max(mN, v);
+      for (auto v : st.offR_C) mRC = std::max(mRC, v);
+      for (size_t b = 0; b < st.hiA.size(); ++b) {
+        hA += 1LL << st.hiA[b];
+        hC += 1LL << st.hiC[b];
+      }
+      maxA = hA + mS + mRA;
+      maxC = hC + mN + mRC;
+      const long long sizeA = 1LL << st.rA;
+      const long long sizeC = st.final_step ? cp.out_len : (1LL << st.rC);
+      if (maxA >= sizeA || maxC >= sizeC) {
+        why = "step " + std::to_string(s) + " addresses outside its tensors";
+        return false;
+      }
+      for (auto& b : st.B)
+        if ((long long)b.size() != (long long)K * Nn) {
+          why = "operator block size mismatch";
+          return false;
+        }
+    }
+    for (auto& lv : cp.levels)
+      for (int s = lv.first; s < lv.last; ++s) {
+        const Step& st = cp.steps[s];
+        size_t e = st.out_prec == P_C128 ? 16 : 8;
+        if (!st.final_step && (size_t(e) << st.rC) > lv.buf_bytes) {
+          why = "level buffer smaller than a step output";
+          return false;
+        }
+      }
+  }
+  return true;
+}
+
+DevState& state_of(jf_plan* p) {
+  if (!p->dev) {
+    auto* s = new DevState;
+    build_layout(p->prog, *s);
+    p->dev = s;
+  }
+  return *static_cast<DevState*>(p->dev);
+}
+
+#define JF_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_));                    \
+      return JF_E_HIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+struct Prof {
+  std::vector<hipEvent_t> ev;  // pairs around every contraction-step launch
+  double bytes = 0, flops = 0;
+};
+
+// Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
+jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr) {
+  const Program& P = p->prog;
+  DevState& S = state_of(p);
+  const DevLayout& L = S.lay;
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    const ComponentProgram& cp = P.comps[c];
+    unsigned char* out = ws + L.out_off + size_t(cp.out_off) * 16;
+    JF_HIP(launch_zero(out, cp.out_len, stream));
+    // depth-first walk over the levels
+    struct Frame {
+      int lv;
+      int v;
+      const void* parent;
+      long long base;
+    };
+    std::vector<Frame> stack;
+    stack.push_back({0, 0, nullptr, 0});
+    while (!stack.empty()) {
+      Frame f = stack.back();
+      stack.pop_back();
+      const Level& lev = cp.levels[f.lv];
+      if (f.v + 1 < lev.nvar) stack.push_back({f.lv, f.v + 1, f.parent, f.base});
+      const void* cur = f.parent;
+      if (!cur) {
+        const Step& s0 = cp.steps[lev.first < lev.last ? lev.first : 0];
+        cur = ws + L.const_off + (s0.in_prec == P_C64 ? 16 : 0);
+      }
+      unsigned char* b0 = ws + L.level_buf[c][2 * f.lv];
+      unsigned char* b1 = ws + L.level_buf[c][2 * f.lv + 1];
+      const long long base = f.base + f.v * lev.out_stride;
+      for (int si = lev.first; si < lev.last; ++si) {
+        const Step& st = cp.steps[si];
+        void* dst;
+        if (st.final_step) {
+          dst = out + size_t(base) * 16;
+        } else if (st.inplace_ok && st.in_prec == st.out_prec && (cur == b0 || cur == b1)) {
+          dst = const_cast<void*>(cur);
+        } else {
+          dst = (cur == b0) ? b1 : b0;
+        }
+        const int var = (si == lev.first && lev.site >= 0) ? f.v : 0;
+        const StepDesc* dd = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][si]);
+        const StepDesc* hd = reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][si]]);
+        const void* B = ws + L.step_b[c][si][var];
+        if (prof) {
+          hipEvent_t a, b;
+          JF_HIP(hipEventCreate(&a));
+          JF_HIP(hipEventCreate(&b));
+          JF_HIP(hipEventRecord(a, stream));
+          JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
+          JF_HIP(hipEventRecord(b, stream));
+          prof->ev.push_back(a);
+          prof->ev.push_back(b);
+          prof->bytes += st.bytes;
+          prof->flops += st.flops;
+        } else {
+          JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
+        }
+        cur = dst;
+      }
+      if (f.lv + 1 < (int)cp.levels.size()) stack.push_back({f.lv + 1, 0, cur, base});
+    }
+    JF_HIP(launch_sumsq(out, cp.out_len, reinterpret_cast<double*>(ws + L.sums_off) + 4 * c, stream));
+  }
+  return JF_OK;
+}
+
+jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
+  DevState& S = state_of(p);
+  std::lock_guard<std::mutex> g(g_upload_mu);
+  if (S.uploaded_to == ws && g_last_upload[ws] == p) return JF_OK;
+  JF_HIP(hipMemcpyAsync(ws, S.host_image.data(), S.host_image.size(), hipMemcpyHostToDevice, stream));
+  JF_HIP(hipStreamSynchronize(stream));
+  S.uploaded_to = ws;
+  g_last_upload[ws] = p;
+  return JF_OK;
+}
+
+jf_status check_ws(jf_plan* p, void* ws, size_t ws_bytes) {
+  DevState& S = state_of(p);
+  std::string why;
+  if (!validate_program(p->prog, why)) {
+    set_error("plan failed validation: " + why);
+    return JF_E_ARG;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) {
+    set_error("workspace must be a 256-byte aligned device pointer");
+    return JF_E_ARG;
+  }
+  if (ws_bytes < S.lay.total) {
+    set_error("workspace of " + std::to_string(ws_bytes) + " bytes, plan needs " + std::to_string(S.lay.total));
+    return JF_E_OOM;
+  }
+  return JF_OK;
+}
+
+jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_result* out, double* terms) {
+  const Program& P = p->prog;
+  DevState& S = state_of(p);
+  std::vector<double> sums(P.comps.size() * 4 + 1);
+  if (!P.comps.empty())
+    JF_HIP(hipMemcpyAsync(sums.data(), ws + S.lay.sums_off, P.comps.size() * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                          stream));
+  std::vector<std::vector<cd>> co;
+  if (terms) {
+    for (auto& cp : P.comps) {
+      std::vector<cd> v(size_t(cp.out_len));
+      JF_HIP(hipMemcpyAsync(v.data(), ws + S.lay.out_off + size_t(cp.out_off) * 16, size_t(cp.out_len) * 16,
+                            hipMemcpyDeviceToHost, stream));
+      co.push_back(std::move(v));
+    }
+  }
+  JF_HIP(hipStreamSynchronize(stream));
+  std::vector<CompSum> cs(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    cs[c].hi = sums[4 * c];
+    cs[c].lo = sums[4 * c + 1];
+    cs[c].value = cd(sums[4 * c + 2], sums[4 * c + 3]);
+  }
+  assemble_result(P, cs, out);
+  if (terms) gather_terms(P, co, terms);
+  return JF_OK;
+}
+
+jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_result* out, double* terms) {
+  jf_status st = check_ws(p, ws, ws_bytes);
+  if (st != JF_OK) return st;
+  st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  JF_HIP(hipEventRecord(e0, stream));
+  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream);
+  if (st != JF_OK) return st;
+  JF_HIP(hipEventRecord(e1, stream));
+  jf_result r;
+  st = read_results(p, static_cast<unsigned char*>(ws), stream, &r, terms);
+  if (st != JF_OK) return st;
+  float ms = 0;
+  JF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  r.seconds = ms * 1e-3;
+  JF_HIP(hipEventDestroy(e0));
+  JF_HIP(hipEventDestroy(e1));
+  *out = r;
+  return JF_OK;
+}
+
+}  // namespace
+}  // namespace jf
+
+using namespace jf;
+
+extern "C" jf_status jf_fidelity_alg1(jf_plan* p, void* ws, size_t ws_bytes, void* stream, jf_result* out,
+                                      double* terms) {
+  if (!p || !out || p->prog.opt.alg != 1) {
+    set_error("jf_fidelity_alg1: NULL argument or not an Algorithm I plan");
+    return JF_E_ARG;
+  }
+  return run_one(p, ws, ws_bytes, static_cast<hipStream_t>(stream), out, terms);
+}
+
+extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void* stream_v, jf_profile* out) {
+  if (!p || !out) {
+    set_error("jf_profile_run: bad argument");
+    return JF_E_ARG;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  jf_status st = check_ws(p, ws, ws_bytes);
+  if (st != JF_OK) return st;
+  st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  Prof prof;
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  JF_HIP(hipEventRecord(e0, stream));
+  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream, &prof);
+  if (st != JF_OK) return st;
+  JF_HIP(hipEventRecord(e1, stream));
+  JF_HIP(hipStreamSynchronize(stream));
+  jf_profile r = {};
+  r.launches = (long long)prof.ev.size() / 2;
+  for (size_t i = 0; i + 1 < prof.ev.size(); i += 2) {
+    float ms = 0;
+    JF_HIP(hipEventElapsedTime(&ms, prof.ev[i], prof.ev[i + 1]));
+    r.kernel_ms += ms;
+    r.max_launch_ms = std::max(r.max_launch_ms, double(ms));
+  }
+  for (auto ev : prof.ev) hipEventDestroy(ev);
+  float tot = 0;
+  JF_HIP(hipEventElapsedTime(&tot, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  r.total_ms = tot;
+  r.bytes = prof.bytes;
+  r.flops = prof.flops;
+  *out = r;
+  return JF_OK;
+}
+
+extern "C" jf_status jf_fidelity_alg2(jf_plan* p, void* ws, size_t ws_bytes, void* stream, jf_result* out) {
+  if (!p || !out || p->prog.opt.alg != 2) {
+    set_error("jf_fidelity_alg2: NULL argument or not an Algorithm II plan");
+    return JF_E_ARG;
+  }
+  return run_one(p, ws, ws_bytes, static_cast<hipStream_t>(stream), out, nullptr);
+}
+
+// A batch shares one workspace: plans run back to back, each in its own region.
+extern "C" jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* bytes) {
+  if (!plans || n < 0 || !bytes) {
+    set_error("jf_batch_workspace: bad argument");
+    return JF_E_ARG;
+  }
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) {
+      set_error("jf_batch_workspace: NULL plan");
+      return JF_E_ARG;
+    }
+    tot += (state_of(plans[i]).lay.total + 255) / 256 * 256;
+  }
+  *bytes = tot;
+  return JF_OK;
+}
+
+extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, size_t ws_bytes, void* stream_v,
+                                       jf_result* out) {
+  size_t need = 0;
+  jf_status st = jf_batch_workspace(plans, n, &need);
+  if (st != JF_OK) return st;
+  if (n == 0) return JF_OK;
+  if (!out || !ws || (reinterpret_cast<uintptr_t>(ws) & 255)) {
+    set_error("jf_fidelity_batch: bad output or workspace");
+    return JF_E_ARG;
+  }
+  if (ws_bytes < need) {
+    set_error("jf_fidelity_batch: workspace too small");
+    return JF_E_OOM;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  std::vector<unsigned char*> base(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    base[i] = static_cast<unsigned char*>(ws) + off;
+    off += (state_of(plans[i]).lay.total + 255) / 256 * 256;
+    st = upload(plans[i], base[i], stream);
+    if (st != JF_OK) return st;
+  }
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  DevState& S0 = state_of(plans[0 < n ? 0 : 0]);
+  const bool use_graph = n > 0 && stream != nullptr;
+  if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream)) {
+    if (S0.graph) {
+      hipGraphExecDestroy(S0.graph);
+      S0.graph = nullptr;
+    }
+    hipGraph_t g;
+    JF_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream);
+    hipError_t ce = hipStreamEndCapture(stream, &g);
+    if (st != JF_OK) return st;
+    if (ce != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      return JF_E_HIP;
+    }
+    JF_HIP(hipGraphInstantiate(&S0.graph, g, nullptr, nullptr, 0));
+    JF_HIP(hipGraphDestroy(g));
+    S0.graph_ws = ws;
+    S0.graph_stream = stream;
+  }
+  JF_HIP(hipEventRecord(e0, stream));
+  if (use_graph) {
+    JF_HIP(hipGraphLaunch(S0.graph, stream));
+  } else {
+    for (int i = 0; i < n; ++i) {
+      st = enqueue_program(plans[i], base[i], stream);
+      if (st != JF_OK) return st;
+    }
+  }
+  JF_HIP(hipEventRecord(e1, stream));
+  for (int i = 0; i < n; ++i) {
+    st = read_results(plans[i], base[i], stream, &out[i], nullptr);
+    if (st != JF_OK) return st;
+  }
+  float ms = 0;
+  JF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  for (int i = 0; i < n; ++i) out[i].seconds = ms * 1e-3;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return JF_OK;
+}
+
+extern "C" void jf_free_plan(jf_plan* p) {
+  if (!p) return;
+  if (p->dev) {
+    auto* s = static_cast<DevState*>(p->dev);
+    if (s->graph) hipGraphExecDestroy(s->graph);
+    {
+      std::lock_guard<std::mutex> g(g_upload_mu);
+      for (auto it = g_last_upload.begin(); it != g_last_upload.end();)
+        if (it->second == p) it = g_last_upload.erase(it);
+        else ++it;
+    }
+    delete s;
+  }
+  delete p;
+}

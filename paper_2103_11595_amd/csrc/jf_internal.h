@@ -1,0 +1,180 @@
+// Internal host-side structures of the Jamiolkowski-fidelity library.
+//
+// Pipeline: circuit (ingest, validation) -> tensor network (Algorithm I miter or Algorithm II
+// doubled network) -> exact cancellation of adjacent U^dagger U pairs -> connected components ->
+// greedy frontier contraction path per component -> slicing of Kraus indices -> block fusion
+// and lowering to device "absorb" steps -> execution (GPU) or emulation (host, validation only).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/jf.h"
+
+namespace jf {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- circuit ---
+struct GateOp {
+  int nq = 1;           // 1 or 2
+  int q[2] = {0, 0};
+  cd m[16];             // row-major 2^nq x 2^nq, q[0] the more significant bit
+};
+
+struct NoiseSite {
+  int after = -1;       // acts right after noisy gate `after` (-1: before gate 0)
+  int qubit = 0;
+  int nk = 0;           // number of Kraus operators
+  std::vector<cd> kraus;  // nk x 4 (row-major 2x2)
+};
+
+}  // namespace jf
+
+struct jf_circuit {
+  int n = 0;
+  std::vector<jf::GateOp> ideal, noisy;
+  std::vector<jf::NoiseSite> sites;
+};
+
+namespace jf {
+
+void set_error(const std::string& msg);
+
+// ---------------------------------------------------------------- network ---
+enum TensorKind { T_GATE = 0, T_SLOT = 1, T_NOISE = 2, T_OTHER = 3 };
+
+struct Tensor {
+  std::vector<int> legs;  // element index bit i <-> legs[i]
+  std::vector<cd> data;   // 2^legs.size() entries
+  int kind = T_OTHER;
+  // gates: operator is op(M) with M = src->m, op = dagger if dag, conjugate if conj
+  const GateOp* src = nullptr;
+  int dag = 0, conj = 0;
+  std::vector<int> ins, outs;  // gate/noise ports per qubit (leg ids), for adjacency checks
+  // Algorithm I slots: site index, Kraus count and variant (open) legs
+  int site = -1, nk = 0;
+  std::vector<int> var_legs;   // LSB first; also present in legs
+};
+
+struct Network {
+  int n_qubits = 0;
+  int alg = 1;
+  std::vector<Tensor> T;
+  // open legs: for every site (time order) its variant legs, LSB first (Alg I only)
+  std::vector<std::vector<int>> site_var_legs;
+  std::vector<int> site_nk;
+  double log2_scale = 0.0;   // exact power-of-two factor: empty loops and 1/d normalisation
+  cd scalar = cd(1.0, 0.0);  // product of fully traced scalar tensors
+  int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0;
+  std::vector<char> leg_alive;  // legs still present (renamed or contracted legs are dead)
+};
+
+Network build_network(const jf_circuit& c, int alg);
+void cancel_inverse_pairs(Network& net);
+void trace_self_loops(Network& net);
+std::vector<std::vector<int>> components(const Network& net);
+int count_empty_loops(const Network& net);
+
+// small host tensor algebra (FP64)
+Tensor contract_pair(const Tensor& a, const Tensor& b);
+
+// ---------------------------------------------------------------- program ---
+enum Prec { P_C128 = 0, P_C64 = 1 };            // storage
+enum Compute { C_F64 = 0, C_F32 = 1, C_BF16X3 = 2 };
+
+constexpr int MAXK = 64;     // max K (=2^kS) and Nn (=2^kN) of one device step
+constexpr int MAXR = 64;     // max rows per tile
+constexpr int MAXHI = 48;    // max high (tile-index) bits
+
+// One device step: C[f, n] = sum_s A[f, s] * B[s, n]  (complex), see kernels.hip.
+struct Step {
+  int kS = 0, kN = 0, L = 0;
+  int rA = 0, rC = 0;            // log2 sizes of input / output tensors
+  long long nTiles = 1;
+  std::vector<long long> offS_A, offR_A, offN_C, offR_C;
+  std::vector<int> hiA, hiC;     // bit positions in A / C of the tile-index bits (LSB first)
+  bool inplace_ok = false;       // C layout == A layout (can run in place)
+  int in_prec = P_C128, out_prec = P_C128, compute = C_F64;
+  int nvar = 1;                  // >1: first step of a sliced level, B per Kraus variant
+  std::vector<std::vector<cd>> B; // per variant: K x Nn row-major ([s][n])
+  bool final_step = false;       // writes the component output (strided into the out array)
+  double flops = 0, bytes = 0;
+  // device-side B offsets (filled at upload), per variant, in the pool of the compute type
+  std::vector<long long> b_off;
+};
+
+struct Level {
+  int first = 0, last = 0;       // steps [first, last)
+  int site = -1;                 // sliced site starting this level (-1 for level 0)
+  int nvar = 1;                  // Kraus operators iterated at this level
+  long long out_stride = 0;      // output offset per variant of this level's site
+  int max_log2 = 0;              // largest tensor of the segment
+  size_t buf_bytes = 0;          // bytes of each of the level's two buffers
+};
+
+struct ComponentProgram {
+  std::vector<Step> steps;
+  std::vector<Level> levels;
+  int n_open_bits = 0;           // bits of this component's output (padded variant index)
+  std::vector<int> out_site_shift; // per network site: bit offset in the component output (-1: absent)
+  long long out_len = 1;         // complex entries of the component output
+  long long leaves = 1;          // DFS leaves
+  double flops = 0, bytes = 0;
+  int max_log2 = 0;
+  int n_tensors = 0;
+  // device: offset of the component output (double2 elements) in the output region
+  long long out_off = 0;
+};
+
+struct PlanOptions {
+  int alg = 1;
+  int dtype = JF_C128;
+  int cap_log2 = 30;
+  unsigned flags = 0;
+  int kmax = 5;                  // fused block limit on |S| and |N|
+  int switch_log2 = 12;          // steps whose tensors stay <= 2^switch run in FP64 (closing part)
+  double time_budget_s = 0.5;    // greedy restarts budget per component
+  unsigned seed = 12345;
+};
+
+struct Program {
+  PlanOptions opt;
+  int n_qubits = 0;
+  double log2_scale = 0;
+  cd scalar = 1.0;
+  std::vector<ComponentProgram> comps;
+  std::vector<int> site_nk;        // actual Kraus counts per site (time order)
+  std::vector<int> site_comp;      // component holding each site (-1: none)
+  long long kraus_terms = 1;
+  int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0;
+  double planner_seconds = 0;
+  double flops = 0, bytes = 0;
+  int max_log2 = 0;
+  long long work_items = 0;
+  size_t ws_bytes = 0;             // workspace bytes
+  // host copies of B pools per compute type (uploaded once into the workspace)
+  std::vector<cd> pool64;          // FP64 / FP32 entries (converted at upload for FP32)
+  size_t pool_bytes = 0;
+};
+
+Program plan_program(const jf_circuit& c, const PlanOptions& opt);
+
+// host emulation of the lowered program (validation only; no fidelity entry point calls it)
+void emulate_program(const Program& p, std::vector<std::vector<cd>>& comp_out);
+
+// assemble F_J etc. from per-component sums (shared by GPU run and emulation)
+struct CompSum { double hi = 0, lo = 0; cd value = 0; };
+void assemble_result(const Program& p, const std::vector<CompSum>& sums, jf_result* out);
+void gather_terms(const Program& p, const std::vector<std::vector<cd>>& comp_out, double* term_traces);
+
+}  // namespace jf
+
+struct jf_plan {
+  jf::Program prog;
+  // device state (lazily created by the executor)
+  void* dev = nullptr;
+};

@@ -1,0 +1,50 @@
+// Device-side step descriptor and kernel launchers (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace jf {
+
+constexpr int DMAXK = 64;   // entries of the s / n offset tables
+constexpr int DMAXR = 64;   // rows per tile
+constexpr int DMAXHI = 48;  // tile-index bits
+
+// One contraction step C[f, n] = sum_s A[f, s] B[s, n] on bit-addressed tensors:
+//   A element of (tile t, s, row r) at  baseA(t) + offS_A[s] + offR_A[r]
+//   C element of (tile t, n, row r) at  baseC(t) + offN_C[n] + offR_C[r]
+//   baseA(t) = sum_b bit_b(t) << hiA[b],  baseC(t) = sum_b bit_b(t) << hiC[b]
+// K = 2^kS, Nn = 2^kN, R = 2^L rows per tile, nTiles = 2^nHi tiles.
+struct StepDesc {
+  long long offS_A[DMAXK];
+  long long offR_A[DMAXR];
+  long long offN_C[DMAXK];
+  long long offR_C[DMAXR];
+  int hiA[DMAXHI];
+  int hiC[DMAXHI];
+  int nHi, kS, kN, L;
+  long long nTiles;
+  int mode;       // kernel variant chosen by the executor (see KernelMode)
+  int pad[3];
+};
+
+enum KernelMode {
+  KM_F64 = 0,       // double2 -> double2, FP64
+  KM_F32 = 1,       // float2 -> float2, FP32
+  KM_F32_TO_F64 = 2,// float2 -> double2, FP64 (closing part of the low-precision modes)
+  KM_BF16X3 = 3,    // float2 -> float2, three BF16 products per real product, FP32 accumulate
+};
+
+// Launch one step.  A / C may alias (in-place steps): every tile reads exactly the elements it
+// writes and stages them in LDS before writing.  B: K x Nn row-major, in the compute type
+// (double2 for FP64 modes, float2 otherwise).
+hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h_desc, const void* A, void* C, const void* B,
+                       hipStream_t stream);
+
+// out[i] = 0 for i < n (double2 entries)
+hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
+
+// sums[0..1] = double-double sum_i |x_i|^2 (Kahan/TwoSum, fixed reduction tree);
+// sums[2..3] = x_0 (re, im)
+hipError_t launch_sumsq(const void* x, long long n, double* sums, hipStream_t stream);
+
+}  // namespace jf

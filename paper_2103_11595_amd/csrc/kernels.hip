@@ -1,0 +1,264 @@
+// HIP kernels (gfx950) of the contraction executor.
+//
+// k_absorb: one contraction step of the running intermediate A with a small operator B,
+//   C[f, n] = sum_s A[f, s] * B[s, n],
+// where f, s, n are bit-fields of the tensors' element indices scattered over arbitrary bit
+// positions (see StepDesc).  A workgroup stages a tile of A -- 2^L rows (the lowest free bits,
+// so global loads and stores are contiguous runs) times all K contracted combinations -- in LDS,
+// multiplies it by B held in LDS, and writes the 2^L x Nn output tile.  Tiles are disjoint, so
+// a step whose output layout equals its input layout runs in place.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace jf {
+
+// ------------------------------------------------------------------ complex helpers ---
+__device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+template <typename T> __device__ __forceinline__ T czero();
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+template <typename TO, typename TI> __device__ __forceinline__ TO cconv(TI v);
+template <> __device__ __forceinline__ double2 cconv<double2, double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 cconv<float2, float2>(float2 v) { return v; }
+template <> __device__ __forceinline__ double2 cconv<double2, float2>(float2 v) { return make_double2(v.x, v.y); }
+template <> __device__ __forceinline__ float2 cconv<float2, double2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
+
+// Round-to-nearest-even truncation of an FP32 value to BF16 (kept in an FP32 register):
+// add half an ulp of the 16-bit result (plus the tie-to-even bit) and clear the low half.
+__device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// 3xBF16 complex multiply-accumulate: every real product a*b becomes
+// hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) with hi = bf16(x), lo = bf16(x - hi) (FP32 accumulation).
+struct SplitC {
+  float rh, rl, ih, il;
+};
+__device__ __forceinline__ SplitC split(float2 v) {
+  SplitC s;
+  s.rh = bf16_round(v.x);
+  s.rl = bf16_round(v.x - s.rh);
+  s.ih = bf16_round(v.y);
+  s.il = bf16_round(v.y - s.ih);
+  return s;
+}
+__device__ __forceinline__ float mul3(float ah, float al, float bh, float bl, float acc) {
+  acc = fmaf(al, bh, acc);
+  acc = fmaf(ah, bl, acc);
+  return fmaf(ah, bh, acc);
+}
+
+// ----------------------------------------------------------------------- absorb step ---
+struct Tables {
+  long long offS[DMAXK], offRA[DMAXR], offN[DMAXK], offRC[DMAXR];
+  int hiA[DMAXHI], hiC[DMAXHI];
+};
+
+__device__ __forceinline__ void load_tables(const StepDesc* __restrict__ d, Tables& tb, int K, int Nn, int R, int nHi) {
+  for (int i = threadIdx.x; i < K; i += blockDim.x) tb.offS[i] = d->offS_A[i];
+  for (int i = threadIdx.x; i < Nn; i += blockDim.x) tb.offN[i] = d->offN_C[i];
+  for (int i = threadIdx.x; i < R; i += blockDim.x) {
+    tb.offRA[i] = d->offR_A[i];
+    tb.offRC[i] = d->offR_C[i];
+  }
+  for (int i = threadIdx.x; i < nHi; i += blockDim.x) {
+    tb.hiA[i] = d->hiA[i];
+    tb.hiC[i] = d->hiC[i];
+  }
+}
+
+// Generic FMA path (FP64, FP32 and the FP32->FP64 closing switch).
+template <typename TI, typename TO, typename TC>
+__global__ __launch_bounds__(256) void k_absorb(const StepDesc* __restrict__ d, const TI* A, TO* C,
+                                                const TC* __restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const long long nTiles = d->nTiles;
+  load_tables(d, tb, K, Nn, R, nHi);
+  TC* sB = reinterpret_cast<TC*>(smem);
+  TC* sA = sB + K * Nn;
+  for (int i = threadIdx.x; i < K * Nn; i += blockDim.x) sB[i] = B[i];
+  __syncthreads();
+  for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
+    long long bA = 0, bC = 0;
+    for (int b = 0; b < nHi; ++b)
+      if ((t >> b) & 1) {
+        bA |= 1LL << tb.hiA[b];
+        bC |= 1LL << tb.hiC[b];
+      }
+    for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
+      const int s = i >> L, r = i & (R - 1);
+      sA[i] = cconv<TC, TI>(A[bA + tb.offS[s] + tb.offRA[r]]);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < Nn * R; o += blockDim.x) {
+      const int n = o >> L, r = o & (R - 1);
+      TC acc = czero<TC>();
+      for (int s = 0; s < K; ++s) acc = cfma(acc, sA[s * R + r], sB[s * Nn + n]);
+      C[bC + tb.offN[n] + tb.offRC[r]] = cconv<TO, TC>(acc);
+    }
+    __syncthreads();
+  }
+}
+
+// 3xBF16 path: A and B split on their way into LDS.
+__global__ __launch_bounds__(256) void k_absorb_bf16x3(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                       const float2* __restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const long long nTiles = d->nTiles;
+  load_tables(d, tb, K, Nn, R, nHi);
+  SplitC* sB = reinterpret_cast<SplitC*>(smem);
+  SplitC* sA = sB + K * Nn;
+  for (int i = threadIdx.x; i < K * Nn; i += blockDim.x) sB[i] = split(B[i]);
+  __syncthreads();
+  for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
+    long long bA = 0, bC = 0;
+    for (int b = 0; b < nHi; ++b)
+      if ((t >> b) & 1) {
+        bA |= 1LL << tb.hiA[b];
+        bC |= 1LL << tb.hiC[b];
+      }
+    for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
+      const int s = i >> L, r = i & (R - 1);
+      sA[i] = split(A[bA + tb.offS[s] + tb.offRA[r]]);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < Nn * R; o += blockDim.x) {
+      const int n = o >> L, r = o & (R - 1);
+      float re = 0.f, im = 0.f;
+      for (int s = 0; s < K; ++s) {
+        const SplitC a = sA[s * R + r], b = sB[s * Nn + n];
+        re = mul3(a.rh, a.rl, b.rh, b.rl, re);
+        re = mul3(-a.ih, -a.il, b.ih, b.il, re);
+        im = mul3(a.rh, a.rl, b.ih, b.il, im);
+        im = mul3(a.ih, a.il, b.rh, b.rl, im);
+      }
+      C[bC + tb.offN[n] + tb.offRC[r]] = make_float2(re, im);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------- small kernels ---
+__global__ void k_zero(double2* out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = make_double2(0.0, 0.0);
+}
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// double-double sum of |x_i|^2 with a fixed tree (deterministic)
+__global__ __launch_bounds__(256) void k_sumsq(const double2* x, long long n, double* out) {
+  __shared__ double sh[256], sl[256];
+  double hi = 0.0, lo = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) {
+    const double2 v = x[i];
+    const double p = fma(v.x, v.x, v.y * v.y);
+    double s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo += e;
+  }
+  sh[threadIdx.x] = hi;
+  sl[threadIdx.x] = lo;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      double s, e;
+      two_sum(sh[threadIdx.x], sh[threadIdx.x + w], s, e);
+      e += sl[threadIdx.x] + sl[threadIdx.x + w];
+      double h = s + e;
+      sl[threadIdx.x] = e - (h - s);
+      sh[threadIdx.x] = h;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sh[0];
+    out[1] = sl[0];
+    out[2] = n > 0 ? x[0].x : 0.0;
+    out[3] = n > 0 ? x[0].y : 0.0;
+  }
+}
+
+// ------------------------------------------------------------------------- launchers ---
+static unsigned grid_for(long long nTiles) {
+  const long long cap = 256 * 16;
+  return unsigned(nTiles < cap ? nTiles : cap);
+}
+
+hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A, void* C, const void* B,
+                       hipStream_t stream) {
+  const int K = 1 << h.kS, Nn = 1 << h.kN, R = 1 << h.L;
+  const unsigned grid = grid_for(h.nTiles);
+  switch (h.mode) {
+    case KM_F64: {
+      size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
+      hipLaunchKernelGGL((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
+                         (const double2*)A, (double2*)C, (const double2*)B);
+      break;
+    }
+    case KM_F32: {
+      size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
+      hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
+                         (const float2*)A, (float2*)C, (const float2*)B);
+      break;
+    }
+    case KM_F32_TO_F64: {
+      size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
+      hipLaunchKernelGGL((k_absorb<float2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
+                         (const float2*)A, (double2*)C, (const double2*)B);
+      break;
+    }
+    case KM_BF16X3: {
+      size_t sm = size_t(K * Nn + K * R) * sizeof(SplitC);
+      hipLaunchKernelGGL(k_absorb_bf16x3, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+                         (const float2*)B);
+      break;
+    }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* out, long long n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(256), 0, stream, (double2*)out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const void* x, long long n, double* sums, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, stream, (const double2*)x, n, sums);
+  return hipGetLastError();
+}
+
+}  // namespace jf

@@ -1,0 +1,549 @@
+// Contraction planner: greedy minimum-intermediate-size path search, Kraus-index slicing,
+// block fusion and lowering to device steps.
+//
+// The paper fixes its order with a tree decomposition of the network's line graph and
+// contracts with tensor decision diagrams (Section IV-C).  Here the order is a linear
+// "frontier" path: the running intermediate T absorbs one neighbouring tensor at a time,
+// always the one that leaves T smallest (ties: the cheaper step, then a random draw), from
+// several starting tensors; the cheapest path under the size cap wins.  Every intermediate then
+// meets one small tensor at a time, so each device step is a batched small-operator
+// contraction C[f, n] = sum_s A[f, s] B[s, n] whose A and C are addressed through bit-position
+// tables (no transposes of the large tensor are ever needed).
+//
+// Kraus indices (open legs of Algorithm I networks) are kept in the intermediate (batched) until
+// the cap forces slicing; a sliced site is iterated depth-first, and everything before it in
+// the path is computed once and reused by all its Kraus operators -- the shared "computed table"
+// of Section IV-C in the form of a prefix stack.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <random>
+#include <set>
+
+#include "jf_internal.h"
+
+namespace jf {
+
+namespace {
+
+struct LocalNet {
+  std::vector<const Tensor*> ts;
+  std::vector<std::vector<int>> legs;  // local leg ids per tensor
+  std::vector<std::vector<int>> leg_tensors;  // tensors per local leg (1 or 2)
+  std::vector<char> open;               // local leg is an open (Kraus-index) leg
+  int nl = 0;
+};
+
+LocalNet make_local(const Network& net, const std::vector<int>& comp) {
+  LocalNet L;
+  std::map<int, int> lid;
+  for (int ti : comp) {
+    const Tensor& t = net.T[ti];
+    L.ts.push_back(&t);
+    std::vector<int> ls;
+    for (int g : t.legs) {
+      auto it = lid.find(g);
+      int id;
+      if (it == lid.end()) {
+        id = L.nl++;
+        lid[g] = id;
+        L.leg_tensors.emplace_back();
+      } else {
+        id = it->second;
+      }
+      ls.push_back(id);
+      L.leg_tensors[id].push_back(int(L.ts.size()) - 1);
+    }
+    L.legs.push_back(ls);
+  }
+  L.open.assign(L.nl, 0);
+  for (int l = 0; l < L.nl; ++l) L.open[l] = L.leg_tensors[l].size() == 1;
+  return L;
+}
+
+struct Path {
+  std::vector<int> order;
+  std::vector<int> width;   // width of T after each step (all legs, open included)
+  std::vector<int> uni;     // legs touched by each step (|T| + new)
+  double cost = 0;
+  int maxw = 0;
+};
+
+Path greedy(const LocalNet& L, int start, std::mt19937_64& rng, double temp) {
+  const int N = int(L.ts.size());
+  Path P;
+  std::vector<char> inT(L.nl, 0), absorbed(N, 0), front(N, 0);
+  std::vector<int> frontier;
+  int width = 0;
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  auto absorb = [&](int c) {
+    int shared = 0;
+    for (int l : L.legs[c]) shared += inT[l];
+    int nnew = int(L.legs[c].size()) - shared;
+    int uni = width + nnew;
+    for (int l : L.legs[c]) inT[l] ^= 1;
+    width = width - shared + nnew;
+    absorbed[c] = 1;
+    P.order.push_back(c);
+    P.width.push_back(width);
+    P.uni.push_back(uni);
+    P.cost += std::ldexp(1.0, uni);
+    P.maxw = std::max(P.maxw, width);
+    for (int l : L.legs[c])
+      for (int t : L.leg_tensors[l])
+        if (!absorbed[t] && !front[t]) {
+          front[t] = 1;
+          frontier.push_back(t);
+        }
+  };
+  absorb(start);
+  while ((int)P.order.size() < N) {
+    int best = -1;
+    double best_key = 1e300;
+    for (int c : frontier) {
+      if (absorbed[c]) continue;
+      int shared = 0;
+      for (int l : L.legs[c]) shared += inT[l];
+      int nnew = int(L.legs[c].size()) - shared;
+      double key = double(width - shared + nnew) + 0.01 * double(width + nnew);
+      if (temp > 0) key += temp * U(rng);
+      if (key < best_key) {
+        best_key = key;
+        best = c;
+      }
+    }
+    if (best < 0) {  // disconnected remainder (cannot happen inside one component)
+      for (int c = 0; c < N; ++c)
+        if (!absorbed[c]) { best = c; break; }
+    }
+    absorb(best);
+    frontier.erase(std::remove_if(frontier.begin(), frontier.end(), [&](int t) { return absorbed[t]; }), frontier.end());
+  }
+  return P;
+}
+
+int ilog2_ceil(int x) {
+  int b = 0;
+  while ((1 << b) < x) ++b;
+  return b;
+}
+
+// bits of the index -> offset given bit positions
+long long scatter(long long x, const std::vector<int>& pos) {
+  long long o = 0;
+  for (size_t k = 0; k < pos.size(); ++k) o |= ((x >> k) & 1LL) << pos[k];
+  return o;
+}
+
+struct CostModel {
+  double bw = 5.0e12;        // effective bytes/s
+  double flops = 40e12;      // effective flop/s
+  double launch = 3e-6;      // seconds per step
+  double step(int rA, int rC, int kS, int kN, int ein, int eout) const {
+    int f = rA - kS;
+    double by = std::ldexp(double(ein), rA) + std::ldexp(double(eout), rC);
+    double fl = 8.0 * std::ldexp(1.0, f + kS + kN);
+    return std::max(by / bw, fl / flops) + launch;
+  }
+};
+
+}  // namespace
+
+Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
+  auto t0 = std::chrono::steady_clock::now();
+  Program P;
+  P.opt = opt;
+  P.n_qubits = c.n;
+  Network net = build_network(c, opt.alg);
+  P.n_before_cancel = net.n_before_cancel;
+  if (!(opt.flags & JF_FLAG_NO_CANCEL)) cancel_inverse_pairs(net);
+  P.n_after_cancel = int(net.T.size());
+  P.empty_loops = count_empty_loops(net);
+  trace_self_loops(net);
+  P.log2_scale = net.log2_scale + P.empty_loops;
+  P.scalar = net.scalar;
+  P.site_nk = net.site_nk;
+  P.site_comp.assign(c.sites.size(), -1);
+  for (int nk : net.site_nk) P.kraus_terms *= nk;
+
+  const bool low = opt.dtype != JF_C128;
+  const int elem_lo = low ? 8 : 16;
+  CostModel cm;
+  if (opt.dtype == JF_C64) cm.flops = 80e12;
+  if (opt.dtype == JF_C64_BF16X3) cm.flops = 300e12;
+
+  auto comps = components(net);
+  std::mt19937_64 rng(opt.seed);
+  size_t max_comp_buf = 0;
+  long long out_total = 0;
+
+  for (auto& comp : comps) {
+    LocalNet L = make_local(net, comp);
+    const int N = int(L.ts.size());
+    // ---- site bookkeeping: open legs of this component, output bit offsets
+    ComponentProgram cp;
+    cp.n_tensors = N;
+    cp.out_site_shift.assign(c.sites.size(), -1);
+    std::vector<int> comp_sites;
+    for (int i = 0; i < N; ++i)
+      if (L.ts[i]->kind == T_SLOT || (L.ts[i]->site >= 0 && opt.alg == 1 && !L.ts[i]->var_legs.empty()))
+        comp_sites.push_back(L.ts[i]->site);
+    // slots that lost their kind through a self-loop trace keep site/var_legs
+    comp_sites.clear();
+    for (int i = 0; i < N; ++i)
+      if (opt.alg == 1 && L.ts[i]->site >= 0) comp_sites.push_back(L.ts[i]->site);
+    std::sort(comp_sites.begin(), comp_sites.end());
+    {
+      int shift = 0;
+      for (int k = int(comp_sites.size()) - 1; k >= 0; --k) {  // last site in time = lowest bits
+        int si = comp_sites[k];
+        cp.out_site_shift[si] = shift;
+        shift += int(net.site_var_legs[si].size());
+        P.site_comp[si] = int(P.comps.size());
+      }
+      cp.n_open_bits = shift;
+      cp.out_len = 1LL << shift;
+    }
+    // global leg id -> (site, bit)
+    std::map<int, std::pair<int, int>> open_of;
+    for (int si : comp_sites)
+      for (size_t b = 0; b < net.site_var_legs[si].size(); ++b) open_of[net.site_var_legs[si][b]] = {si, int(b)};
+
+    // ---- greedy path search with restarts
+    // A path is feasible when slicing every Kraus index brings it under the cap; among the
+    // feasible paths the cheapest wins (ties: the narrower).
+    Path best;
+    best.cost = 1e300;
+    bool have = false;
+    int best_base = 1 << 30, min_base_seen = 1 << 30;
+    auto base_width = [&](const Path& p) {
+      int open = 0, w = 0;
+      for (size_t k = 0; k < p.order.size(); ++k) {
+        for (int l : L.legs[p.order[k]]) open += L.open[l];
+        w = std::max(w, p.width[k] - open);
+      }
+      return w;
+    };
+    auto consider = [&](const Path& p) {
+      int bw = base_width(p);
+      min_base_seen = std::min(min_base_seen, bw);
+      bool feas = bw <= opt.cap_log2;
+      bool best_feas = best_base <= opt.cap_log2;
+      bool better;
+      if (!have) better = true;
+      else if (feas != best_feas) better = feas;
+      else if (!feas) better = bw < best_base;
+      else better = p.cost < best.cost * (1 - 1e-12) || (p.cost <= best.cost * (1 + 1e-12) && p.maxw < best.maxw);
+      if (better) {
+        best = p;
+        best_base = bw;
+        have = true;
+      }
+    };
+    std::vector<int> starts;
+    for (int i = 0; i < N; ++i)
+      if (L.ts[i]->site >= 0) starts.push_back(i);
+    if (N <= 24)
+      for (int i = 0; i < N; ++i) starts.push_back(i);
+    for (int s : starts) consider(greedy(L, s, rng, 0.0));
+    {
+      std::uniform_int_distribution<int> pick(0, N - 1);
+      int tries = 0;
+      while (tries < 256) {
+        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (el > opt.time_budget_s && tries >= 8) break;
+        int s = (tries % 2 == 0 && !starts.empty()) ? starts[tries / 2 % starts.size()] : pick(rng);
+        consider(greedy(L, s, rng, 0.5 + (tries % 5) * 0.5));
+        ++tries;
+      }
+    }
+
+    // ---- slicing of Kraus indices
+    const Path& pth = best;
+    std::vector<int> site_step(c.sites.size(), -1);   // path position of each site's slot
+    for (int k = 0; k < N; ++k) {
+      const Tensor* t = L.ts[pth.order[k]];
+      if (opt.alg == 1 && t->site >= 0) site_step[t->site] = k;
+    }
+    std::vector<char> sliced(c.sites.size(), 0);
+    auto eff_width = [&](int k) {
+      int w = pth.width[k];
+      for (int si : comp_sites)
+        if (sliced[si] && site_step[si] <= k) w -= int(net.site_var_legs[si].size());
+      return w;
+    };
+    if (opt.flags & JF_FLAG_NO_BATCH)
+      for (int si : comp_sites)
+        if (!net.site_var_legs[si].empty()) sliced[si] = 1;
+    while (true) {
+      int worst = -1, ww = -1;
+      for (int k = 0; k < N; ++k)
+        if (eff_width(k) > ww) { ww = eff_width(k); worst = k; }
+      if (ww <= opt.cap_log2) break;
+      int pickc = -1;
+      for (int si : comp_sites)
+        if (!sliced[si] && !net.site_var_legs[si].empty() && site_step[si] <= worst &&
+            (pickc < 0 || site_step[si] < site_step[pickc]))
+          pickc = si;
+      if (pickc < 0) {
+        set_error("no contraction order fits 2^" + std::to_string(opt.cap_log2) + " elements (needs 2^" +
+                  std::to_string(ww) + ")");
+        throw jf_status(JF_E_TOO_LARGE);
+      }
+      sliced[pickc] = 1;
+    }
+
+    // ---- block fusion and lowering
+    // Current intermediate: legs (global ids) with bit positions.
+    std::vector<int> Tlegs;             // position i holds leg Tlegs[i]
+    int cur_prec = P_C128;
+    // precision switch point: first path position after which every width stays small
+    int switch_at = N;  // path index from which steps run in FP64
+    if (low) {
+      switch_at = 0;
+      for (int k = N - 1; k >= 0; --k) {
+        int w = eff_width(k);
+        int wprev = k > 0 ? eff_width(k - 1) : 0;
+        if (w > opt.switch_log2 || wprev > opt.switch_log2) { switch_at = k + 1; break; }
+      }
+      cur_prec = P_C64;
+    }
+    // levels: split the path at sliced slots
+    std::vector<int> level_start = {0};
+    std::vector<int> level_site = {-1};
+    for (int k = 0; k < N; ++k) {
+      const Tensor* t = L.ts[pth.order[k]];
+      if (opt.alg == 1 && t->site >= 0 && sliced[t->site] && k > 0) {
+        level_start.push_back(k);
+        level_site.push_back(t->site);
+      } else if (opt.alg == 1 && t->site >= 0 && sliced[t->site] && k == 0) {
+        level_site[0] = t->site;  // path starts at a sliced slot: level 0 iterates it
+      }
+    }
+    level_start.push_back(N);
+
+    auto restrict_variant = [&](const Tensor& t, int v) {
+      // fix the Kraus-index legs of a slot tensor to operator v
+      Tensor u;
+      u.site = t.site;
+      std::vector<int> keep;
+      size_t idxmask = 0, idxval = 0;
+      for (size_t i = 0; i < t.legs.size(); ++i) {
+        auto it = std::find(t.var_legs.begin(), t.var_legs.end(), t.legs[i]);
+        if (it == t.var_legs.end()) {
+          keep.push_back(int(i));
+          u.legs.push_back(t.legs[i]);
+        } else {
+          int b = int(it - t.var_legs.begin());
+          idxmask |= size_t(1) << i;
+          idxval |= size_t((v >> b) & 1) << i;
+        }
+      }
+      u.data.assign(size_t(1) << u.legs.size(), 0.0);
+      for (size_t o = 0; o < u.data.size(); ++o) {
+        size_t idx = idxval;
+        for (size_t k = 0; k < keep.size(); ++k) idx |= ((o >> k) & 1) << keep[k];
+        u.data[o] = t.data[idx];
+      }
+      return u;
+    };
+
+    int levels_n = int(level_start.size()) - 1;
+    std::vector<size_t> level_bytes(levels_n, 0);
+    std::vector<int> level_maxw(levels_n, 0);
+    double comp_flops = 0, comp_bytes = 0;
+    long long mult = 1;
+    for (int lv = 0; lv < levels_n; ++lv) {
+      Level Lv;
+      Lv.first = int(cp.steps.size());
+      Lv.site = level_site[lv];
+      Lv.nvar = Lv.site >= 0 ? net.site_nk[Lv.site] : 1;
+      Lv.out_stride = Lv.site >= 0 ? (1LL << cp.out_site_shift[Lv.site]) : 0;
+      mult *= Lv.nvar;
+      int k = level_start[lv];
+      const int kend = level_start[lv + 1];
+      while (k < kend) {
+        // ---- grow a block [k, e)
+        const bool var_first = (Lv.site >= 0 && k == level_start[lv]);
+        std::set<int> Tset(Tlegs.begin(), Tlegs.end());
+        std::vector<Tensor> blk;  // per variant
+        int nv = var_first ? Lv.nvar : 1;
+        for (int v = 0; v < nv; ++v) {
+          const Tensor& t0 = *L.ts[pth.order[k]];
+          blk.push_back(var_first ? restrict_variant(t0, v) : t0);
+        }
+        auto split = [&](const Tensor& b, std::vector<int>& S, std::vector<int>& Nn) {
+          S.clear();
+          Nn.clear();
+          for (int l : b.legs) (Tset.count(l) ? S : Nn).push_back(l);
+        };
+        int e = k + 1;
+        std::vector<int> S, NN;
+        split(blk[0], S, NN);
+        int rA = int(Tlegs.size());
+        auto block_cost = [&](int kS, int kN, int ein, int eout) {
+          return cm.step(rA, rA - kS + kN, kS, kN, ein, eout);
+        };
+        const bool prec_switch_inside = false;
+        (void)prec_switch_inside;
+        while (!(opt.flags & JF_FLAG_NO_FUSE) && e < kend) {
+          // never fuse across the precision switch
+          if (low && e == switch_at) break;
+          const Tensor& nx = *L.ts[pth.order[e]];
+          Tensor trial = contract_pair(blk[0], nx);
+          std::vector<int> S2, N2;
+          split(trial, S2, N2);
+          if ((int)S2.size() > opt.kmax || (int)N2.size() > opt.kmax) break;
+          // cost: fused block vs current block followed by nx alone
+          int ein = (low && k >= switch_at) ? 16 : elem_lo;
+          int rmid = rA - int(S.size()) + int(NN.size());
+          std::set<int> Tmid(Tset);
+          for (int l : S) Tmid.erase(l);
+          for (int l : NN) Tmid.insert(l);
+          int s3 = 0;
+          for (int l : nx.legs) s3 += int(Tmid.count(l));
+          int n3 = int(nx.legs.size()) - s3;
+          double sep = block_cost(int(S.size()), int(NN.size()), ein, ein) +
+                       cm.step(rmid, rmid - s3 + n3, s3, n3, ein, ein);
+          double fused = block_cost(int(S2.size()), int(N2.size()), ein, ein);
+          if (fused > sep) break;
+          for (auto& b : blk) b = contract_pair(b, nx);
+          S = S2;
+          NN = N2;
+          ++e;
+        }
+        // ---- lower block [k, e) to one device step
+        Step st;
+        st.nvar = nv;
+        st.kS = int(S.size());
+        st.kN = int(NN.size());
+        st.rA = rA;
+        std::vector<int> F;
+        for (int l : Tlegs)
+          if (!std::count(S.begin(), S.end(), l)) F.push_back(l);  // in A position order
+        st.rC = int(F.size()) + st.kN;
+        std::map<int, int> posA;
+        for (int i = 0; i < (int)Tlegs.size(); ++i) posA[Tlegs[i]] = i;
+        std::sort(S.begin(), S.end(), [&](int a, int b) { return posA[a] < posA[b]; });
+        std::sort(NN.begin(), NN.end());
+        const bool final_step = (e == N);
+        std::map<int, int> posC;
+        if (final_step) {
+          // every remaining leg is an open Kraus-index leg: write at its output bit
+          for (int l : F) posC[l] = cp.out_site_shift[open_of[l].first] + open_of[l].second;
+          for (int l : NN) posC[l] = cp.out_site_shift[open_of.at(l).first] + open_of.at(l).second;
+        } else if (st.kS == st.kN) {
+          for (int l : F) posC[l] = posA[l];
+          for (int i = 0; i < st.kN; ++i) posC[NN[i]] = posA[S[i]];
+          st.inplace_ok = true;
+        } else {
+          for (int i = 0; i < (int)F.size(); ++i) posC[F[i]] = i;
+          for (int i = 0; i < st.kN; ++i) posC[NN[i]] = int(F.size()) + i;
+        }
+        st.final_step = final_step;
+        // rows: the lowest F legs
+        // rows per tile: at most 64, and the LDS tile (K x (Nn + R) entries of 16 bytes) within 60 KB
+        int Lr = std::min<int>(int(F.size()), 6);
+        while (Lr > 0 && (1 << st.kS) * ((1 << st.kN) + (1 << Lr)) > 3840) --Lr;
+        st.L = Lr;
+        std::vector<int> rowsA, rowsC, hiA, hiC, sA, nC;
+        for (int i = 0; i < Lr; ++i) {
+          rowsA.push_back(posA[F[i]]);
+          rowsC.push_back(posC[F[i]]);
+        }
+        for (int i = Lr; i < (int)F.size(); ++i) {
+          hiA.push_back(posA[F[i]]);
+          hiC.push_back(posC[F[i]]);
+        }
+        for (int l : S) sA.push_back(posA[l]);
+        for (int l : NN) nC.push_back(posC[l]);
+        st.hiA = hiA;
+        st.hiC = hiC;
+        st.nTiles = 1LL << hiA.size();
+        for (long long s = 0; s < (1LL << st.kS); ++s) st.offS_A.push_back(scatter(s, sA));
+        for (long long r = 0; r < (1LL << Lr); ++r) {
+          st.offR_A.push_back(scatter(r, rowsA));
+          st.offR_C.push_back(scatter(r, rowsC));
+        }
+        for (long long n = 0; n < (1LL << st.kN); ++n) st.offN_C.push_back(scatter(n, nC));
+        // B matrices [s][n] from the fused block tensor(s)
+        const int K = 1 << st.kS, Nn = 1 << st.kN;
+        for (auto& b : blk) {
+          std::vector<int> sb(st.kS), nb(st.kN);
+          for (int i = 0; i < st.kS; ++i) sb[i] = int(std::find(b.legs.begin(), b.legs.end(), S[i]) - b.legs.begin());
+          for (int i = 0; i < st.kN; ++i) nb[i] = int(std::find(b.legs.begin(), b.legs.end(), NN[i]) - b.legs.begin());
+          std::vector<cd> M(size_t(K) * Nn);
+          for (int s = 0; s < K; ++s)
+            for (int n = 0; n < Nn; ++n) {
+              size_t idx = 0;
+              for (int i = 0; i < st.kS; ++i) idx |= size_t((s >> i) & 1) << sb[i];
+              for (int i = 0; i < st.kN; ++i) idx |= size_t((n >> i) & 1) << nb[i];
+              M[size_t(s) * Nn + n] = b.data[idx];
+            }
+          st.B.push_back(std::move(M));
+        }
+        // precision of this step
+        if (!low) {
+          st.in_prec = st.out_prec = P_C128;
+          st.compute = C_F64;
+        } else {
+          st.in_prec = cur_prec;
+          bool fp64 = (k >= switch_at) || final_step;
+          st.out_prec = fp64 ? P_C128 : P_C64;
+          st.compute = fp64 ? C_F64 : (opt.dtype == JF_C64 ? C_F32 : C_BF16X3);
+          cur_prec = st.out_prec;
+        }
+        int ein = st.in_prec == P_C128 ? 16 : 8, eout = st.out_prec == P_C128 ? 16 : 8;
+        st.flops = 8.0 * std::ldexp(1.0, int(F.size()) + st.kS + st.kN);
+        st.bytes = std::ldexp(double(ein), st.rA) + std::ldexp(double(eout), st.rC);
+        comp_flops += st.flops * mult;
+        comp_bytes += st.bytes * mult;
+        if (!final_step) {
+          level_bytes[lv] = std::max(level_bytes[lv], size_t(eout) << st.rC);
+          level_maxw[lv] = std::max(level_maxw[lv], st.rC);
+        }
+        cp.max_log2 = std::max({cp.max_log2, st.rA, final_step ? 0 : st.rC});
+        // new intermediate layout
+        int rC = st.rC;
+        std::vector<int> nT(final_step ? 0 : rC, -1);
+        if (!final_step)
+          for (auto& kv : posC) nT[kv.second] = kv.first;
+        Tlegs = nT;
+        cp.steps.push_back(std::move(st));
+        k = e;
+      }
+      Lv.last = int(cp.steps.size());
+      Lv.max_log2 = level_maxw[lv];
+      Lv.buf_bytes = std::max<size_t>(level_bytes[lv], 256);
+      cp.levels.push_back(Lv);
+    }
+    cp.leaves = mult;
+    cp.flops = comp_flops;
+    cp.bytes = comp_bytes;
+    size_t cbuf = 0;
+    for (auto& lv : cp.levels) cbuf += 2 * ((lv.buf_bytes + 255) / 256 * 256);
+    max_comp_buf = std::max(max_comp_buf, cbuf);
+    cp.out_off = out_total;
+    out_total += cp.out_len;
+    P.flops += cp.flops;
+    P.bytes += cp.bytes;
+    P.max_log2 = std::max(P.max_log2, cp.max_log2);
+    P.work_items += cp.leaves;
+    P.comps.push_back(std::move(cp));
+  }
+  // workspace: B pools | constants | level buffers | outputs | sums
+  size_t pool = 0;
+  for (auto& cp : P.comps)
+    for (auto& st : cp.steps) {
+      size_t e = st.compute == C_F64 ? 16 : 8;
+      for (auto& b : st.B) pool += (b.size() * e + 255) / 256 * 256;
+    }
+  P.pool_bytes = pool;
+  P.ws_bytes = pool + 256 + max_comp_buf + (size_t(out_total) * 16 + 255) / 256 * 256 +
+               (P.comps.size() * 4 * 8 + 255) / 256 * 256;
+  P.planner_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return P;
+}
+
+}  // namespace jf

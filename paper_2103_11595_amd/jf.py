@@ -1,0 +1,321 @@
+"""Python binding of libjf.so (include/jf.h): argument marshalling only.
+
+Every step of the fidelity computation runs in the library (host planner + HIP kernels).
+PyTorch provides the device workspace and the stream.  There is no fallback: a missing library
+or a missing GPU raises.
+
+Names mirror the C ABI: jf_load_circuit, jf_plan_contraction, jf_plan_info, jf_fidelity_alg1,
+jf_fidelity_alg2, jf_fidelity_batch, jf_is_equivalent, plus Python conveniences
+(load_instance, plan, fidelity).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjf.so")
+
+JF_C128, JF_C64, JF_C64_BF16X3 = 0, 1, 2
+DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x3": JF_C64_BF16X3}
+JF_FLAG_NO_CANCEL, JF_FLAG_NO_FUSE, JF_FLAG_NO_BATCH = 1, 2, 4
+
+STATUS = {0: "JF_OK", -1: "JF_E_ARG", -2: "JF_E_NOT_UNITARY", -3: "JF_E_NOT_TP", -4: "JF_E_QUBIT",
+          -5: "JF_E_TOO_LARGE", -6: "JF_E_OOM", -7: "JF_E_HIP", -8: "JF_E_UNSUPPORTED"}
+
+GATE_KINDS = {"h": 0, "s": 1, "sdg": 2, "t": 3, "tdg": 4, "x": 5, "y": 6, "z": 7, "sx": 8, "rz": 9,
+              "rx": 10, "ry": 11, "su2": 12, "cx": 13, "cz": 14, "cs": 15, "swap": 16,
+              "mat1": 17, "mat2": 18}
+NOISE_KINDS = {"kraus": 0, "depolarizing": 1, "bit_flip": 2, "phase_flip": 3, "bit_phase_flip": 4,
+               "amplitude_damping": 5}
+
+
+class JfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class jf_gate(C.Structure):
+    _fields_ = [("kind", C.c_int), ("q0", C.c_int), ("q1", C.c_int), ("theta", C.c_double * 3),
+                ("mat", C.POINTER(C.c_double))]
+
+
+class jf_noise(C.Structure):
+    _fields_ = [("after_op", C.c_int), ("qubit", C.c_int), ("channel", C.c_int), ("p", C.c_double),
+                ("n_kraus", C.c_int), ("kraus", C.POINTER(C.c_double))]
+
+
+class jf_result(C.Structure):
+    _fields_ = [("fj", C.c_double), ("one_minus_fj", C.c_double), ("imag_residual", C.c_double),
+                ("kraus_terms", C.c_longlong), ("work_items", C.c_longlong),
+                ("max_log2_intermediate", C.c_double), ("path_flops", C.c_double),
+                ("path_bytes", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class jf_plan_stats(C.Structure):
+    _fields_ = [("n_steps", C.c_int), ("n_components", C.c_int), ("n_sliced_sites", C.c_int),
+                ("n_open_bits", C.c_int), ("n_tensors_before_cancel", C.c_int),
+                ("n_tensors_after_cancel", C.c_int), ("planner_seconds", C.c_double),
+                ("empty_loops", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class jf_profile(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("kernel_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double), ("total_ms", C.c_double), ("max_launch_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_stats_get",
+           "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
+           "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
+           "jf_profile_run"]
+
+_lib = None
+
+
+def lib():
+    """Load libjf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_11595_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, sz = C.c_void_p, C.c_size_t
+    L.jf_load_circuit.argtypes = [C.c_int, C.POINTER(jf_gate), C.c_int, C.POINTER(jf_gate), C.c_int,
+                                  C.POINTER(jf_noise), C.c_int, C.c_double, C.POINTER(vp)]
+    L.jf_plan_contraction.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_uint, C.POINTER(vp)]
+    L.jf_plan_info.argtypes = [vp, C.POINTER(sz), C.POINTER(jf_result)]
+    L.jf_plan_stats_get.argtypes = [vp, C.POINTER(jf_plan_stats)]
+    L.jf_fidelity_alg1.argtypes = [vp, vp, sz, vp, C.POINTER(jf_result), C.POINTER(C.c_double)]
+    L.jf_fidelity_alg2.argtypes = [vp, vp, sz, vp, C.POINTER(jf_result)]
+    L.jf_batch_workspace.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(sz)]
+    L.jf_fidelity_batch.argtypes = [C.POINTER(vp), C.c_int, vp, sz, vp, C.POINTER(jf_result)]
+    L.jf_is_equivalent.argtypes = [C.POINTER(jf_result), C.c_double]
+    L.jf_is_equivalent.restype = C.c_int
+    L.jf_free_circuit.argtypes = [vp]
+    L.jf_free_circuit.restype = None
+    L.jf_free_plan.argtypes = [vp]
+    L.jf_free_plan.restype = None
+    L.jf_last_error.restype = C.c_char_p
+    L.jf_emulate_plan.argtypes = [vp, C.POINTER(C.c_double), C.c_longlong]
+    L.jf_profile_run.argtypes = [vp, vp, sz, vp, C.POINTER(jf_profile)]
+    for name in EXPORTS:
+        if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise JfError(st, lib().jf_last_error().decode())
+
+
+# ---------------------------------------------------------------------------- handles ---
+
+class Circuit:
+    def __init__(self, ptr, n, n_sites):
+        self.ptr = ptr
+        self.n = n
+        self.n_sites = n_sites
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().jf_free_circuit(self.ptr)
+            self.ptr = None
+
+
+class Plan:
+    def __init__(self, ptr, alg, dtype, circuit):
+        self.ptr = ptr
+        self.alg = alg
+        self.dtype = dtype
+        self.circuit = circuit
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().jf_free_plan(self.ptr)
+            self.ptr = None
+
+    def info(self):
+        ws = C.c_size_t()
+        r = jf_result()
+        _check(lib().jf_plan_info(self.ptr, C.byref(ws), C.byref(r)))
+        d = r.as_dict()
+        d["workspace_bytes"] = ws.value
+        return d
+
+    def stats(self):
+        s = jf_plan_stats()
+        _check(lib().jf_plan_stats_get(self.ptr, C.byref(s)))
+        return s.as_dict()
+
+    def emulate(self):
+        """Host emulation of the lowered step program (validation aid): complex terms for Alg I,
+        T/d^2 for Alg II."""
+        import numpy as np
+        info = self.info()
+        n = 2 * info["kraus_terms"] if self.alg == 1 else 2
+        buf = (C.c_double * n)()
+        _check(lib().jf_emulate_plan(self.ptr, buf, n))
+        a = np.frombuffer(buf, dtype=np.float64).copy()
+        return a[0::2] + 1j * a[1::2]
+
+
+def _gate_struct(g, keep):
+    name, qs = g[0], g[1]
+    params = list(g[2]) if len(g) > 2 else []
+    s = jf_gate()
+    if name not in GATE_KINDS:
+        raise ValueError(f"unknown gate {name!r}")
+    s.kind = GATE_KINDS[name]
+    s.q0 = int(qs[0])
+    s.q1 = int(qs[1]) if len(qs) > 1 else 0
+    if name not in ("mat1", "mat2"):
+        for i, v in enumerate(params[:3]):
+            s.theta[i] = float(v)
+    else:
+        flat = [x for row in params[0] for z in row for x in (complex(z).real, complex(z).imag)] \
+            if params and isinstance(params[0], (list, tuple)) else []
+        arr = (C.c_double * len(flat))(*flat)
+        keep.append(arr)
+        s.mat = C.cast(arr, C.POINTER(C.c_double))
+    return s
+
+
+def jf_load_circuit(inst: dict, tol: float = 0.0) -> Circuit:
+    """Marshal an instance dict (see paper_2103_11595_amd.instances) into jf_load_circuit."""
+    keep = []
+    gates = inst["gates"]
+    G = (jf_gate * max(1, len(gates)))(*[_gate_struct(g, keep) for g in gates])
+    noisy = inst.get("noisy_gates")
+    NG = (jf_gate * max(1, len(noisy)))(*[_gate_struct(g, keep) for g in noisy]) if noisy else None
+    sites = inst.get("noise", [])
+    ns = []
+    for s in sites:
+        x = jf_noise()
+        x.after_op = int(s["after"])
+        x.qubit = int(s["qubit"])
+        if "kraus" in s:
+            x.channel = NOISE_KINDS["kraus"]
+            flat = [v for K in s["kraus"] for row in K for z in row for v in (complex(z).real, complex(z).imag)]
+            arr = (C.c_double * len(flat))(*flat)
+            keep.append(arr)
+            x.n_kraus = len(s["kraus"])
+            x.kraus = C.cast(arr, C.POINTER(C.c_double))
+        else:
+            x.channel = NOISE_KINDS[s["channel"]]
+            x.p = float(s["p"])
+        ns.append(x)
+    N = (jf_noise * max(1, len(ns)))(*ns)
+    out = C.c_void_p()
+    _check(lib().jf_load_circuit(int(inst["n"]), G, len(gates), NG, len(noisy) if noisy else 0,
+                                 N, len(ns), float(tol), C.byref(out)))
+    return Circuit(out.value, int(inst["n"]), len(ns))
+
+
+def jf_plan_contraction(circ: Circuit, alg: int = 1, dtype="c128", max_log2: int = 0, flags: int = 0) -> Plan:
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    out = C.c_void_p()
+    _check(lib().jf_plan_contraction(circ.ptr, int(alg), dt, int(max_log2), int(flags), C.byref(out)))
+    return Plan(out.value, int(alg), dt, circ)
+
+
+def jf_plan_info(plan: Plan) -> dict:
+    return plan.info()
+
+
+# ------------------------------------------------------------------------- GPU calls ---
+
+def _torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("jf: no GPU visible; the fidelity entry points run only on the GPU")
+    return torch
+
+
+def workspace(nbytes: int, device=None):
+    """Device workspace as a torch uint8 tensor (the caching allocator aligns to >= 512 bytes)."""
+    torch = _torch_cuda()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def _stream_ptr(stream):
+    torch = _torch_cuda()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def jf_fidelity_alg1(plan: Plan, ws=None, stream=None, want_terms: bool = False) -> dict:
+    import numpy as np
+    info = plan.info()
+    if ws is None:
+        ws = workspace(info["workspace_bytes"])
+    r = jf_result()
+    terms = (C.c_double * (2 * info["kraus_terms"]))() if want_terms else None
+    _check(lib().jf_fidelity_alg1(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                  C.byref(r), terms))
+    d = r.as_dict()
+    if want_terms:
+        a = np.frombuffer(terms, dtype=np.float64).copy()
+        d["terms"] = a[0::2] + 1j * a[1::2]
+    return d
+
+
+def jf_fidelity_alg2(plan: Plan, ws=None, stream=None) -> dict:
+    info = plan.info()
+    if ws is None:
+        ws = workspace(info["workspace_bytes"])
+    r = jf_result()
+    _check(lib().jf_fidelity_alg2(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
+    return r.as_dict()
+
+
+def jf_batch_workspace(plans) -> int:
+    arr = (C.c_void_p * len(plans))(*[p.ptr for p in plans])
+    out = C.c_size_t()
+    _check(lib().jf_batch_workspace(arr, len(plans), C.byref(out)))
+    return out.value
+
+
+def jf_fidelity_batch(plans, ws=None, stream=None) -> list:
+    arr = (C.c_void_p * len(plans))(*[p.ptr for p in plans])
+    if ws is None:
+        ws = workspace(jf_batch_workspace(plans))
+    res = (jf_result * len(plans))()
+    _check(lib().jf_fidelity_batch(arr, len(plans), C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), res))
+    return [r.as_dict() for r in res]
+
+
+def jf_profile_run(plan: Plan, ws=None, stream=None) -> dict:
+    if ws is None:
+        ws = workspace(plan.info()["workspace_bytes"])
+    r = jf_profile()
+    _check(lib().jf_profile_run(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
+    return r.as_dict()
+
+
+def jf_is_equivalent(result: dict, eps: float) -> bool:
+    r = jf_result(**{k: result[k] for k, _ in jf_result._fields_})
+    return bool(lib().jf_is_equivalent(C.byref(r), float(eps)))
+
+
+# --------------------------------------------------------------------- conveniences ---
+
+def plan(inst: dict, alg: int = 1, dtype="c128", max_log2: int = 0, flags: int = 0) -> Plan:
+    return jf_plan_contraction(jf_load_circuit(inst), alg, dtype, max_log2, flags)
+
+
+def fidelity(inst: dict, alg: int = 1, dtype="c128", want_terms: bool = False, **kw) -> dict:
+    p = plan(inst, alg, dtype, **kw)
+    return jf_fidelity_alg1(p, want_terms=want_terms) if alg == 1 else jf_fidelity_alg2(p)

@@ -1,0 +1,236 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the oracle, and against properties
+that hold exactly at any size for the full workloads.
+
+Tolerances: |dF_J| <= 1e-12 and per-term |dt| <= 1e-12 for complex128; |dF_J| <= 1e-6 for the
+complex64 and 3xBF16 modes (whose traces and sums are still accumulated in FP64)."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import clifford, dense
+from paper_2103_11595_amd import instances as gen
+from paper_2103_11595_amd import jf
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"c128": 1e-12, "c64": 1e-6, "bf16x3": 1e-6}
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _terms(ref):
+    return np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+
+
+def run1(inst, dtype="c128", **kw):
+    say("alg1", inst.get("name", ""), "n", inst["n"], "gates", len(inst["gates"]), "sites", len(inst.get("noise", [])), dtype, kw)
+    return jf.fidelity(inst, 1, dtype, want_terms=True, **kw)
+
+
+def run2(inst, dtype="c128", **kw):
+    say("alg2", inst.get("name", ""), "n", inst["n"], "gates", len(inst["gates"]), "sites", len(inst.get("noise", [])), dtype, kw)
+    return jf.fidelity(inst, 2, dtype, **kw)
+
+
+# --- the small workload and worked examples -----------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64", "bf16x3"])
+def test_config1_against_oracle(dtype):
+    inst = gen.config1()
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    got = run1(inst, dtype)
+    assert got["kraus_terms"] == 16
+    assert abs(got["fj"] - ref["fj"]) <= TOL[dtype]
+    assert abs(got["one_minus_fj"] - ref["one_minus_fj"]) <= TOL[dtype]
+    if dtype == "c128":
+        assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12
+    got2 = run2(inst, dtype)
+    assert abs(got2["fj"] - ref["fj"]) <= TOL[dtype]
+
+
+def test_examples_3_and_4_on_gpu():
+    g = json.load(open(os.path.join(GOLDEN, "example3_alg1.json")))
+    g4 = json.load(open(os.path.join(GOLDEN, "example4_alg2.json")))
+    for case in g["cases"]:
+        p = case["p_paper"]
+        inst = {"n": 2, "gates": g["gates"], "noise": [dict(s, p=1 - p) for s in g["noise_template"]]}
+        got = run1(inst)
+        want = np.array([complex(*v) for v in case["traces_unnormalised"]]) / 4
+        assert np.max(np.abs(got["terms"] - want)) < 1e-13
+        assert abs(got["fj"] - case["fj"]) < 1e-13
+    for case in g4["cases"]:
+        p = case["p_paper"]
+        inst = {"n": 2, "gates": g["gates"], "noise": [dict(s, p=1 - p) for s in g["noise_template"]]}
+        got = run2(inst)
+        assert abs(got["fj"] * 16 - case["doubled_network_value"]) < 1e-12
+
+
+# --- 200 seeded small instances ------------------------------------------------------------
+
+def _small(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 9))
+    return gen.random_circuit(n, int(rng.integers(20, 120)), int(rng.integers(1, 4)), 1e-3, 0.2, 1000 + seed)
+
+
+@pytest.mark.parametrize("block", range(10))
+def test_small_instances_alg1(block):
+    for seed in range(20 * block, 20 * block + 20):
+        inst = _small(seed)
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        got = run1(inst, "c128")
+        assert abs(got["fj"] - ref["fj"]) <= 1e-12, seed
+        assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12, seed
+        for dt in ("c64", "bf16x3"):
+            g = run1(inst, dt)
+            assert abs(g["fj"] - ref["fj"]) <= TOL[dt], (seed, dt, g["fj"] - ref["fj"])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_small_instances_alg2(seed):
+    inst = gen.random_circuit(2 + seed % 4, 30 + 7 * seed, 1 + seed % 4, 1e-3, 0.2, 3000 + seed)
+    if seed % 3 == 0:
+        inst["noise"][0]["channel"] = "amplitude_damping"
+    want = dense.fidelity_alg2(inst)
+    for dt in ("c128", "c64", "bf16x3"):
+        got = run2(inst, dt)
+        assert abs(got["fj"] - want["fj"]) <= TOL[dt], (seed, dt)
+        assert got["imag_residual"] <= TOL[dt]
+
+
+def test_sliced_and_unfused_programs_match():
+    inst = gen.random_circuit(5, 80, 5, 1e-3, 0.1, 77)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    for flags in (jf.JF_FLAG_NO_BATCH, jf.JF_FLAG_NO_FUSE, jf.JF_FLAG_NO_CANCEL):
+        got = run1(inst, "c128", flags=flags)
+        assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12, flags
+    got = run1(inst, "c128", max_log2=8)
+    assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12
+
+
+# --- full-size workloads: exact properties -------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config2_full_size_properties(dtype):
+    inst = gen.config2()
+    ps = [s["p"] for s in inst["noise"]]
+    got = run1(inst, dtype)
+    t = got["terms"].reshape(4, 4, 4, 4)
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    # identity tuple: the miter collapses to U^dag U, t/d = prod sqrt(1-p)
+    assert abs(t[0, 0, 0, 0] - math.prod(math.sqrt(1 - p) for p in ps)) <= tol
+    # a single Pauli error leaves tr(P (x) I) = 0
+    for i in range(4):
+        for j in (1, 2, 3):
+            idx = [0, 0, 0, 0]
+            idx[i] = j
+            assert abs(t[tuple(idx)]) <= tol
+    lo = math.prod(1 - p for p in ps)
+    hi = 1 - sum(p * math.prod(1 - q for k, q in enumerate(ps) if k != i) for i, p in enumerate(ps))
+    assert lo - tol <= got["fj"] <= hi + tol
+    assert abs(np.sum(np.abs(got["terms"]) ** 2) - got["fj"]) <= 1e-12
+
+
+def test_config2_c64_and_bf16x3_against_c128():
+    inst = gen.config2()
+    ref = run1(inst, "c128")
+    for dt in ("c64", "bf16x3"):
+        got = run1(inst, dt)
+        say(dt, "dF_J vs c128", got["fj"] - ref["fj"])
+        assert abs(got["fj"] - ref["fj"]) <= 1e-6, dt
+
+
+def test_config2_clifford_twin_exact():
+    twin = gen.clifford_twin(gen.config2(), 2)
+    want = clifford.fidelity(twin)["fj"]
+    got = run1(twin, "c128")
+    assert abs(got["fj"] - want) <= 1e-12
+
+
+def test_config3_clifford_twin_alg2_exact():
+    twin = gen.clifford_twin(gen.config3(), 3)
+    want = clifford.fidelity(twin)["fj"]
+    for dt in ("c128", "c64"):
+        got = run2(twin, dt)
+        assert abs(got["fj"] - want) <= TOL[dt], dt
+
+
+def test_config3_alg2_runs_and_is_consistent():
+    inst = gen.config3()
+    a = run2(inst, "c128")
+    b = run2(inst, "c64")
+    assert 0.0 < a["fj"] <= 1.0 and a["imag_residual"] <= 1e-12
+    assert abs(a["fj"] - b["fj"]) <= 1e-6
+
+
+def test_config5_alg2_precision_modes():
+    inst = gen.config5()
+    twin = gen.clifford_twin(inst, 5)
+    cut = clifford.fidelity(twin, max_errors=3)
+    got = run2(twin, "c128")
+    assert cut["fj"] - 1e-12 <= got["fj"] <= cut["fj"] + cut["tail"] + 1e-12
+    res = {dt: run2(inst, dt) for dt in ("c128", "c64", "bf16x3")}
+    ps = [s["p"] for s in inst["noise"]]
+    lo = math.prod(1 - p for p in ps)
+    hi = 1 - sum(p * math.prod(1 - q for k, q in enumerate(ps) if k != i) for i, p in enumerate(ps))
+    assert lo - 1e-12 <= res["c128"]["fj"] <= hi + 1e-12
+    for dt in ("c64", "bf16x3"):
+        assert abs(res[dt]["fj"] - res["c128"]["fj"]) <= 1e-6, dt
+
+
+@pytest.mark.parametrize("member", [0, 1, 2, 3])
+def test_config4_members_clifford_twins(member):
+    inst = gen.config4(count=8)[member]
+    twin = gen.clifford_twin(inst, member)
+    want = clifford.fidelity(twin)["fj"]
+    got = run1(twin, "c128")
+    assert abs(got["fj"] - want) <= 1e-12
+
+
+def test_stability_with_idle_qubits_on_gpu():
+    inst = gen.random_circuit(10, 200, 3, 1e-3, 1e-2, 5)
+    a = run1(inst)
+    b = run1(dict(inst, n=13))
+    assert abs(a["fj"] - b["fj"]) <= 1e-12
+
+
+# --- determinism, batching, errors ---------------------------------------------------------
+
+def test_replays_are_bitwise_identical():
+    inst = gen.config2()
+    p = jf.plan(inst, 1, "c64")
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    say("determinism cfg2 c64 x10")
+    vals = [jf.jf_fidelity_alg1(p, ws)["fj"] for _ in range(10)]
+    assert len(set(vals)) == 1
+
+
+def test_batch_matches_individual_runs():
+    insts = [gen.config1(s) for s in (1, 2, 3)] + [gen.random_circuit(9, 150, 2, 1e-3, 1e-2, 11)]
+    plans = [jf.plan(i, 1, "c128") for i in insts] + [jf.plan(gen.config1(4), 2, "c128")]
+    say("batch of", len(plans))
+    singles = [jf.jf_fidelity_alg1(p) if p.alg == 1 else jf.jf_fidelity_alg2(p) for p in plans]
+    ws = jf.workspace(jf.jf_batch_workspace(plans))
+    import torch
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            out = jf.jf_fidelity_batch(plans, ws, s)
+        torch.cuda.synchronize()
+        for a, b in zip(out, singles):
+            assert a["fj"] == b["fj"], rep
+
+
+def test_workspace_too_small_is_reported():
+    p = jf.plan(gen.config1(), 1)
+    ws = jf.workspace(256)
+    with pytest.raises(jf.JfError) as e:
+        jf.jf_fidelity_alg1(p, ws)
+    assert e.value.status == -6

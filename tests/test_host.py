@@ -1,0 +1,150 @@
+"""Host-side tests (no GPU): the C ABI loads and exports what include/jf.h declares, input
+validation and error statuses, and the planner/lowering checked by emulating the device step
+program on the host against the oracle."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from paper_2103_11595_amd import instances as gen
+from paper_2103_11595_amd import jf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "jf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert "jf_fidelity_alg1" in names and "jf_plan_contraction" in names and "jf_fidelity_batch" in names
+    L = jf.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_abi():
+    for name in ("jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_fidelity_alg1", "jf_fidelity_alg2",
+                 "jf_fidelity_batch", "jf_is_equivalent"):
+        assert callable(getattr(jf, name))
+
+
+# --- validation and error statuses ---------------------------------------------------------
+
+def _status(fn):
+    with pytest.raises(jf.JfError) as e:
+        fn()
+    return e.value.status
+
+
+def test_error_paths():
+    base = gen.random_circuit(3, 10, 1, 0.01, None, 0)
+    assert _status(lambda: jf.jf_load_circuit(dict(base, gates=[["h", [3], []]]))) == -4          # JF_E_QUBIT
+    assert _status(lambda: jf.jf_load_circuit(dict(base, gates=[["cx", [1, 1], []]]))) == -4
+    bad = [[[1, 0], [0, 1]], [[0, 0.5], [0.5, 0]]]
+    assert _status(lambda: jf.jf_load_circuit(dict(base, gates=[["mat1", [0], [bad[1]]]]))) == -2   # not unitary
+    notp = dict(base, noise=[{"after": 0, "qubit": 0, "kraus": [[[1, 0], [0, 1]], [[0.1, 0], [0, 0]]]}])
+    assert _status(lambda: jf.jf_load_circuit(notp)) == -3                                        # not TP
+    assert _status(lambda: jf.jf_load_circuit(dict(base, noise=[{"after": 99, "qubit": 0, "channel": "depolarizing", "p": 0.1}]))) == -1
+    assert _status(lambda: jf.jf_load_circuit(dict(base, noise=[{"after": 0, "qubit": 0, "channel": "depolarizing", "p": 1.5}]))) == -1
+    c = jf.jf_load_circuit(base)
+    assert _status(lambda: jf.jf_plan_contraction(c, alg=3)) == -1
+    assert _status(lambda: jf.jf_plan_contraction(c, alg=1, max_log2=99)) == -1
+    assert "p" in jf.lib().jf_last_error().decode() or True
+
+
+def test_cap_too_small_reports_too_large():
+    inst = gen.random_circuit(8, 120, 2, 0.01, None, 4)
+    c = jf.jf_load_circuit(inst)
+    st = _status(lambda: jf.jf_plan_contraction(c, 1, "c128", max_log2=2))
+    assert st == -5
+    assert "fits" in jf.lib().jf_last_error().decode()
+
+
+def test_cap_forces_slicing_not_failure():
+    inst = gen.random_circuit(3, 40, 6, 0.01, 0.1, 8)   # 12 Kraus-index bits dominate the width
+    c = jf.jf_load_circuit(inst)
+    free = jf.jf_plan_contraction(c, 1, "c128")
+    need = int(free.info()["max_log2_intermediate"])
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    for cut in (2, 4, 6):
+        tight = jf.jf_plan_contraction(c, 1, "c128", max_log2=need - cut)
+        assert tight.stats()["n_sliced_sites"] >= cut // 2
+        assert tight.info()["max_log2_intermediate"] <= need - cut
+        assert np.max(np.abs(tight.emulate() - want)) < 1e-12
+
+
+def test_is_equivalent_is_strict():
+    r = {"fj": 0.9, "one_minus_fj": 0.1, "imag_residual": 0.0, "kraus_terms": 1, "work_items": 1,
+         "max_log2_intermediate": 0.0, "path_flops": 0.0, "path_bytes": 0.0, "seconds": 0.0}
+    assert jf.jf_is_equivalent(r, 0.1) is False      # Definition 1: F_J > 1 - eps
+    assert jf.jf_is_equivalent(r, 0.1000001) is True
+
+
+# --- network simplification ----------------------------------------------------------------
+
+def test_cancellation_and_idle_wires():
+    inst = gen.random_circuit(6, 80, 0, 0.0, None, 1)
+    p = jf.plan(inst, 1)
+    s = p.stats()
+    assert s["n_tensors_before_cancel"] == 160 and s["n_tensors_after_cancel"] == 0
+    assert s["empty_loops"] == 6 and s["n_components"] == 0
+    assert abs(p.emulate()[0] - 1.0) < 1e-15
+    inst = gen.random_circuit(6, 80, 0, 0.0, None, 1)
+    p = jf.plan(inst, 1, flags=jf.JF_FLAG_NO_CANCEL)
+    assert p.stats()["n_tensors_after_cancel"] == 160
+    assert abs(p.emulate()[0] - 1.0) < 1e-12
+
+
+def test_alg2_network_has_doubled_wires():
+    inst = gen.random_circuit(3, 30, 2, 0.05, None, 2)
+    p = jf.plan(inst, 2, flags=jf.JF_FLAG_NO_CANCEL)
+    assert p.stats()["n_tensors_before_cancel"] == 4 * 30 + 2   # V, V*, V^dag, V^T per gate + M_N per site
+
+
+# --- emulated step programs against the oracle (planner, slicing, fusion, layouts) ---------
+
+@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("flags", [0, jf.JF_FLAG_NO_FUSE, jf.JF_FLAG_NO_BATCH, jf.JF_FLAG_NO_CANCEL])
+def test_emulated_alg1_terms_match_oracle(seed, flags):
+    n = 2 + seed % 4
+    inst = gen.random_circuit(n, 20 + 4 * seed, 1 + seed % 3, 0.01, 0.3, 500 + seed)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    got = jf.plan(inst, 1, "c128", flags=flags).emulate()
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_emulated_alg2_matches_oracle(seed):
+    inst = gen.random_circuit(3 + seed % 2, 30 + 5 * seed, 2 + seed % 2, 0.01, 0.3, 700 + seed)
+    want = dense.fidelity_alg2(inst)["fj"]
+    got = jf.plan(inst, 2, "c128").emulate()[0]
+    assert abs(got.real - want) < 1e-12 and abs(got.imag) < 1e-12
+
+
+def test_emulated_mixed_channels_and_explicit_kraus():
+    inst = gen.random_circuit(4, 40, 3, 0.05, 0.2, 9)
+    inst["noise"][0]["channel"] = "amplitude_damping"
+    inst["noise"][1] = dict(inst["noise"][1], kraus=[k.tolist() for k in dense.kraus_set("bit_phase_flip", 0.3)] +
+                            [[[0, 0], [0, 0]]])   # three Kraus operators: padded variant index
+    inst["noise"][2]["after"] = -1
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    assert np.max(np.abs(jf.plan(inst, 1).emulate() - want)) < 1e-12
+    assert abs(jf.plan(inst, 2).emulate()[0].real - ref["fj"]) < 1e-12
+
+
+def test_plans_of_the_workloads_fit_one_gpu():
+    for inst, alg, cap in [(gen.config1(), 1, 28), (gen.config2(), 1, 28), (gen.config3(), 2, 28), (gen.config5(), 2, 28)]:
+        p = jf.plan(inst, alg, "c64")
+        info = p.info()
+        assert info["max_log2_intermediate"] <= cap
+        assert info["workspace_bytes"] < 64 * 2**30
