@@ -14,7 +14,15 @@ d times a phase when the product is proportional to the identity and 0 otherwise
     F_J = sum over tuples of prod_i w_{i j_i} * [P'_{1 j_1} ... P'_{m j_m} proportional to I].
 
 Paulis are symplectic bit vectors (x | z << n); a product is proportional to I exactly when the
-XOR of the vectors is zero.  Conjugation rules: H swaps x and z; S and SDG map z ^= x; Paulis only
+XOR of the vectors is zero.  Writing the Kraus choice at site i as two bits (a_i, b_i) (X^a Z^b
+up to phase), the condition is M c = 0 for the 2n x 2m GF(2) matrix M whose columns are the
+propagated X_i and Z_i, so
+
+    F_J = sum over c in ker(M) of prod_i w_i(a_i, b_i),
+
+an exact sum over the 2^(2m - rank M) kernel vectors (``fidelity``).  ``fidelity_dp`` sums the
+same quantity by dynamic programming over the sites (exponential in m; small cases only, used to
+cross-check the kernel enumeration).  Conjugation rules: H swaps x and z; S and SDG map z ^= x; Paulis only
 change signs; CX(c, t): x_t ^= x_c, z_c ^= z_t; CZ(a, b): z_a ^= x_b, z_b ^= x_a; SWAP swaps.
 """
 from __future__ import annotations
@@ -81,56 +89,112 @@ def _channel_paulis(channel: str, p: float, q: int, n: int):
     raise ValueError(f"not a Pauli channel: {channel}")
 
 
-def fidelity(inst: dict, max_errors: int | None = None) -> dict:
-    """Exact F_J of a Clifford circuit with Pauli-channel noise.
-
-    With ``max_errors`` set, tuples with more than that many non-identity Kraus operators are
-    dropped; every dropped tuple contributes between 0 and its weight, so the true value lies in
-    [fj, fj + tail] with ``tail`` the probability of more than ``max_errors`` errors."""
+def _propagated(inst):
+    """(per-site weight table over (a, b) -> w, propagated X and Z vectors) for every site."""
     n = inst["n"]
     gates = inst["gates"]
     for g in gates:
         if g[0] not in CLIFFORD_GATES:
             raise ValueError(f"gate {g[0]} is not Clifford")
-    sites = inst.get("noise", [])
-    # propagate each site's Paulis through every gate after it
-    order = sorted(range(len(sites)), key=lambda i: (sites[i]["after"], i))
-    site_terms = []
-    for si in order:
-        s = sites[si]
+    out = []
+    for s in inst.get("noise", []):
         if s["channel"] not in PAULI_CHANNELS:
             raise ValueError(f"channel {s['channel']} is not a Pauli channel")
-        terms = []
-        for w, v in _channel_paulis(s["channel"], s["p"], s["qubit"], n):
-            for g in gates[s["after"] + 1:]:
-                v = _conjugate(v, g[0], g[1], n)
-            terms.append((w, v))
-        site_terms.append(terms)
+        q = s["qubit"]
+        vx, vz = 1 << q, 1 << (q + n)
+        for g in gates[s["after"] + 1:]:
+            vx = _conjugate(vx, g[0], g[1], n)
+            vz = _conjugate(vz, g[0], g[1], n)
+        w = [0.0] * 4                       # index a + 2b: I, X, Z, Y
+        X, Z = 1 << q, 1 << (q + n)
+        for wt, v in _channel_paulis(s["channel"], s["p"], q, n):
+            a, b = int(bool(v & X)), int(bool(v & Z))
+            w[a + 2 * b] += wt
+        out.append((w, vx, vz))
+    return out
 
-    # distribution over (xor vector, error count); identity Kraus operators are listed first
-    state = {(0, 0): 1.0}
-    for terms in site_terms:
+
+def _kernel_basis(cols):
+    """Basis (as bitmasks over the column indices) of {c : XOR of cols[j] over set bits j = 0}."""
+    pivots = {}          # pivot bit -> (reduced vector, combination mask)
+    basis = []
+    for j, v in enumerate(cols):
+        comb = 1 << j
+        while v:
+            top = v.bit_length() - 1
+            if top not in pivots:
+                pivots[top] = (v, comb)
+                break
+            pv, pc = pivots[top]
+            v ^= pv
+            comb ^= pc
+        if v == 0:
+            basis.append(comb)
+    return basis
+
+
+def _enumerate_kernel(basis, sites, chunk_bits=20):
+    """sum over the span of ``basis`` of prod_i w_i(c_i), exact, in numpy chunks of 2^20 codewords."""
+    import numpy as np
+    k = len(basis)
+    m = len(sites)
+    low = min(k, chunk_bits)
+    mask64 = (1 << 64) - 1
+    # codewords of the low basis vectors: every subset, as two 64-bit words
+    lo = np.zeros(1 << low, dtype=np.uint64)
+    hi = np.zeros(1 << low, dtype=np.uint64)
+    for b in range(low):
+        half = 1 << b
+        lo[half:2 * half] = lo[:half] ^ np.uint64(basis[b] & mask64)
+        hi[half:2 * half] = hi[:half] ^ np.uint64(basis[b] >> 64)
+    # product tables over groups of 8 sites (16 codeword bits): T_g[x] = prod_i w_i(bits of x)
+    tables = []
+    for g0 in range(0, m, 8):
+        T = np.ones(1, dtype=np.float64)
+        for i in range(g0, min(m, g0 + 8)):
+            T = np.multiply.outer(np.array(sites[i][0], dtype=np.float64), T).reshape(-1)
+        # T is indexed with site g0 in the lowest two bits
+        tables.append((2 * g0, T))
+    parts = []
+    for h in range(1 << (k - low)):
+        c = 0
+        for b in range(k - low):
+            if (h >> b) & 1:
+                c ^= basis[low + b]
+        clo = lo ^ np.uint64(c & mask64)
+        chi = hi ^ np.uint64(c >> 64)
+        prod = np.ones(1 << low, dtype=np.float64)
+        for pos, T in tables:
+            word, sh = (clo, pos) if pos < 64 else (chi, pos - 64)
+            idx = ((word >> np.uint64(sh)) & np.uint64(len(T) - 1)).astype(np.int64)
+            prod *= T[idx]
+        parts.append(math.fsum(prod.tolist()) if len(prod) <= 4096 else float(np.sum(np.sort(prod))))
+    return math.fsum(parts)
+
+
+def fidelity(inst: dict, max_kernel_dim: int = 30, chunk_bits: int = 20) -> dict:
+    """Exact F_J of a Clifford circuit with Pauli-channel noise (kernel enumeration)."""
+    sites = _propagated(inst)
+    cols = []
+    for w, vx, vz in sites:
+        cols.extend([vx, vz])
+    basis = _kernel_basis(cols)
+    k = len(basis)
+    if k > max_kernel_dim:
+        raise ValueError(f"kernel dimension {k} too large to enumerate")
+    return {"fj": _enumerate_kernel(basis, sites, chunk_bits), "kernel_dim": k}
+
+
+def fidelity_dp(inst: dict) -> dict:
+    """The same sum by dynamic programming over the sites (XOR vector -> weight)."""
+    state = {0: 1.0}
+    for w, vx, vz in _propagated(inst):
         new = {}
-        for (v, e), w0 in state.items():
-            for j, (w, u) in enumerate(terms):
-                ne = e + (1 if j > 0 else 0)
-                if max_errors is not None and ne > max_errors:
+        for v, w0 in state.items():
+            for idx, (dx, dz) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+                if w[idx] == 0.0:
                     continue
-                key = (v ^ u, ne)
-                new[key] = new.get(key, 0.0) + w0 * w
+                key = v ^ (vx if dx else 0) ^ (vz if dz else 0)
+                new[key] = new.get(key, 0.0) + w0 * w[idx]
         state = new
-    fj = math.fsum(w for (v, e), w in state.items() if v == 0)
-
-    tail = 0.0
-    if max_errors is not None:
-        # exact distribution of the number of errors (each site errs with prob 1 - w_identity)
-        dist = [1.0]
-        for terms in site_terms:
-            q = 1.0 - terms[0][0]
-            nd = [0.0] * (len(dist) + 1)
-            for k, pk in enumerate(dist):
-                nd[k] += pk * (1 - q)
-                nd[k + 1] += pk * q
-            dist = nd
-        tail = math.fsum(dist[max_errors + 1:])
-    return {"fj": fj, "tail": tail}
+    return {"fj": state.get(0, 0.0)}

@@ -44,12 +44,16 @@ extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype 
   }
 }
 
+namespace jf {
+size_t plan_workspace_bytes(jf_plan* p);  // executor.hip: exact device layout of the plan
+}
+
 extern "C" jf_status jf_plan_info(const jf_plan* p, size_t* ws, jf_result* costs) {
   if (!p) {
     set_error("jf_plan_info: NULL plan");
     return JF_E_ARG;
   }
-  if (ws) *ws = p->prog.ws_bytes;
+  if (ws) *ws = plan_workspace_bytes(const_cast<jf_plan*>(p));
   if (costs) {
     jf_result r = {};
     r.kraus_terms = p->prog.kraus_terms;

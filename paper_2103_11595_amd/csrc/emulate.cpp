@@ -2,11 +2,64 @@
 // itself.  The emulation runs a plan's step program in FP64 with the very offset tables the
 // GPU kernels read; it exists so that the CPU test suite can validate the planner, slicing,
 // block fusion and output placement.  No fidelity entry point calls it.
+#include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "jf_internal.h"
 
 namespace jf {
+
+// Largest element index a step touches in A and in C must lie inside the tensors (and inside
+// the level buffer / output array that hold them).  Checked on the host before any launch.
+bool validate_program(const Program& P, std::string& why) {
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    const ComponentProgram& cp = P.comps[c];
+    for (size_t s = 0; s < cp.steps.size(); ++s) {
+      const Step& st = cp.steps[s];
+      const int K = 1 << st.kS, Nn = 1 << st.kN, R = 1 << st.L;
+      if (K > MAXK || Nn > MAXK || R > MAXR || (int)st.hiA.size() > MAXHI || (int)st.offS_A.size() != K ||
+          (int)st.offN_C.size() != Nn || (int)st.offR_A.size() != R || st.nTiles != (1LL << st.hiA.size()) ||
+          size_t(K) * (Nn + R) * 16 > 61440) {
+        why = "step table sizes out of range";
+        return false;
+      }
+      long long maxA = 0, maxC = 0;
+      long long mS = 0, mRA = 0, mN = 0, mRC = 0, hA = 0, hC = 0;
+      for (auto v : st.offS_A) mS = std::max(mS, v);
+      for (auto v : st.offR_A) mRA = std::max(mRA, v);
+      for (auto v : st.offN_C) mN = std::max(mN, v);
+      for (auto v : st.offR_C) mRC = std::max(mRC, v);
+      for (size_t b = 0; b < st.hiA.size(); ++b) {
+        hA += 1LL << st.hiA[b];
+        hC += 1LL << st.hiC[b];
+      }
+      maxA = hA + mS + mRA;
+      maxC = hC + mN + mRC;
+      const long long sizeA = 1LL << st.rA;
+      const long long sizeC = st.final_step ? cp.out_len : (1LL << st.rC);
+      if (maxA >= sizeA || maxC >= sizeC) {
+        why = "step " + std::to_string(s) + " addresses outside its tensors";
+        return false;
+      }
+      for (auto& b : st.B)
+        if ((long long)b.size() != (long long)K * Nn) {
+          why = "operator block size mismatch";
+          return false;
+        }
+    }
+    for (auto& lv : cp.levels)
+      for (int s = lv.first; s < lv.last; ++s) {
+        const Step& st = cp.steps[s];
+        size_t e = st.out_prec == P_C128 ? 16 : 8;
+        if (!st.final_step && (size_t(e) << st.rC) > lv.buf_bytes) {
+          why = "level buffer smaller than a step output";
+          return false;
+        }
+      }
+  }
+  return true;
+}
 
 void assemble_result(const Program& p, const std::vector<CompSum>& sums, jf_result* out) {
   jf_result r = {};

@@ -143,57 +143,6 @@ void build_layout(const Program& P, DevState& S) {
   std::memcpy(&S.host_image[L.const_off + 20], &zerof, 4);
 }
 
-// Largest element index a step touches in A and in C must lie inside the tensors (and inside
-// the level buffer / output array that hold them).  Checked on the host before any launch.
-bool validate_program(const Program& P, std::string& why) {
-  for (size_t c = 0; c < P.comps.size(); ++c) {
-    const ComponentProgram& cp = P.comps[c];
-    for (size_t s = 0; s < cp.steps.size(); ++s) {
-      const Step& st = cp.steps[s];
-      const int K = 1 << st.kS, Nn = 1 << st.kN, R = 1 << st.L;
-      if (K > DMAXK || Nn > DMAXK || R > DMAXR || (int)st.hiA.size() > DMAXHI || (int)st.offS_A.size() != K ||
-          (int)st.offN_C.size() != Nn || (int)st.offR_A.size() != R || st.nTiles != (1LL << st.hiA.size()) ||
-          size_t(K) * (Nn + R) * 16 > 61440) {
-        why = "step table sizes out of range";
-        return false;
-      }
-      long long maxA = 0, maxC = 0;
-      long long mS = 0, mRA = 0, mN = 0, mRC = 0, hA = 0, hC = 0;
-      for (auto v : st.offS_A) mS = std::max(mS, v);
-      for (auto v : st.offR_A) mRA = std::max(mRA, v);
-      for (auto v : st.offN_C) mN = std::max(mN, v);
-      for (auto v : st.offR_C) mRC = std::max(mRC, v);
-      for (size_t b = 0; b < st.hiA.size(); ++b) {
-        hA += 1LL << st.hiA[b];
-        hC += 1LL << st.hiC[b];
-      }
-      maxA = hA + mS + mRA;
-      maxC = hC + mN + mRC;
-      const long long sizeA = 1LL << st.rA;
-      const long long sizeC = st.final_step ? cp.out_len : (1LL << st.rC);
-      if (maxA >= sizeA || maxC >= sizeC) {
-        why = "step " + std::to_string(s) + " addresses outside its tensors";
-        return false;
-      }
-      for (auto& b : st.B)
-        if ((long long)b.size() != (long long)K * Nn) {
-          why = "operator block size mismatch";
-          return false;
-        }
-    }
-    for (auto& lv : cp.levels)
-      for (int s = lv.first; s < lv.last; ++s) {
-        const Step& st = cp.steps[s];
-        size_t e = st.out_prec == P_C128 ? 16 : 8;
-        if (!st.final_step && (size_t(e) << st.rC) > lv.buf_bytes) {
-          why = "level buffer smaller than a step output";
-          return false;
-        }
-      }
-  }
-  return true;
-}
-
 DevState& state_of(jf_plan* p) {
   if (!p->dev) {
     auto* s = new DevState;
@@ -367,6 +316,9 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
 }
 
 }  // namespace
+
+size_t plan_workspace_bytes(jf_plan* p) { return state_of(p).lay.total; }
+
 }  // namespace jf
 
 using namespace jf;

@@ -163,6 +163,9 @@ struct Program {
 
 Program plan_program(const jf_circuit& c, const PlanOptions& opt);
 
+// bounds check of every step's addresses, table sizes and LDS budget (host; before any launch)
+bool validate_program(const Program& P, std::string& why);
+
 // host emulation of the lowered program (validation only; no fidelity entry point calls it)
 void emulate_program(const Program& p, std::vector<std::vector<cd>>& comp_out);
 

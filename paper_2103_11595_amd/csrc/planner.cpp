@@ -395,6 +395,8 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           std::vector<int> S2, N2;
           split(trial, S2, N2);
           if ((int)S2.size() > opt.kmax || (int)N2.size() > opt.kmax) break;
+          // keep the operator block and at least 16 tile rows within the LDS budget
+          if ((1 << S2.size()) * ((1 << N2.size()) + 16) > 3840) break;
           // cost: fused block vs current block followed by nx alone
           int ein = (low && k >= switch_at) ? 16 : elem_lo;
           int rmid = rA - int(S.size()) + int(NN.size());
@@ -543,6 +545,11 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   P.ws_bytes = pool + 256 + max_comp_buf + (size_t(out_total) * 16 + 255) / 256 * 256 +
                (P.comps.size() * 4 * 8 + 255) / 256 * 256;
   P.planner_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  std::string why;
+  if (!validate_program(P, why)) {
+    set_error("internal planner error: " + why);
+    throw jf_status(JF_E_ARG);
+  }
   return P;
 }
 

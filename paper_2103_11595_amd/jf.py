@@ -89,6 +89,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_11595_amd.build`")
+    # torch ships its own HIP runtime under the same soname; load it first so that libjf binds to
+    # that one runtime (device pointers and streams then come from the runtime libjf uses)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, sz = C.c_void_p, C.c_size_t
     L.jf_load_circuit.argtypes = [C.c_int, C.POINTER(jf_gate), C.c_int, C.POINTER(jf_gate), C.c_int,

@@ -248,12 +248,14 @@ def test_clifford_checker_matches_dense(seed):
     assert abs(a - b) < 1e-12
 
 
-def test_clifford_checker_truncation_bound():
-    base = gen.random_circuit(8, 120, 9, 0.05, 0.2, 3)
-    twin = gen.clifford_twin(base, 3)
-    full = clifford.fidelity(twin)["fj"]
-    cut = clifford.fidelity(twin, max_errors=3)
-    assert cut["fj"] - 1e-15 <= full <= cut["fj"] + cut["tail"] + 1e-15
+def test_clifford_kernel_enumeration_matches_dp():
+    for seed in range(6):
+        base = gen.random_circuit(8, 120, 7, 0.05, 0.2, 30 + seed)
+        twin = gen.clifford_twin(base, seed)
+        a = clifford.fidelity(twin)["fj"]
+        b = clifford.fidelity_dp(twin)["fj"]
+        c = clifford.fidelity(twin, chunk_bits=1)["fj"]     # many chunks
+        assert abs(a - b) < 1e-13 and abs(c - b) < 1e-13
 
 
 # --- gate definitions (Section II-A and Example 1) ----------------------------------------
