@@ -156,6 +156,11 @@ typedef struct {
 } jf_plan_stats;
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 
+/* Text description of the lowered program, one line per device step:
+ * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes".
+ * Writes at most len bytes (NUL-terminated) and returns the full length needed. Host only. */
+long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
+
 /*
  * jf_fidelity_alg1 -- run an Algorithm I plan on the GPU.
  *   dev_ws/ws_bytes  device workspace (>= jf_plan_info size), stream = hipStream_t or NULL

@@ -1,5 +1,7 @@
 // C ABI: argument checking, planning entry points and handle management.  The GPU entry points
 // (jf_fidelity_alg1/alg2/batch, jf_batch_workspace) live in executor.hip.
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -115,3 +117,27 @@ extern "C" int jf_is_equivalent(const jf_result* r, double eps) {
 }
 
 extern "C" void jf_free_plan(jf_plan* p);  // executor.hip (releases device state too)
+
+extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len) {
+  if (!p) return -1;
+  std::string out;
+  const char* pn[] = {"c128", "c64"};
+  const char* cn[] = {"f64", "f32", "bf16x3"};
+  for (size_t c = 0; c < p->prog.comps.size(); ++c) {
+    const ComponentProgram& cp = p->prog.comps[c];
+    for (size_t lv = 0; lv < cp.levels.size(); ++lv)
+      for (int s = cp.levels[lv].first; s < cp.levels[lv].last; ++s) {
+        const Step& st = cp.steps[s];
+        char line[256];
+        snprintf(line, sizeof(line), "%zu %d %zu %d %d %d %d %d %lld %s %s %s %d %.6g %.6g\n", c, s, lv, st.kS, st.kN, st.L,
+                 st.rA, st.rC, st.nTiles, pn[st.in_prec], pn[st.out_prec], cn[st.compute], st.nvar, st.flops, st.bytes);
+        out += line;
+      }
+  }
+  if (buf && len > 0) {
+    long long n = std::min<long long>(len - 1, (long long)out.size());
+    memcpy(buf, out.data(), size_t(n));
+    buf[n] = 0;
+  }
+  return (long long)out.size() + 1;
+}

@@ -162,6 +162,112 @@ __global__ __launch_bounds__(256) void k_absorb_bf16x3(const StepDesc* __restric
   }
 }
 
+
+// ------------------------------------------------------------------ MFMA path (gfx950) ---
+// The tile product is computed transposed on the matrix cores: with the complex embedding
+//   A_real[r][2s + a] = (Re, Im)[a] of A[s][r]          (R x 2K)
+//   B_real[2s + a][2n + b] = [[Re, Im], [-Im, Re]][a][b] of B[s][n]   (2K x 2Nn)
+// one real GEMM gives C_real = A_real B_real, whose columns 2n, 2n + 1 are Re, Im of C[., n].
+// The MFMA computes D = B_real^T A_real^T (M = 2Nn, N = R, K = 2K) so that the 16 lanes of a
+// lane group hold 16 consecutive tile rows: their stores are contiguous runs.
+// v_mfma_*_16x16x4: lane l supplies A-operand (row l%16, k l/16) and B-operand (k l/16, col l%16).
+// Accumulator register v of lane group g = l/16 holds D row 4g + v (FP32) or 4v + g (FP64);
+// the mapping of MFMA rows to (complex column, component) below makes registers (0, 1) and
+// (2, 3) of every lane the (Re, Im) pairs of two complex outputs.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using acc_t = floatx4;
+  using c2 = float2;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row_of(int g, int v) { return 4 * g + v; }
+  static __device__ __forceinline__ int n_of(int i) { return i >> 1; }
+  static __device__ __forceinline__ int c_of(int i) { return i & 1; }
+};
+template <> struct Mfma<double> {
+  using acc_t = doublex4;
+  using c2 = double2;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row_of(int g, int v) { return 4 * v + g; }
+  static __device__ __forceinline__ int n_of(int i) { return (i & 3) + 4 * (i >> 3); }
+  static __device__ __forceinline__ int c_of(int i) { return (i >> 2) & 1; }
+};
+
+// Requires Nn >= 8, R >= 16, K >= 2 (the executor checks).  LDS: the real B^T operand,
+// k-major (2K x 2Nn), and the A tile as Re / Im planes (K x R each).
+template <typename T>
+__global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict__ d,
+                                                     const typename Mfma<T>::c2* A,
+                                                     typename Mfma<T>::c2* C,
+                                                     const typename Mfma<T>::c2* __restrict__ B) {
+  using M = Mfma<T>;
+  using C2 = typename M::c2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int K2 = 2 * K, M2 = 2 * Nn;
+  const long long nTiles = d->nTiles;
+  load_tables(d, tb, K, Nn, R, nHi);
+  T* sBt = reinterpret_cast<T*>(smem);   // [k][i], k < K2, i < M2
+  T* sAr = sBt + K2 * M2;                // [s][r]
+  T* sAi = sAr + K * R;
+  // B^T operand: row i of M-block mb maps to complex column mb * 8 + n_of(i % 16), component c_of
+  for (int idx = threadIdx.x; idx < K2 * M2; idx += blockDim.x) {
+    const int k = idx / M2, i = idx - k * M2;
+    const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
+    const int s = k >> 1, ca = k & 1;
+    const C2 bv = B[s * Nn + n];
+    T v = (ca ^ cb) ? bv.y : bv.x;
+    sBt[idx] = (ca && !cb) ? -v : v;
+  }
+  __syncthreads();  // offset tables and B^T visible to every wave before the first tile
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int Mb = M2 >> 4, Nb = R >> 4;
+  for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
+    long long bA = 0, bC = 0;
+    for (int b = 0; b < nHi; ++b)
+      if ((t >> b) & 1) {
+        bA |= 1LL << tb.hiA[b];
+        bC |= 1LL << tb.hiC[b];
+      }
+    __syncthreads();  // every wave is done with the previous tile's planes
+    for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
+      const int s = i >> L, r = i & (R - 1);
+      const C2 v = A[bA + tb.offS[s] + tb.offRA[r]];
+      sAr[i] = v.x;
+      sAi[i] = v.y;
+    }
+    __syncthreads();
+    for (int nb = wave; nb < Nb; nb += 4) {
+      const int j = nb * 16 + l16;  // tile row supplied / produced by this lane
+      for (int mb = 0; mb < Mb; ++mb) {
+        typename M::acc_t acc = {0, 0, 0, 0};
+        const T* bt = sBt + mb * 16 + l16;
+        for (int kk = 0; kk < K2; kk += 4) {
+          const int k = kk + g;
+          const T* plane = (k & 1) ? sAi : sAr;
+          acc = M::op(bt[k * M2], plane[(k >> 1) * R + j], acc);
+        }
+        for (int p = 0; p < 2; ++p) {
+          const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
+          C2 o;
+          o.x = acc[2 * p];
+          o.y = acc[2 * p + 1];
+          C[bC + tb.offN[n] + tb.offRC[j]] = o;
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------- small kernels ---
 __global__ void k_zero(double2* out, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -220,12 +326,24 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
   const unsigned grid = grid_for(h.nTiles);
   switch (h.mode) {
     case KM_F64: {
+      if (Nn >= 8 && R >= 16 && K >= 2) {
+        size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(double);
+        hipLaunchKernelGGL(k_absorb_mfma<double>, dim3(grid), dim3(256), sm, stream, d_desc, (const double2*)A,
+                           (double2*)C, (const double2*)B);
+        break;
+      }
       size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
       hipLaunchKernelGGL((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
                          (const double2*)A, (double2*)C, (const double2*)B);
       break;
     }
     case KM_F32: {
+      if (Nn >= 8 && R >= 16 && K >= 2) {
+        size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(float);
+        hipLaunchKernelGGL(k_absorb_mfma<float>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,
+                           (float2*)C, (const float2*)B);
+        break;
+      }
       size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
       hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
                          (const float2*)A, (float2*)C, (const float2*)B);

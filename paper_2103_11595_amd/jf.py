@@ -77,7 +77,7 @@ class jf_profile(C.Structure):
 EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_stats_get",
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
-           "jf_profile_run"]
+           "jf_profile_run", "jf_plan_describe"]
 
 _lib = None
 
@@ -110,10 +110,12 @@ def lib():
     L.jf_free_plan.argtypes = [vp]
     L.jf_free_plan.restype = None
     L.jf_last_error.restype = C.c_char_p
+    L.jf_plan_describe.restype = C.c_longlong
     L.jf_emulate_plan.argtypes = [vp, C.POINTER(C.c_double), C.c_longlong]
     L.jf_profile_run.argtypes = [vp, vp, sz, vp, C.POINTER(jf_profile)]
+    L.jf_plan_describe.argtypes = [vp, C.c_char_p, C.c_longlong]
     for name in EXPORTS:
-        if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error"):
+        if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -162,6 +164,21 @@ class Plan:
         s = jf_plan_stats()
         _check(lib().jf_plan_stats_get(self.ptr, C.byref(s)))
         return s.as_dict()
+
+    def describe(self):
+        """Per-step shapes of the lowered program (list of dicts)."""
+        L = lib()
+        n = L.jf_plan_describe(self.ptr, None, 0)
+        buf = C.create_string_buffer(int(n))
+        L.jf_plan_describe(self.ptr, buf, n)
+        keys = ["comp", "step", "level", "kS", "kN", "L", "rA", "rC", "tiles", "in_prec", "out_prec", "compute",
+                "nvar", "flops", "bytes"]
+        rows = []
+        for line in buf.value.decode().splitlines():
+            vals = line.split()
+            rows.append({k: (v if k in ("in_prec", "out_prec", "compute") else float(v) if k in ("flops", "bytes") else int(v))
+                         for k, v in zip(keys, vals)})
+        return rows
 
     def emulate(self):
         """Host emulation of the lowered step program (validation aid): complex terms for Alg I,
