@@ -45,7 +45,7 @@ std::map<const void*, const void*> g_last_upload;  // workspace -> plan that las
 
 int mode_of(const Step& st) {
   if (st.compute == C_F64) return st.in_prec == P_C64 ? KM_F32_TO_F64 : KM_F64;
-  if (st.compute == C_F32) return KM_F32;
+  if (st.compute == C_F32) return st.two_term ? KM_F32X2 : KM_F32;
   return KM_BF16X3;
 }
 
@@ -65,7 +65,9 @@ void build_layout(const Program& P, DevState& S) {
     L.step_b[c].resize(P.comps[c].steps.size());
     for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
       const Step& st = P.comps[c].steps[s];
-      size_t e = st.compute == C_F64 ? 16 : 8;
+      // FP64 steps: double2 blocks; FP32 steps: hi and lo float2 blocks (b = hi + lo to ~48 bits);
+      // 3xBF16 steps: float2 blocks (split on the device)
+      size_t e = st.compute == C_F64 ? 16 : (st.compute == C_F32 && st.two_term) ? 16 : 8;
       for (auto& b : st.B) {
         L.step_b[c][s].push_back(off);
         off += align256(b.size() * e);
@@ -127,10 +129,16 @@ void build_layout(const Program& P, DevState& S) {
             std::memcpy(dst + 16 * i + 8, &im, 8);
           }
         } else {
-          for (size_t i = 0; i < st.B[v].size(); ++i) {
+          const size_t nb = st.B[v].size();
+          for (size_t i = 0; i < nb; ++i) {
             float re = float(st.B[v][i].real()), im = float(st.B[v][i].imag());
             std::memcpy(dst + 8 * i, &re, 4);
             std::memcpy(dst + 8 * i + 4, &im, 4);
+            if (st.compute == C_F32 && st.two_term) {
+              float rl = float(st.B[v][i].real() - double(re)), il = float(st.B[v][i].imag() - double(im));
+              std::memcpy(dst + 8 * (nb + i), &rl, 4);
+              std::memcpy(dst + 8 * (nb + i) + 4, &il, 4);
+            }
           }
         }
       }

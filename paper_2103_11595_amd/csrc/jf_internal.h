@@ -102,6 +102,7 @@ struct Step {
   int nvar = 1;                  // >1: first step of a sliced level, B per Kraus variant
   std::vector<std::vector<cd>> B; // per variant: K x Nn row-major ([s][n])
   bool final_step = false;       // writes the component output (strided into the out array)
+  bool two_term = false;         // FP32 steps: operator stored as an FP32 pair (hi + lo)
   double flops = 0, bytes = 0;
   // device-side B offsets (filled at upload), per variant, in the pool of the compute type
   std::vector<long long> b_off;

@@ -32,6 +32,7 @@ enum KernelMode {
   KM_F32 = 1,       // float2 -> float2, FP32
   KM_F32_TO_F64 = 2,// float2 -> double2, FP64 (closing part of the low-precision modes)
   KM_BF16X3 = 3,    // float2 -> float2, three BF16 products per real product, FP32 accumulate
+  KM_F32X2 = 4,     // float2 -> float2, FP32, operator as an FP32 pair (hi + lo) -- noise-carrying blocks
 };
 
 // Launch one step.  A / C may alias (in-place steps): every tile reads exactly the elements it

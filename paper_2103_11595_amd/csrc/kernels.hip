@@ -121,6 +121,44 @@ __global__ __launch_bounds__(256) void k_absorb(const StepDesc* __restrict__ d, 
   }
 }
 
+// FP32 path with a two-term operator: B = Bhi + Blo (both FP32, Blo the rounding residual of
+// the FP64 block), so the operator itself carries no rounding error; A and the accumulation
+// stay FP32.
+__global__ __launch_bounds__(256) void k_absorb_f32x2(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                      const float2* __restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const long long nTiles = d->nTiles;
+  load_tables(d, tb, K, Nn, R, nHi);
+  float2* sB = reinterpret_cast<float2*>(smem);   // hi then lo
+  float2* sA = sB + 2 * K * Nn;
+  for (int i = threadIdx.x; i < 2 * K * Nn; i += blockDim.x) sB[i] = B[i];
+  __syncthreads();
+  for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
+    long long bA = 0, bC = 0;
+    for (int b = 0; b < nHi; ++b)
+      if ((t >> b) & 1) {
+        bA |= 1LL << tb.hiA[b];
+        bC |= 1LL << tb.hiC[b];
+      }
+    for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
+      const int s = i >> L, r = i & (R - 1);
+      sA[i] = A[bA + tb.offS[s] + tb.offRA[r]];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < Nn * R; o += blockDim.x) {
+      const int n = o >> L, r = o & (R - 1);
+      float2 acc = make_float2(0.f, 0.f);
+      for (int s = 0; s < K; ++s) acc = cfma(acc, sA[s * R + r], sB[K * Nn + s * Nn + n]);  // residual first
+      for (int s = 0; s < K; ++s) acc = cfma(acc, sA[s * R + r], sB[s * Nn + n]);
+      C[bC + tb.offN[n] + tb.offRC[r]] = acc;
+    }
+    __syncthreads();
+  }
+}
+
 // 3xBF16 path: A and B split on their way into LDS.
 __global__ __launch_bounds__(256) void k_absorb_bf16x3(const StepDesc* __restrict__ d, const float2* A, float2* C,
                                                        const float2* __restrict__ B) {
@@ -200,8 +238,11 @@ template <> struct Mfma<double> {
 };
 
 // Requires Nn >= 8, R >= 16, K >= 2 (the executor checks).  LDS: the real B^T operand,
-// k-major (2K x 2Nn), and the A tile as Re / Im planes (K x R each).
-template <typename T>
+// k-major (2K x 2Nn; a second copy holds the residual operator for two-term steps), and the A
+// tile as Re / Im planes (K x R each).  With TWO_TERM the operator is Bhi + Blo (FP32 pair); the
+// small Blo products are accumulated first so that the correction survives the FP32 roundings of
+// the running sum.
+template <typename T, bool TWO_TERM>
 __global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict__ d,
                                                      const typename Mfma<T>::c2* A,
                                                      typename Mfma<T>::c2* C,
@@ -215,8 +256,8 @@ __global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict_
   const int K2 = 2 * K, M2 = 2 * Nn;
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
-  T* sBt = reinterpret_cast<T*>(smem);   // [k][i], k < K2, i < M2
-  T* sAr = sBt + K2 * M2;                // [s][r]
+  T* sBt = reinterpret_cast<T*>(smem);            // [k][i] (hi), then [k][i] (lo)
+  T* sAr = sBt + (TWO_TERM ? 2 : 1) * K2 * M2;    // [s][r]
   T* sAi = sAr + K * R;
   // B^T operand: row i of M-block mb maps to complex column mb * 8 + n_of(i % 16), component c_of
   for (int idx = threadIdx.x; idx < K2 * M2; idx += blockDim.x) {
@@ -224,8 +265,13 @@ __global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict_
     const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
     const int s = k >> 1, ca = k & 1;
     const C2 bv = B[s * Nn + n];
-    T v = (ca ^ cb) ? bv.y : bv.x;
+    const T v = (ca ^ cb) ? bv.y : bv.x;
     sBt[idx] = (ca && !cb) ? -v : v;
+    if (TWO_TERM) {
+      const C2 bl = B[K * Nn + s * Nn + n];
+      const T w = (ca ^ cb) ? bl.y : bl.x;
+      sBt[K2 * M2 + idx] = (ca && !cb) ? -w : w;
+    }
   }
   __syncthreads();  // offset tables and B^T visible to every wave before the first tile
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -251,10 +297,15 @@ __global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict_
       for (int mb = 0; mb < Mb; ++mb) {
         typename M::acc_t acc = {0, 0, 0, 0};
         const T* bt = sBt + mb * 16 + l16;
+        if (TWO_TERM) {
+          for (int kk = 0; kk < K2; kk += 4) {
+            const int k = kk + g;
+            acc = M::op(bt[K2 * M2 + k * M2], ((k & 1) ? sAi : sAr)[(k >> 1) * R + j], acc);
+          }
+        }
         for (int kk = 0; kk < K2; kk += 4) {
           const int k = kk + g;
-          const T* plane = (k & 1) ? sAi : sAr;
-          acc = M::op(bt[k * M2], plane[(k >> 1) * R + j], acc);
+          acc = M::op(bt[k * M2], ((k & 1) ? sAi : sAr)[(k >> 1) * R + j], acc);
         }
         for (int p = 0; p < 2; ++p) {
           const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
@@ -328,8 +379,8 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     case KM_F64: {
       if (Nn >= 8 && R >= 16 && K >= 2) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(double);
-        hipLaunchKernelGGL(k_absorb_mfma<double>, dim3(grid), dim3(256), sm, stream, d_desc, (const double2*)A,
-                           (double2*)C, (const double2*)B);
+        hipLaunchKernelGGL((k_absorb_mfma<double, false>), dim3(grid), dim3(256), sm, stream, d_desc,
+                           (const double2*)A, (double2*)C, (const double2*)B);
         break;
       }
       size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
@@ -340,13 +391,25 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     case KM_F32: {
       if (Nn >= 8 && R >= 16 && K >= 2) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(float);
-        hipLaunchKernelGGL(k_absorb_mfma<float>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,
-                           (float2*)C, (const float2*)B);
+        hipLaunchKernelGGL((k_absorb_mfma<float, false>), dim3(grid), dim3(256), sm, stream, d_desc,
+                           (const float2*)A, (float2*)C, (const float2*)B);
         break;
       }
       size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
       hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
                          (const float2*)A, (float2*)C, (const float2*)B);
+      break;
+    }
+    case KM_F32X2: {
+      if (Nn >= 8 && R >= 16 && K >= 2) {
+        size_t sm = size_t(8 * K * Nn + 2 * K * R) * sizeof(float);
+        hipLaunchKernelGGL((k_absorb_mfma<float, true>), dim3(grid), dim3(256), sm, stream, d_desc,
+                           (const float2*)A, (float2*)C, (const float2*)B);
+        break;
+      }
+      size_t sm = size_t(2 * K * Nn + K * R) * sizeof(float2);
+      hipLaunchKernelGGL(k_absorb_f32x2, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+                         (const float2*)B);
       break;
     }
     case KM_F32_TO_F64: {

@@ -495,6 +495,13 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           st.out_prec = fp64 ? P_C128 : P_C64;
           st.compute = fp64 ? C_F64 : (opt.dtype == JF_C64 ? C_F32 : C_BF16X3);
           cur_prec = st.out_prec;
+          // Noise operators are near-identity blocks repeated at many sites: their FP32
+          // rounding errors share a sign and add up linearly over the sites, so blocks that
+          // carry one keep the operator as an FP32 pair (hi + lo).  Gate-only blocks round
+          // with uncorrelated errors and stay single.
+          if (st.compute == C_F32)
+            for (int q = k; q < e; ++q)
+              if (L.ts[pth.order[q]]->site >= 0) st.two_term = true;
         }
         int ein = st.in_prec == P_C128 ? 16 : 8, eout = st.out_prec == P_C128 ? 16 : 8;
         st.flops = 8.0 * std::ldexp(1.0, int(F.size()) + st.kS + st.kN);
