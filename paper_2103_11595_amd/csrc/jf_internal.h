@@ -87,7 +87,7 @@ enum Prec { P_C128 = 0, P_C64 = 1 };            // storage
 enum Compute { C_F64 = 0, C_F32 = 1, C_BF16X3 = 2 };
 
 constexpr int MAXK = 64;     // max K (=2^kS) and Nn (=2^kN) of one device step
-constexpr int MAXR = 64;     // max rows per tile
+constexpr int MAXR = 256;    // max rows per tile
 constexpr int MAXHI = 48;    // max high (tile-index) bits
 
 // One device step: C[f, n] = sum_s A[f, s] * B[s, n]  (complex), see kernels.hip.

@@ -6,7 +6,7 @@
 namespace jf {
 
 constexpr int DMAXK = 64;   // entries of the s / n offset tables
-constexpr int DMAXR = 64;   // rows per tile
+constexpr int DMAXR = 256;  // rows per tile
 constexpr int DMAXHI = 48;  // tile-index bits
 
 // One contraction step C[f, n] = sum_s A[f, s] B[s, n] on bit-addressed tensors:

@@ -237,30 +237,33 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int c_of(int i) { return (i >> 2) & 1; }
 };
 
-// Requires Nn >= 8, R >= 16, K >= 2 (the executor checks).  LDS: the real B^T operand,
-// k-major (2K x 2Nn; a second copy holds the residual operator for two-term steps), and the A
-// tile as Re / Im planes (K x R each).  With TWO_TERM the operator is Bhi + Blo (FP32 pair); the
-// small Blo products are accumulated first so that the correction survives the FP32 roundings of
-// the running sum.
-template <typename T, bool TWO_TERM>
-__global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict__ d,
-                                                     const typename Mfma<T>::c2* A,
-                                                     typename Mfma<T>::c2* C,
-                                                     const typename Mfma<T>::c2* __restrict__ B) {
+// Requires Nn >= 8, R >= 16, K >= 2 and K * R <= 4096 (the executor checks).  LDS: the real
+// B^T operand, k-major (2K x 2Nn; a second copy holds the residual operator for two-term steps),
+// and the A tile as Re / Im planes (K x R each).  The next tile is fetched into registers while
+// the current one is multiplied (NT threads, K * R / NT elements each).  With TWO_TERM the
+// operator is Bhi + Blo (an FP32 pair); the small Blo products are accumulated first so that the
+// correction survives the FP32 roundings of the running sum.
+template <typename T, bool TWO_TERM, int NT>
+__global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__ d,
+                                                    const typename Mfma<T>::c2* A,
+                                                    typename Mfma<T>::c2* C,
+                                                    const typename Mfma<T>::c2* __restrict__ B) {
   using M = Mfma<T>;
   using C2 = typename M::c2;
+  constexpr int MAXE = 4096 / NT;  // staged elements per thread
+  constexpr int NW = NT / 64;      // waves
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
-  const int K2 = 2 * K, M2 = 2 * Nn;
+  const int K2 = 2 * K, M2 = 2 * Nn, KR = K * R;
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
   T* sBt = reinterpret_cast<T*>(smem);            // [k][i] (hi), then [k][i] (lo)
   T* sAr = sBt + (TWO_TERM ? 2 : 1) * K2 * M2;    // [s][r]
-  T* sAi = sAr + K * R;
+  T* sAi = sAr + KR;
   // B^T operand: row i of M-block mb maps to complex column mb * 8 + n_of(i % 16), component c_of
-  for (int idx = threadIdx.x; idx < K2 * M2; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < K2 * M2; idx += NT) {
     const int k = idx / M2, i = idx - k * M2;
     const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
     const int s = k >> 1, ca = k & 1;
@@ -277,22 +280,38 @@ __global__ __launch_bounds__(256) void k_absorb_mfma(const StepDesc* __restrict_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int Mb = M2 >> 4, Nb = R >> 4;
-  for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
-    long long bA = 0, bC = 0;
-    for (int b = 0; b < nHi; ++b)
-      if ((t >> b) & 1) {
-        bA |= 1LL << tb.hiA[b];
-        bC |= 1LL << tb.hiC[b];
-      }
+  auto base = [&](long long t, const int* hi) {
+    long long b = 0;
+    for (int q = 0; q < nHi; ++q)
+      if ((t >> q) & 1) b |= 1LL << hi[q];
+    return b;
+  };
+  C2 stage[MAXE];
+  auto fetch = [&](long long t) {
+    const long long bA = base(t, tb.hiA);
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = threadIdx.x + NT * e;
+      if (i < KR) stage[e] = A[bA + tb.offS[i >> L] + tb.offRA[i & (R - 1)]];
+    }
+  };
+  long long t = blockIdx.x;
+  if (t < nTiles) fetch(t);
+  for (; t < nTiles; t += gridDim.x) {
+    const long long bC = base(t, tb.hiC);
     __syncthreads();  // every wave is done with the previous tile's planes
-    for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
-      const int s = i >> L, r = i & (R - 1);
-      const C2 v = A[bA + tb.offS[s] + tb.offRA[r]];
-      sAr[i] = v.x;
-      sAi[i] = v.y;
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = threadIdx.x + NT * e;
+      if (i < KR) {
+        sAr[i] = stage[e].x;
+        sAi[i] = stage[e].y;
+      }
     }
     __syncthreads();
-    for (int nb = wave; nb < Nb; nb += 4) {
+    // the next tile belongs to this workgroup only: its loads overlap this tile's products
+    if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
+    for (int nb = wave; nb < Nb; nb += NW) {
       const int j = nb * 16 + l16;  // tile row supplied / produced by this lane
       for (int mb = 0; mb < Mb; ++mb) {
         typename M::acc_t acc = {0, 0, 0, 0};
@@ -377,9 +396,9 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
   const unsigned grid = grid_for(h.nTiles);
   switch (h.mode) {
     case KM_F64: {
-      if (Nn >= 8 && R >= 16 && K >= 2) {
+      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(double);
-        hipLaunchKernelGGL((k_absorb_mfma<double, false>), dim3(grid), dim3(256), sm, stream, d_desc,
+        hipLaunchKernelGGL((k_absorb_mfma<double, false, 512>), dim3(grid), dim3(512), sm, stream, d_desc,
                            (const double2*)A, (double2*)C, (const double2*)B);
         break;
       }
@@ -389,9 +408,9 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32: {
-      if (Nn >= 8 && R >= 16 && K >= 2) {
+      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(float);
-        hipLaunchKernelGGL((k_absorb_mfma<float, false>), dim3(grid), dim3(256), sm, stream, d_desc,
+        hipLaunchKernelGGL((k_absorb_mfma<float, false, 256>), dim3(grid), dim3(256), sm, stream, d_desc,
                            (const float2*)A, (float2*)C, (const float2*)B);
         break;
       }
@@ -401,9 +420,9 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32X2: {
-      if (Nn >= 8 && R >= 16 && K >= 2) {
+      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(8 * K * Nn + 2 * K * R) * sizeof(float);
-        hipLaunchKernelGGL((k_absorb_mfma<float, true>), dim3(grid), dim3(256), sm, stream, d_desc,
+        hipLaunchKernelGGL((k_absorb_mfma<float, true, 256>), dim3(grid), dim3(256), sm, stream, d_desc,
                            (const float2*)A, (float2*)C, (const float2*)B);
         break;
       }

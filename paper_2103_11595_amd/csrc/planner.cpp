@@ -445,9 +445,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         }
         st.final_step = final_step;
         // rows: the lowest F legs
-        // rows per tile: at most 64, and the LDS tile (K x (Nn + R) entries of 16 bytes) within 60 KB
-        int Lr = std::min<int>(int(F.size()), 6);
-        while (Lr > 0 && (1 << st.kS) * ((1 << st.kN) + (1 << Lr)) > 3840) --Lr;
+        // rows per tile: a tile of K x R elements with K * R <= 4096 (at least 2048 when the
+        // tensor allows, so small operators still move 16 KB or more per tile), at most 256 rows,
+        // and the LDS tile (K x (Nn + R) entries of 16 bytes) within 60 KB
+        int Lr = std::min<int>(int(F.size()), 8);
+        while (Lr > 0 && ((1 << st.kS) * (1 << Lr) > 4096 || (1 << st.kS) * ((1 << st.kN) + (1 << Lr)) > 3840)) --Lr;
+        while (Lr > 6 && (1 << st.kS) * (1 << (Lr - 1)) >= 2048) --Lr;
         st.L = Lr;
         std::vector<int> rowsA, rowsC, hiA, hiC, sA, nC;
         for (int i = 0; i < Lr; ++i) {
