@@ -338,6 +338,119 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   }
 }
 
+
+// 3xBF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Every FP32 operand x is split
+// into hi = bf16(x) and lo = bf16(x - hi); a product a*b is hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b)
+// with FP32 accumulation (the cross terms in their own accumulator, added at the end).
+// Operand layout of the instruction: lane l supplies A-operand row l%16, k = 8(l/16) .. +7 and
+// B-operand column l%16, same k; accumulator register v holds row 4(l/16) + v (as FP32 16x16x4).
+// LDS holds both operands split, as BF16, row-major with the 2K reals of a row contiguous (rows
+// padded to whole 32-k chunks plus 8, so a lane's 8 consecutive k are one 16-byte read).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as_float(uint32_t(b) << 16); }
+__device__ __forceinline__ bf16x8 lds8(const unsigned short* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_absorb_bf16x3_mfma(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                           const float2* __restrict__ B) {
+  using M = Mfma<float>;  // same accumulator layout
+  constexpr int MAXE = 4096 / NT;
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int K2 = 2 * K, M2 = 2 * Nn, KR = K * R;
+  const int K2c = (K2 + 31) & ~31, KP = K2c + 8;  // k chunks of 32, row pitch in BF16 elements
+  const long long nTiles = d->nTiles;
+  load_tables(d, tb, K, Nn, R, nHi);
+  unsigned short* sBh = reinterpret_cast<unsigned short*>(smem);  // [i][KP], i < M2
+  unsigned short* sBl = sBh + M2 * KP;
+  unsigned short* sAh = sBl + M2 * KP;                            // [j][KP], j < R
+  unsigned short* sAl = sAh + R * KP;
+  for (int idx = threadIdx.x; idx < (2 * M2 + 2 * R) * KP; idx += NT) sBh[idx] = 0;  // zero padding
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < K2 * M2; idx += NT) {
+    const int k = idx / M2, i = idx - k * M2;
+    const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
+    const int s = k >> 1, ca = k & 1;
+    const float2 bv = B[s * Nn + n];
+    float v = (ca ^ cb) ? bv.y : bv.x;
+    if (ca && !cb) v = -v;
+    const unsigned short h = bf16_bits(v);
+    sBh[i * KP + k] = h;
+    sBl[i * KP + k] = bf16_bits(v - bf16_value(h));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int Mb = M2 >> 4, Nb = R >> 4;
+  auto base = [&](long long t, const int* hi) {
+    long long b = 0;
+    for (int q = 0; q < nHi; ++q)
+      if ((t >> q) & 1) b |= 1LL << hi[q];
+    return b;
+  };
+  float2 stage[MAXE];
+  auto fetch = [&](long long t) {
+    const long long bA = base(t, tb.hiA);
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = threadIdx.x + NT * e;
+      if (i < KR) stage[e] = A[bA + tb.offS[i >> L] + tb.offRA[i & (R - 1)]];
+    }
+  };
+  long long t = blockIdx.x;
+  if (t < nTiles) fetch(t);
+  for (; t < nTiles; t += gridDim.x) {
+    const long long bC = base(t, tb.hiC);
+    __syncthreads();  // every wave is done with the previous tile
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = threadIdx.x + NT * e;
+      if (i < KR) {
+        const int s = i >> L, r = i & (R - 1);
+        const unsigned short hr = bf16_bits(stage[e].x), hi = bf16_bits(stage[e].y);
+        sAh[r * KP + 2 * s] = hr;
+        sAh[r * KP + 2 * s + 1] = hi;
+        sAl[r * KP + 2 * s] = bf16_bits(stage[e].x - bf16_value(hr));
+        sAl[r * KP + 2 * s + 1] = bf16_bits(stage[e].y - bf16_value(hi));
+      }
+    }
+    __syncthreads();
+    if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
+    for (int nb = wave; nb < Nb; nb += NW) {
+      const int j = nb * 16 + l16;
+      for (int mb = 0; mb < Mb; ++mb) {
+        floatx4 acc = {0, 0, 0, 0}, cross = {0, 0, 0, 0};
+        const unsigned short* bh = sBh + (mb * 16 + l16) * KP + 8 * g;
+        const unsigned short* bl = sBl + (mb * 16 + l16) * KP + 8 * g;
+        const unsigned short* ah = sAh + j * KP + 8 * g;
+        const unsigned short* al = sAl + j * KP + 8 * g;
+        for (int kc = 0; kc < K2c; kc += 32) {
+          const bf16x8 xbh = lds8(bh + kc), xbl = lds8(bl + kc), xah = lds8(ah + kc), xal = lds8(al + kc);
+          cross = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbl, xah, cross, 0, 0, 0);
+          cross = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbh, xal, cross, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbh, xah, acc, 0, 0, 0);
+        }
+        for (int p = 0; p < 2; ++p) {
+          const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
+          C[bC + tb.offN[n] + tb.offRC[j]] = make_float2(acc[2 * p] + cross[2 * p], acc[2 * p + 1] + cross[2 * p + 1]);
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------- small kernels ---
 __global__ void k_zero(double2* out, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -438,6 +551,13 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_BF16X3: {
+      if (Nn >= 8 && R >= 16 && K * R <= 4096) {
+        const int KP = ((2 * K + 31) & ~31) + 8;
+        size_t sm = size_t(4 * Nn + 2 * R) * KP * sizeof(unsigned short);
+        hipLaunchKernelGGL(k_absorb_bf16x3_mfma<256>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,
+                           (float2*)C, (const float2*)B);
+        break;
+      }
       size_t sm = size_t(K * Nn + K * R) * sizeof(SplitC);
       hipLaunchKernelGGL(k_absorb_bf16x3, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
                          (const float2*)B);
