@@ -25,6 +25,9 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct DevLayout {
   size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
+  size_t lds_items_off = 0, lds_steps_off = 0;
+  std::vector<int> lds_comps;                             // components run by the persistent kernel
+  int lds_steps = 0;
   std::vector<std::vector<size_t>> step_desc;             // per component, per step: descriptor offset
   std::vector<std::vector<std::vector<size_t>>> step_b;   // per component, step, variant: B offset
   std::vector<std::vector<size_t>> level_buf;             // per component: 2 buffers per level
@@ -38,6 +41,7 @@ struct DevState {
   hipGraphExec_t graph = nullptr;
   const void* graph_ws = nullptr;
   hipStream_t graph_stream = nullptr;
+  std::vector<const jf_plan*> graph_plans;  // the batch the cached graph was captured for
 };
 
 std::mutex g_upload_mu;
@@ -76,11 +80,24 @@ void build_layout(const Program& P, DevState& S) {
   }
   L.const_off = off;
   off += 256;  // double2 one at +0, float2 one at +16
+  for (size_t c = 0; c < P.comps.size(); ++c)
+    if (P.comps[c].lds_resident) {
+      L.lds_comps.push_back(int(c));
+      L.lds_steps += int(P.comps[c].steps.size());
+    }
+  L.lds_items_off = off;
+  off += align256(L.lds_comps.size() * sizeof(LdsItem));
+  L.lds_steps_off = off;
+  off += align256(size_t(L.lds_steps) * sizeof(LdsStep));
   L.buf_off = off;
   size_t maxbuf = 0;
   L.level_buf.resize(P.comps.size());
   for (size_t c = 0; c < P.comps.size(); ++c) {
     size_t o = 0;
+    if (P.comps[c].lds_resident) {
+      L.level_buf[c].assign(2 * P.comps[c].levels.size(), L.buf_off);
+      continue;
+    }
     for (auto& lv : P.comps[c].levels) {
       L.level_buf[c].push_back(L.buf_off + o);
       o += align256(lv.buf_bytes);
@@ -151,6 +168,31 @@ void build_layout(const Program& P, DevState& S) {
   std::memcpy(&S.host_image[L.const_off + 20], &zerof, 4);
 }
 
+// Persistent-kernel tables of a plan whose workspace starts at ws (absolute device pointers).
+void fill_lds_tables(const Program& P, const DevLayout& L, unsigned char* ws, LdsItem* items, LdsStep* steps,
+                     int step_base) {
+  int si = 0;
+  for (size_t q = 0; q < L.lds_comps.size(); ++q) {
+    const int c = L.lds_comps[q];
+    const ComponentProgram& cp = P.comps[c];
+    LdsItem it;
+    it.first = step_base + si;
+    it.count = int(cp.steps.size());
+    it.out = reinterpret_cast<double2*>(ws + L.out_off + size_t(cp.out_off) * 16);
+    it.sums = reinterpret_cast<double*>(ws + L.sums_off) + 4 * c;
+    it.out_len = cp.out_len;
+    items[q] = it;
+    for (size_t k = 0; k < cp.steps.size(); ++k) {
+      LdsStep e;
+      e.desc = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][k]);
+      e.B = ws + L.step_b[c][k][0];
+      e.mode = mode_of(cp.steps[k]);
+      e.final_step = cp.steps[k].final_step ? 1 : 0;
+      steps[si++] = e;
+    }
+  }
+}
+
 DevState& state_of(jf_plan* p) {
   if (!p->dev) {
     auto* s = new DevState;
@@ -175,12 +217,17 @@ struct Prof {
 };
 
 // Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
-jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr) {
+jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
+                          bool skip_lds = false) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
   const DevLayout& L = S.lay;
+  if (!skip_lds && !L.lds_comps.empty())
+    JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off), int(L.lds_comps.size()),
+                             reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), stream));
   for (size_t c = 0; c < P.comps.size(); ++c) {
     const ComponentProgram& cp = P.comps[c];
+    if (cp.lds_resident) continue;
     unsigned char* out = ws + L.out_off + size_t(cp.out_off) * 16;
     JF_HIP(launch_zero(out, cp.out_len, stream));
     // depth-first walk over the levels
@@ -246,6 +293,9 @@ jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
   DevState& S = state_of(p);
   std::lock_guard<std::mutex> g(g_upload_mu);
   if (S.uploaded_to == ws && g_last_upload[ws] == p) return JF_OK;
+  fill_lds_tables(p->prog, S.lay, static_cast<unsigned char*>(ws),
+                  reinterpret_cast<LdsItem*>(&S.host_image[S.lay.lds_items_off]),
+                  reinterpret_cast<LdsStep*>(&S.host_image[S.lay.lds_steps_off]), 0);
   JF_HIP(hipMemcpyAsync(ws, S.host_image.data(), S.host_image.size(), hipMemcpyHostToDevice, stream));
   JF_HIP(hipStreamSynchronize(stream));
   S.uploaded_to = ws;
@@ -401,6 +451,12 @@ extern "C" jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* by
     }
     tot += (state_of(plans[i]).lay.total + 255) / 256 * 256;
   }
+  size_t items = 0, steps = 0;
+  for (int i = 0; i < n; ++i) {
+    items += state_of(plans[i]).lay.lds_comps.size();
+    steps += state_of(plans[i]).lay.lds_steps;
+  }
+  tot += align256(items * sizeof(LdsItem)) + align256(steps * sizeof(LdsStep));
   *bytes = tot;
   return JF_OK;
 }
@@ -425,22 +481,47 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   for (int i = 0; i < n; ++i) {
     base[i] = static_cast<unsigned char*>(ws) + off;
     off += (state_of(plans[i]).lay.total + 255) / 256 * 256;
+    st = check_ws(plans[i], base[i], state_of(plans[i]).lay.total);
+    if (st != JF_OK) return st;
     st = upload(plans[i], base[i], stream);
     if (st != JF_OK) return st;
+  }
+  // every small component of every plan in one persistent launch
+  std::vector<LdsItem> items;
+  std::vector<LdsStep> lsteps;
+  for (int i = 0; i < n; ++i) {
+    const DevLayout& L = state_of(plans[i]).lay;
+    std::vector<LdsItem> it(L.lds_comps.size());
+    std::vector<LdsStep> ss(L.lds_steps);
+    fill_lds_tables(plans[i]->prog, L, base[i], it.data(), ss.data(), int(lsteps.size()));
+    items.insert(items.end(), it.begin(), it.end());
+    lsteps.insert(lsteps.end(), ss.begin(), ss.end());
+  }
+  unsigned char* items_dev = static_cast<unsigned char*>(ws) + off;
+  unsigned char* steps_dev = items_dev + align256(items.size() * sizeof(LdsItem));
+  if (!items.empty()) {
+    JF_HIP(hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(LdsItem), hipMemcpyHostToDevice, stream));
+    JF_HIP(hipMemcpyAsync(steps_dev, lsteps.data(), lsteps.size() * sizeof(LdsStep), hipMemcpyHostToDevice, stream));
+    JF_HIP(hipStreamSynchronize(stream));
   }
   hipEvent_t e0, e1;
   JF_HIP(hipEventCreate(&e0));
   JF_HIP(hipEventCreate(&e1));
   DevState& S0 = state_of(plans[0 < n ? 0 : 0]);
   const bool use_graph = n > 0 && stream != nullptr;
-  if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream)) {
+  std::vector<const jf_plan*> key(plans, plans + n);
+  if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream || S0.graph_plans != key)) {
     if (S0.graph) {
       hipGraphExecDestroy(S0.graph);
       S0.graph = nullptr;
     }
     hipGraph_t g;
     JF_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream);
+    if (!items.empty() &&
+        launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
+                          reinterpret_cast<const LdsStep*>(steps_dev), stream) != hipSuccess)
+      st = JF_E_HIP;
+    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream, nullptr, true);
     hipError_t ce = hipStreamEndCapture(stream, &g);
     if (st != JF_OK) return st;
     if (ce != hipSuccess) {
@@ -451,13 +532,17 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     JF_HIP(hipGraphDestroy(g));
     S0.graph_ws = ws;
     S0.graph_stream = stream;
+    S0.graph_plans = key;
   }
   JF_HIP(hipEventRecord(e0, stream));
   if (use_graph) {
     JF_HIP(hipGraphLaunch(S0.graph, stream));
   } else {
+    if (!items.empty())
+      JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
+                               reinterpret_cast<const LdsStep*>(steps_dev), stream));
     for (int i = 0; i < n; ++i) {
-      st = enqueue_program(plans[i], base[i], stream);
+      st = enqueue_program(plans[i], base[i], stream, nullptr, true);
       if (st != JF_OK) return st;
     }
   }

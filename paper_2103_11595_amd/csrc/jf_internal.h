@@ -129,6 +129,8 @@ struct ComponentProgram {
   int n_tensors = 0;
   // device: offset of the component output (double2 elements) in the output region
   long long out_off = 0;
+  // one level and every intermediate <= 2^11 elements: runs whole in one workgroup (LDS)
+  bool lds_resident = false;
 };
 
 struct PlanOptions {

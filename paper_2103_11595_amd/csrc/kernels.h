@@ -41,6 +41,26 @@ enum KernelMode {
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h_desc, const void* A, void* C, const void* B,
                        hipStream_t stream);
 
+// Persistent executor of small component programs (every intermediate <= 2^11 elements, one
+// level): one workgroup per item, both ping-pong buffers in LDS, FP64 throughout.  A step entry
+// points at its descriptor and operator block (compute type given by mode; FP32 two-term blocks
+// are summed hi + lo); the final step writes the item's output and its double-double sum of
+// |t|^2 (sums[0..1]) and t_0 (sums[2..3]).
+constexpr int LDS_RESIDENT_LOG2 = 11;
+struct LdsStep {
+  const StepDesc* desc;
+  const void* B;
+  int mode;
+  int final_step;
+};
+struct LdsItem {
+  int first, count;   // steps [first, first + count) of the step table
+  double2* out;       // component output (double2 x out_len)
+  double* sums;       // 4 doubles
+  long long out_len;
+};
+hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream);
+
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
 

@@ -497,6 +497,99 @@ __global__ __launch_bounds__(256) void k_sumsq(const double2* x, long long n, do
   }
 }
 
+
+// ------------------------------------------------------------ persistent LDS executor ---
+// Items are whole component programs whose tensors fit in LDS.  Each workgroup takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ... (static assignment: deterministic results).  A step
+// computes every output element with one thread (no in-place: the two buffers alternate).
+__device__ __forceinline__ double2 load_op(const void* B, int mode, int idx, int KN) {
+  if (mode == KM_F64 || mode == KM_F32_TO_F64) return reinterpret_cast<const double2*>(B)[idx];
+  const float2 h = reinterpret_cast<const float2*>(B)[idx];
+  double2 v = make_double2(h.x, h.y);
+  if (mode == KM_F32X2) {
+    const float2 l = reinterpret_cast<const float2*>(B)[KN + idx];
+    v.x += l.x;
+    v.y += l.y;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ items, int n_items,
+                                                    const LdsStep* __restrict__ steps) {
+  __shared__ double2 buf[2][1 << LDS_RESIDENT_LOG2];
+  __shared__ Tables tb;
+  __shared__ double rh[256], rl[256];
+  __shared__ double2 first;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const LdsItem item = items[it];
+    int cur = -1;  // -1: the scalar 1
+    double hi = 0.0, lo = 0.0;
+    if (threadIdx.x == 0) first = make_double2(0.0, 0.0);
+    for (int q = 0; q < item.count; ++q) {
+      const LdsStep st = steps[item.first + q];
+      const StepDesc* d = st.desc;
+      const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+      const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+      __syncthreads();  // previous step complete before its tables are replaced
+      load_tables(d, tb, K, Nn, R, nHi);
+      __syncthreads();
+      const int dst = cur == 0 ? 1 : 0;
+      const long long total = d->nTiles << (kN + L);
+      for (long long o = threadIdx.x; o < total; o += blockDim.x) {
+        const int r = int(o & (R - 1));
+        const int n = int((o >> L) & (Nn - 1));
+        const long long t = o >> (L + kN);
+        long long bA = 0, bC = 0;
+        for (int b = 0; b < nHi; ++b)
+          if ((t >> b) & 1) {
+            bA |= 1LL << tb.hiA[b];
+            bC |= 1LL << tb.hiC[b];
+          }
+        double2 acc = make_double2(0.0, 0.0);
+        for (int s2 = 0; s2 < K; ++s2) {
+          const double2 a = cur < 0 ? make_double2(1.0, 0.0) : buf[cur][bA + tb.offS[s2] + tb.offRA[r]];
+          acc = cfma(acc, a, load_op(st.B, st.mode, s2 * Nn + n, K * Nn));
+        }
+        const long long oc = bC + tb.offN[n] + tb.offRC[r];
+        if (st.final_step) {
+          item.out[oc] = acc;
+          const double p = fma(acc.x, acc.x, acc.y * acc.y);
+          double sum, err;
+          two_sum(hi, p, sum, err);
+          hi = sum;
+          lo += err;
+          if (oc == 0) first = acc;
+        } else {
+          buf[dst][oc] = acc;
+        }
+      }
+      cur = dst;
+    }
+    // double-double reduction of the |t|^2 partial sums (fixed tree)
+    rh[threadIdx.x] = hi;
+    rl[threadIdx.x] = lo;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        double sum, err;
+        two_sum(rh[threadIdx.x], rh[threadIdx.x + w], sum, err);
+        err += rl[threadIdx.x] + rl[threadIdx.x + w];
+        const double h2 = sum + err;
+        rl[threadIdx.x] = err - (h2 - sum);
+        rh[threadIdx.x] = h2;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      item.sums[0] = rh[0];
+      item.sums[1] = rl[0];
+      item.sums[2] = first.x;
+      item.sums[3] = first.y;
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------------- launchers ---
 static unsigned grid_for(long long nTiles) {
   const long long cap = 256 * 16;
@@ -565,6 +658,13 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     }
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  const int grid = n_items < 2048 ? n_items : 2048;
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(256), 0, stream, items, n_items, steps);
   return hipGetLastError();
 }
 

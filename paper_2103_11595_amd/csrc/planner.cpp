@@ -531,6 +531,9 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       cp.levels.push_back(Lv);
     }
     cp.leaves = mult;
+    cp.lds_resident = cp.levels.size() == 1 && cp.levels[0].nvar == 1;
+    for (auto& st : cp.steps)
+      if (st.rA > 11 || (!st.final_step && st.rC > 11)) cp.lds_resident = false;
     cp.flops = comp_flops;
     cp.bytes = comp_bytes;
     size_t cbuf = 0;

@@ -239,3 +239,19 @@ def test_workspace_too_small_is_reported():
     with pytest.raises(jf.JfError) as e:
         jf.jf_fidelity_alg1(p, ws)
     assert e.value.status == -6
+
+
+def test_batch_of_small_circuits_against_oracle():
+    # many small networks of uneven size in one batch: the LDS-resident ones run in one
+    # persistent launch, the rest as step programs; each result against the dense oracle
+    rng = np.random.default_rng(99)
+    insts = []
+    for i in range(40):
+        n = int(rng.integers(2, 9))
+        insts.append(gen.random_circuit(n, int(rng.integers(20, 160)), int(rng.integers(1, 5)), 1e-3, 0.05, 5000 + i))
+    plans = [jf.plan(x, 1 + (i % 2), "c128") for i, x in enumerate(insts)]
+    say("batch of", len(plans), "small circuits")
+    out = jf.jf_fidelity_batch(plans)
+    for i, (x, r) in enumerate(zip(insts, out)):
+        want = dense.fidelity_alg1(x)["fj"]
+        assert abs(r["fj"] - want) <= 1e-12, (i, r["fj"], want)
