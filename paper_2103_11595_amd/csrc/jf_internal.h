@@ -140,7 +140,9 @@ struct PlanOptions {
   unsigned flags = 0;
   int kmax = 5;                  // fused block limit on |S| and |N|
   int switch_log2 = 12;          // steps whose tensors stay <= 2^switch run in FP64 (closing part)
-  double time_budget_s = 0.5;    // greedy restarts budget per component
+  double time_budget_s = 10.0;   // safety cap on the restart search (plans are reproducible below it)
+  int restarts = 16384;          // randomised greedy restarts per component
+  int threads = 8;               // planner worker threads
   unsigned seed = 12345;
 };
 

@@ -20,6 +20,7 @@
 #include <map>
 #include <random>
 #include <set>
+#include <thread>
 
 #include "jf_internal.h"
 
@@ -248,15 +249,47 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       for (int i = 0; i < N; ++i) starts.push_back(i);
     for (int s : starts) consider(greedy(L, s, rng, 0.0));
     {
-      std::uniform_int_distribution<int> pick(0, N - 1);
-      int tries = 0;
-      while (tries < 256) {
-        double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (el > opt.time_budget_s && tries >= 8) break;
-        int s = (tries % 2 == 0 && !starts.empty()) ? starts[tries / 2 % starts.size()] : pick(rng);
-        consider(greedy(L, s, rng, 0.5 + (tries % 5) * 0.5));
-        ++tries;
-      }
+      // Randomised restarts on a thread pool.  Each worker draws its starts and Boltzmann noise
+      // from its own seeded generator and keeps its best path; the winner is chosen by the same
+      // rule in worker order, so the plan does not depend on timing (the time cap only guards
+      // pathological inputs).
+      const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
+      const int tries_total = N <= 24 ? 256 : opt.restarts;
+      std::vector<Path> wbest(workers);
+      std::vector<int> whave(workers, 0);
+      auto work = [&](int w) {
+        std::mt19937_64 wr(opt.seed * 7919u + 104729u * unsigned(w + 1) + unsigned(N));
+        std::uniform_int_distribution<int> pick(0, N - 1);
+        const int mine = tries_total / workers + (w < tries_total % workers ? 1 : 0);
+        Path bestw;
+        int bw_base = 1 << 30;
+        bool hv = false;
+        for (int tries = 0; tries < mine; ++tries) {
+          double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          if (el > opt.time_budget_s && tries >= 8) break;
+          int s = (tries % 2 == 0 && !starts.empty()) ? starts[(tries / 2 + w) % starts.size()] : pick(wr);
+          Path p = greedy(L, s, wr, 0.5 + ((tries + w) % 5) * 0.5);
+          int bw = base_width(p);
+          bool feas = bw <= opt.cap_log2, bfeas = bw_base <= opt.cap_log2;
+          bool better = !hv || (feas != bfeas ? feas
+                                              : (!feas ? bw < bw_base
+                                                       : (p.cost < bestw.cost * (1 - 1e-12) ||
+                                                          (p.cost <= bestw.cost * (1 + 1e-12) && p.maxw < bestw.maxw))));
+          if (better) {
+            bestw = std::move(p);
+            bw_base = bw;
+            hv = true;
+          }
+        }
+        wbest[w] = std::move(bestw);
+        whave[w] = hv;
+      };
+      std::vector<std::thread> pool;
+      for (int w = 1; w < workers; ++w) pool.emplace_back(work, w);
+      work(0);
+      for (auto& th : pool) th.join();
+      for (int w = 0; w < workers; ++w)
+        if (whave[w]) consider(wbest[w]);
     }
 
     // ---- slicing of Kraus indices
