@@ -113,6 +113,10 @@ typedef struct jf_plan jf_plan;
                                   Section IV-C that cancels adjacent mutually inverse gates) */
 #define JF_FLAG_NO_FUSE   2u   /* one contraction step per network tensor (no block fusion) */
 #define JF_FLAG_NO_BATCH  4u   /* slice every Kraus index (one DFS leaf per Kraus tuple) */
+/* Search effort of the planner: JF_FLAG_EFFORT(e), e = 1..15, runs 2^(e+5) randomised greedy
+ * restarts per component (default, e = 0 in the flags: 2^16).  More restarts find cheaper
+ * contraction orders; the plan is reproducible for a given effort. */
+#define JF_FLAG_EFFORT(e) (((unsigned)(e) & 15u) << 8)
 
 /*
  * jf_load_circuit -- ingest an ideal circuit, its noisy implementation and the noise sites

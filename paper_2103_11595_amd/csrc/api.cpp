@@ -32,6 +32,8 @@ extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype 
     return JF_E_ARG;
   }
   opt.flags = flags;
+  const unsigned effort = (flags >> 8) & 15u;
+  if (effort) opt.restarts = 1 << (effort + 5);
   opt.kmax = dtype == JF_C64_BF16X3 ? 6 : 5;
   try {
     auto p = new jf_plan;

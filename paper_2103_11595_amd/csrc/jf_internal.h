@@ -141,7 +141,7 @@ struct PlanOptions {
   int kmax = 5;                  // fused block limit on |S| and |N|
   int switch_log2 = 12;          // steps whose tensors stay <= 2^switch run in FP64 (closing part)
   double time_budget_s = 10.0;   // safety cap on the restart search (plans are reproducible below it)
-  int restarts = 16384;          // randomised greedy restarts per component
+  int restarts = 65536;          // randomised greedy restarts per component
   int threads = 8;               // planner worker threads
   unsigned seed = 12345;
 };

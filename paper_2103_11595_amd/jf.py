@@ -20,6 +20,11 @@ JF_C128, JF_C64, JF_C64_BF16X3 = 0, 1, 2
 DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x3": JF_C64_BF16X3}
 JF_FLAG_NO_CANCEL, JF_FLAG_NO_FUSE, JF_FLAG_NO_BATCH = 1, 2, 4
 
+
+def JF_FLAG_EFFORT(e: int) -> int:
+    """Planner search effort: 2^(e+5) randomised greedy restarts per component (e = 1..15)."""
+    return (int(e) & 15) << 8
+
 STATUS = {0: "JF_OK", -1: "JF_E_ARG", -2: "JF_E_NOT_UNITARY", -3: "JF_E_NOT_TP", -4: "JF_E_QUBIT",
           -5: "JF_E_TOO_LARGE", -6: "JF_E_OOM", -7: "JF_E_HIP", -8: "JF_E_UNSUPPORTED"}
 
