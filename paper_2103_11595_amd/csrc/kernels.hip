@@ -243,7 +243,7 @@ template <> struct Mfma<double> {
 // the current one is multiplied (NT threads, K * R / NT elements each).  With TWO_TERM the
 // operator is Bhi + Blo (an FP32 pair); the small Blo products are accumulated first so that the
 // correction survives the FP32 roundings of the running sum.
-template <typename T, bool TWO_TERM, int NT>
+template <typename T, bool TWO_TERM, int NT, int MB>
 __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__ d,
                                                     const typename Mfma<T>::c2* A,
                                                     typename Mfma<T>::c2* C,
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   __syncthreads();  // offset tables and B^T visible to every wave before the first tile
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int Mb = M2 >> 4, Nb = R >> 4;
+  const int Nb = R >> 4;  // MB = M2 / 16 output blocks per row block (the launcher checks)
   auto base = [&](long long t, const int* hi) {
     long long b = 0;
     for (int q = 0; q < nHi; ++q)
@@ -313,24 +313,32 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
     if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
     for (int nb = wave; nb < Nb; nb += NW) {
       const int j = nb * 16 + l16;  // tile row supplied / produced by this lane
-      for (int mb = 0; mb < Mb; ++mb) {
-        typename M::acc_t acc = {0, 0, 0, 0};
-        const T* bt = sBt + mb * 16 + l16;
-        if (TWO_TERM) {
-          for (int kk = 0; kk < K2; kk += 4) {
-            const int k = kk + g;
-            acc = M::op(bt[K2 * M2 + k * M2], ((k & 1) ? sAi : sAr)[(k >> 1) * R + j], acc);
-          }
-        }
+      // k outermost: each A value is read from LDS once and used by all MB output blocks
+      typename M::acc_t acc[MB];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = typename M::acc_t{0, 0, 0, 0};
+      const T* bt = sBt + l16;
+      if (TWO_TERM) {
         for (int kk = 0; kk < K2; kk += 4) {
           const int k = kk + g;
-          acc = M::op(bt[k * M2], ((k & 1) ? sAi : sAr)[(k >> 1) * R + j], acc);
+          const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[K2 * M2 + k * M2 + 16 * mb], a, acc[mb]);
         }
+      }
+      for (int kk = 0; kk < K2; kk += 4) {
+        const int k = kk + g;
+        const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[k * M2 + 16 * mb], a, acc[mb]);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
         for (int p = 0; p < 2; ++p) {
           const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
           C2 o;
-          o.x = acc[2 * p];
-          o.y = acc[2 * p + 1];
+          o.x = acc[mb][2 * p];
+          o.y = acc[mb][2 * p + 1];
           C[bC + tb.offN[n] + tb.offRC[j]] = o;
         }
       }
@@ -596,6 +604,22 @@ static unsigned grid_for(long long nTiles) {
   return unsigned(nTiles < cap ? nTiles : cap);
 }
 
+// MFMA step launch with the output block count (Nn / 8 blocks of 16 MFMA rows) fixed at compile time.
+template <typename T, bool TWO_TERM, int NT>
+void launch_mfma(unsigned grid, size_t sm, hipStream_t stream, const StepDesc* d_desc, int Nn, const void* A,
+                 void* C, const void* B) {
+  using C2 = typename Mfma<T>::c2;
+  const C2* a = (const C2*)A;
+  const C2* b = (const C2*)B;
+  C2* c = (C2*)C;
+  switch (Nn) {
+    case 8: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 16: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 32: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: /* 64, the largest Nn a step may have */ hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+  }
+}
+
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A, void* C, const void* B,
                        hipStream_t stream) {
   const int K = 1 << h.kS, Nn = 1 << h.kN, R = 1 << h.L;
@@ -604,8 +628,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     case KM_F64: {
       if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(double);
-        hipLaunchKernelGGL((k_absorb_mfma<double, false, 512>), dim3(grid), dim3(512), sm, stream, d_desc,
-                           (const double2*)A, (double2*)C, (const double2*)B);
+        launch_mfma<double, false, 512>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
       size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
@@ -616,8 +639,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     case KM_F32: {
       if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(float);
-        hipLaunchKernelGGL((k_absorb_mfma<float, false, 256>), dim3(grid), dim3(256), sm, stream, d_desc,
-                           (const float2*)A, (float2*)C, (const float2*)B);
+        launch_mfma<float, false, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
       size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
@@ -628,8 +650,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     case KM_F32X2: {
       if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(8 * K * Nn + 2 * K * R) * sizeof(float);
-        hipLaunchKernelGGL((k_absorb_mfma<float, true, 256>), dim3(grid), dim3(256), sm, stream, d_desc,
-                           (const float2*)A, (float2*)C, (const float2*)B);
+        launch_mfma<float, true, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
       size_t sm = size_t(2 * K * Nn + K * R) * sizeof(float2);
