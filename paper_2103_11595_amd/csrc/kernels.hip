@@ -237,7 +237,8 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int c_of(int i) { return (i >> 2) & 1; }
 };
 
-// Requires Nn >= 8, R >= 16, K >= 2 and K * R <= 4096 (the executor checks).  LDS: the real
+// Requires R >= 16, K >= 2 and K * R <= 4096 (the executor checks); Nn < 8 pads the operator
+// to one 16-row block and stores only the Nn real columns.  LDS: the real
 // B^T operand, k-major (2K x 2Nn; a second copy holds the residual operator for two-term steps),
 // and the A tile as Re / Im planes (K x R each).  The next tile is fetched into registers while
 // the current one is multiplied (NT threads, K * R / NT elements each).  With TWO_TERM the
@@ -256,7 +257,8 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   __shared__ Tables tb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
-  const int K2 = 2 * K, M2 = 2 * Nn, KR = K * R;
+  // M2: MFMA rows of the operator, at least one 16-row block (rows past 2Nn are zero)
+  const int K2 = 2 * K, M2 = 2 * Nn < 16 ? 16 : 2 * Nn, KR = K * R;
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
   T* sBt = reinterpret_cast<T*>(smem);            // [k][i] (hi), then [k][i] (lo)
@@ -267,11 +269,11 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
     const int k = idx / M2, i = idx - k * M2;
     const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
     const int s = k >> 1, ca = k & 1;
-    const C2 bv = B[s * Nn + n];
+    const C2 bv = n < Nn ? B[s * Nn + n] : C2{0, 0};
     const T v = (ca ^ cb) ? bv.y : bv.x;
     sBt[idx] = (ca && !cb) ? -v : v;
     if (TWO_TERM) {
-      const C2 bl = B[K * Nn + s * Nn + n];
+      const C2 bl = n < Nn ? B[K * Nn + s * Nn + n] : C2{0, 0};
       const T w = (ca ^ cb) ? bl.y : bl.x;
       sBt[K2 * M2 + idx] = (ca && !cb) ? -w : w;
     }
@@ -339,7 +341,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
           C2 o;
           o.x = acc[mb][2 * p];
           o.y = acc[mb][2 * p + 1];
-          C[bC + tb.offN[n] + tb.offRC[j]] = o;
+          if (MB > 1 || n < Nn) C[bC + tb.offN[n] + tb.offRC[j]] = o;
         }
       }
     }
@@ -613,7 +615,7 @@ void launch_mfma(unsigned grid, size_t sm, hipStream_t stream, const StepDesc* d
   const C2* b = (const C2*)B;
   C2* c = (C2*)C;
   switch (Nn) {
-    case 8: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 1: case 2: case 4: case 8: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     case 16: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     case 32: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     default: /* 64, the largest Nn a step may have */ hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
@@ -626,8 +628,8 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
   const unsigned grid = grid_for(h.nTiles);
   switch (h.mode) {
     case KM_F64: {
-      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(double);
+      if (R >= 16 && K >= 2 && K * R <= 4096) {
+        size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(double);
         launch_mfma<double, false, 512>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
@@ -637,8 +639,8 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32: {
-      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(4 * K * Nn + 2 * K * R) * sizeof(float);
+      if (R >= 16 && K >= 2 && K * R <= 4096) {
+        size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
         launch_mfma<float, false, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
@@ -648,8 +650,8 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32X2: {
-      if (Nn >= 8 && R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(8 * K * Nn + 2 * K * R) * sizeof(float);
+      if (R >= 16 && K >= 2 && K * R <= 4096) {
+        size_t sm = size_t(8 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
         launch_mfma<float, true, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
         break;
       }
