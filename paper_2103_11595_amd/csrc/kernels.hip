@@ -349,6 +349,111 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
 }
 
 
+// Register-direct variant: no A tile in LDS.  The sum over the 2K real k indices may be taken in
+// any order, so MFMA k-step t, lane group g is given real index (s = 4 (t / 2) + g, component
+// t % 2): a lane then needs Re and Im of the same A[s][row], one complex load, used on two
+// consecutive k-steps.  A work unit is (tile, block of 16 tile rows); each wave takes units
+// independently (no barrier after set-up) and loads its next unit while multiplying the current
+// one.  KQ = ceil(K / 4) complex values per lane and unit; lanes with s >= K supply zero.  The
+// operator (two copies for TWO_TERM) stays in LDS, k-major in the same order.  In-place steps
+// are safe: a unit writes exactly the elements it has read, after reading all of them.
+template <typename T, bool TWO_TERM, int NT, int MB, int KQ>
+__global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restrict__ d,
+                                                       const typename Mfma<T>::c2* A,
+                                                       typename Mfma<T>::c2* C,
+                                                       const typename Mfma<T>::c2* __restrict__ B) {
+  using M = Mfma<T>;
+  using C2 = typename M::c2;
+  constexpr int NW = NT / 64, KT = 2 * KQ, M2 = 16 * MB;  // MFMA k-steps, operator rows (padded)
+  constexpr int BT = KT * 4 * M2;                         // operator entries per copy
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int rbits = L - 4;
+  const long long nUnits = d->nTiles << rbits;
+  load_tables(d, tb, K, Nn, R, nHi);
+  T* sBt = reinterpret_cast<T*>(smem);  // [4 t + g][i] (hi), then the same for lo
+  for (int idx = threadIdx.x; idx < BT; idx += NT) {
+    const int kr = idx / M2, i = idx - kr * M2;
+    const int t = kr >> 2, g = kr & 3;
+    const int s = 4 * (t >> 1) + g, ca = t & 1;
+    const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
+    T v = 0, w = 0;
+    if (s < K && n < Nn) {
+      const C2 bv = B[s * Nn + n];
+      v = (ca ^ cb) ? bv.y : bv.x;
+      if (ca && !cb) v = -v;
+      if (TWO_TERM) {
+        const C2 bl = B[K * Nn + s * Nn + n];
+        w = (ca ^ cb) ? bl.y : bl.x;
+        if (ca && !cb) w = -w;
+      }
+    }
+    sBt[idx] = v;
+    if (TWO_TERM) sBt[BT + idx] = w;
+  }
+  __syncthreads();  // offset tables and operator visible to every wave
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const long long wstride = (long long)gridDim.x * NW;
+  auto base = [&](long long t, const int* hi) {
+    long long b = 0;
+    for (int q = 0; q < nHi; ++q)
+      if ((t >> q) & 1) b |= 1LL << hi[q];
+    return b;
+  };
+  auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
+  C2 nxt[KQ];
+  auto fetch = [&](long long v) {
+    const long long bA = base(v >> rbits, tb.hiA) + tb.offRA[row_of_unit(v)];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) {
+      const int s = 4 * u + g;
+      nxt[u] = s < K ? A[bA + tb.offS[s]] : C2{0, 0};
+    }
+  };
+  long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
+  if (v < nUnits) fetch(v);
+  for (; v < nUnits; v += wstride) {
+    C2 cur[KQ];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) cur[u] = nxt[u];
+    if (v + wstride < nUnits) fetch(v + wstride);
+    typename M::acc_t acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = typename M::acc_t{0, 0, 0, 0};
+    if (TWO_TERM) {  // residual products first: the correction survives the FP32 running sum
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const T a = (t & 1) ? cur[t >> 1].y : cur[t >> 1].x;
+        const T* bt = sBt + BT + (4 * t + g) * M2 + l16;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[16 * mb], a, acc[mb]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const T a = (t & 1) ? cur[t >> 1].y : cur[t >> 1].x;
+      const T* bt = sBt + (4 * t + g) * M2 + l16;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[16 * mb], a, acc[mb]);
+    }
+    const long long bC = base(v >> rbits, tb.hiC) + tb.offRC[row_of_unit(v)];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
+        C2 o;
+        o.x = acc[mb][2 * p];
+        o.y = acc[mb][2 * p + 1];
+        if (MB > 1 || n < Nn) C[bC + tb.offN[n]] = o;
+      }
+    }
+  }
+}
+
+
 // 3xBF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Every FP32 operand x is split
 // into hi = bf16(x) and lo = bf16(x - hi); a product a*b is hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b)
 // with FP32 accumulation (the cross terms in their own accumulator, added at the end).
@@ -622,12 +727,52 @@ void launch_mfma(unsigned grid, size_t sm, hipStream_t stream, const StepDesc* d
   }
 }
 
+// Register-direct launch: (MB, KQ) fixed at compile time.  Returns false when no instance covers
+// the shape (the caller then uses the LDS-staged kernel).
+template <typename T, bool TWO_TERM, int NT, int MB>
+bool launch_rd_mb(long long units, hipStream_t stream, const StepDesc* d_desc, int K, const void* A, void* C,
+                  const void* B) {
+  using C2 = typename Mfma<T>::c2;
+  const C2* a = (const C2*)A;
+  const C2* b = (const C2*)B;
+  C2* c = (C2*)C;
+  const int KQ = (K + 3) / 4;
+  const long long wgs = (units + NT / 64 - 1) / (NT / 64);
+  const unsigned grid = unsigned(wgs < 2048 ? wgs : 2048);
+  const size_t sm = size_t((TWO_TERM ? 2 : 1) * 2 * KQ * 4 * 16 * MB) * sizeof(T);
+  switch (KQ) {
+    case 1: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
+    case 2: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
+    case 4: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
+    case 8: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
+    default: return false;
+  }
+}
+
+// The register-direct kernel is used where it measured faster than the LDS-staged one: FP64 up
+// to Nn = 32 and FP32 for Nn <= 8 (at larger Nn the FP32 products are MFMA-bound and the staged
+// kernel's shared A tile wins).  Needs at least 16 tile rows and K <= 32.
+template <typename T, bool TWO_TERM, int NT>
+bool launch_rd(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+               const void* B) {
+  const int K = 1 << h.kS, Nn = 1 << h.kN;
+  if (h.L < 4 || K > 32) return false;
+  const long long units = h.nTiles << (h.L - 4);
+  if (Nn <= 8) return launch_rd_mb<T, TWO_TERM, NT, 1>(units, stream, d_desc, K, A, C, B);
+  if constexpr (sizeof(T) == 8) {
+    if (Nn == 16) return launch_rd_mb<T, TWO_TERM, NT, 2>(units, stream, d_desc, K, A, C, B);
+    if (Nn == 32) return launch_rd_mb<T, TWO_TERM, NT, 4>(units, stream, d_desc, K, A, C, B);
+  }
+  return false;
+}
+
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A, void* C, const void* B,
                        hipStream_t stream) {
   const int K = 1 << h.kS, Nn = 1 << h.kN, R = 1 << h.L;
   const unsigned grid = grid_for(h.nTiles);
   switch (h.mode) {
     case KM_F64: {
+      if (launch_rd<double, false, 256>(h, stream, d_desc, A, C, B)) break;
       if (R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(double);
         launch_mfma<double, false, 512>(grid, sm, stream, d_desc, Nn, A, C, B);
@@ -639,6 +784,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32: {
+      if (launch_rd<float, false, 512>(h, stream, d_desc, A, C, B)) break;
       if (R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
         launch_mfma<float, false, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
@@ -650,6 +796,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_F32X2: {
+      if (launch_rd<float, true, 512>(h, stream, d_desc, A, C, B)) break;
       if (R >= 16 && K >= 2 && K * R <= 4096) {
         size_t sm = size_t(8 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
         launch_mfma<float, true, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
