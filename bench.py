@@ -6,7 +6,8 @@ MI355X, complex64 against complex128, on the n=16 / 400-gate / 4-depolarising-si
 
 One step = one full pass of the hot path over the workload: every contraction step of the plan
 for all 256 Kraus tuples, the FP64 closing contractions, the Kahan-compensated sum and the
-readback of F_J.  Planning and the one-time upload of the step program happen before timing.
+readback of F_J.  Planning, the one-time upload of the step program and the kernel autotuner
+(which times every kernel that can run each step and keeps the fastest) happen before timing.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -23,8 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK = {"c64": {"mfma": 157.3, "alu": 78.6}, "c128": {"mfma": 78.6, "alu": 78.6}}  # TFLOP/s
-RIDGE_FP32 = 157.3e12 / 8e12
+PEAK = {"c64": {"mfma": 157.3}, "c128": {"mfma": 78.6}}  # dense MFMA TFLOP/s (fp32 / fp64)
 
 
 def cpu_baseline(budget_s: float = 25.0) -> dict:
@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"], help="form reported as value")
     ap.add_argument("--only", action="store_true", help="run only the reported form (profiling runs)")
+    ap.add_argument("--no-autotune", action="store_true", help="time the fixed kernel rule only")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB with torch (a plain copy kernel of known size, "
                          "the reference for hardware byte counters)")
@@ -99,17 +100,32 @@ def main():
         p = jf.plan(inst, 1, dt)
         info = p.info()
         ws = jf.workspace(info["workspace_bytes"])
-        for _ in range(args.warmup if dt == args.dtype else 1):
+        main = dt == args.dtype
+        steps = args.steps if main else max(3, args.steps // 4)
+
+        def timed(n):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                r = jf.jf_fidelity_alg1(p, ws, stream)
+            torch.cuda.synchronize()
+            return r, (time.perf_counter() - t0) / n
+
+        jf.jf_fidelity_alg1(p, ws, stream)
+        untuned = None
+        if not args.no_autotune:
+            if not args.only:
+                untuned = timed(max(2, steps // 4))[1]
+            t0 = time.perf_counter()
+            jf.jf_autotune(p, ws, stream)
+            tune_s = time.perf_counter() - t0
+        for _ in range(args.warmup if main else 1):
             jf.jf_fidelity_alg1(p, ws, stream)
-        steps = args.steps if dt == args.dtype else max(3, args.steps // 4)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            r = jf.jf_fidelity_alg1(p, ws, stream)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        r, sec = timed(steps)
         prof = jf.jf_profile_run(p, ws, stream)
-        res[dt] = {"plan": p, "info": info, "r": r, "sec": el / steps, "steps": steps, "prof": prof}
+        per_step = jf.jf_profile_steps(p, ws, stream)
+        res[dt] = {"plan": p, "info": info, "r": r, "sec": sec, "steps": steps, "prof": prof, "per_step": per_step,
+                   "untuned_sec": untuned, "tune_s": None if args.no_autotune else tune_s}
         del ws
 
     main_form = res[args.dtype]
@@ -118,11 +134,34 @@ def main():
     prof = main_form["prof"]
     flops, byts, kms = prof["flops"], prof["bytes"], prof["kernel_ms"]
     intensity = flops / byts if byts else 0.0
-    if intensity < RIDGE_FP32:
+    ridge = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"] * 1e3 / PEAK_HBM_GBS
+    if intensity < ridge:
         bound, achieved, peak, unit = "hbm", byts / (kms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
-        bound, unit = "alu", "TFLOP/s"
-        achieved, peak = flops / (kms * 1e-3) / 1e12, PEAK["c64" if args.dtype != "c128" else "c128"]["alu"]
+        bound, unit = "mfma", "TFLOP/s"
+        achieved, peak = flops / (kms * 1e-3) / 1e12, PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
+    # large contractions (complex GEMMs of K >= 16 summed and new extents, intensity >= 8 flop/B)
+    # against the FP32 (c64) or FP64 (c128) MFMA peak, and the other steps against HBM
+    mm = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
+    big = [x for x in main_form["per_step"] if x["flops"] >= 8 * x["bytes"]]
+    rest = [x for x in main_form["per_step"] if x["flops"] < 8 * x["bytes"]]
+    big_ms, rest_ms = sum(x["ms"] for x in big), sum(x["ms"] for x in rest)
+    big_fl, big_b = sum(x["flops"] for x in big), sum(x["bytes"] for x in big)
+    big_tf = big_fl / (big_ms * 1e-3) / 1e12 if big_ms else 0.0
+    attainable = min(mm, (big_fl / big_b) * PEAK_HBM_GBS / 1e3) if big_b else mm
+    classes = {
+        "large_contractions": {"launches": len(big), "ms": big_ms, "tflops": big_tf, "peak_tflops": mm,
+                               "frac_of_mfma_peak": big_tf / mm, "intensity_flop_per_byte": big_fl / big_b if big_b else 0,
+                               "attainable_tflops": attainable, "frac_of_attainable": big_tf / attainable if attainable else 0,
+                               "hbm_gbs": big_b / (big_ms * 1e-3) / 1e9 if big_ms else 0},
+        "streaming_steps": {"launches": len(rest), "ms": rest_ms,
+                            "hbm_gbs": sum(x["bytes"] for x in rest) / (rest_ms * 1e-3) / 1e9 if rest_ms else 0,
+                            "frac_of_hbm_peak": (sum(x["bytes"] for x in rest) / (rest_ms * 1e-3) / 1e9) / PEAK_HBM_GBS if rest_ms else 0},
+    }
+    kv_names = {v: k for k, v in jf.KERNEL_VARIANTS.items()}
+    kernels_used = {}
+    for x in main_form["per_step"]:
+        kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
     ksha = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
     traffic = traffic_record(ksha)
     out = {
@@ -149,8 +188,13 @@ def main():
                        "abs_dfj_vs_c128": abs(v["r"]["fj"] - res["c128"]["r"]["fj"]) if "c128" in res else None,
                        "max_log2_intermediate": v["info"]["max_log2_intermediate"],
                        "path_flops": v["info"]["path_flops"], "path_bytes": v["info"]["path_bytes"],
-                       "launches": v["prof"]["launches"], "kernel_ms": v["prof"]["kernel_ms"]}
+                       "launches": v["prof"]["launches"], "kernel_ms": v["prof"]["kernel_ms"],
+                       "untuned_ms_per_step": v["untuned_sec"] * 1e3 if v["untuned_sec"] else None,
+                       "autotune_s": v["tune_s"]}
                   for dt, v in res.items()},
+        "autotuned": not args.no_autotune,
+        "step_classes": classes,
+        "kernels_used": kernels_used,
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_absorb (contraction step)", "launches": prof["launches"],

@@ -161,7 +161,9 @@ typedef struct {
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 
 /* Text description of the lowered program, one line per device step:
- * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes".
+ * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes rowsA rowsC sA nC",
+ * the last four being comma-separated bit positions (A for tile rows and summed legs, C for tile
+ * rows and new legs; "-" when empty).
  * Writes at most len bytes (NUL-terminated) and returns the full length needed. Host only. */
 long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
 
@@ -207,6 +209,59 @@ typedef struct {
   double max_launch_ms; /* longest single launch */
 } jf_profile;
 jf_status jf_profile_run(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, jf_profile* out);
+
+/*
+ * jf_profile_steps -- the same run, reported per launch: out[i] for the i-th contraction-step
+ * launch in program order (i < cap), *n_launches = number of launches.  mode is the step's
+ * arithmetic (0 FP64, 1 FP32, 2 FP32 in / FP64 out, 3 3xBF16, 4 FP32 with a two-term operator);
+ * variant the kernel that ran it (jf_kernel_variant, never AUTO).
+ */
+typedef struct {
+  double ms;     /* event-measured duration */
+  double flops;  /* real flops (complex MAC = 8) */
+  double bytes;  /* algorithmic bytes: input tensor read once, output written once */
+  int kS, kN, L; /* log2 of summed, new and per-tile row extents */
+  int mode, variant, component;
+} jf_step_profile;
+jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, jf_step_profile* out,
+                           int cap, int* n_launches);
+
+/*
+ * Kernels that can run a contraction step.  The staged kernels stage a tile of the input in LDS
+ * and multiply it on the matrix cores; the direct kernels load every lane's matrix-core operands
+ * straight into registers; FMA multiplies on the vector units.  AUTO is a fixed rule measured on
+ * MI355X.  Not every kernel takes every shape: a step keeps the AUTO rule where its choice does
+ * not apply.
+ */
+typedef enum {
+  JF_KV_AUTO = 0,
+  JF_KV_STAGED_256 = 1,
+  JF_KV_STAGED_512 = 2,
+  JF_KV_DIRECT_256 = 3,
+  JF_KV_DIRECT_512 = 4,
+  JF_KV_FMA = 5
+} jf_kernel_variant;
+
+/*
+ * jf_autotune -- the autotuner of the tile / kernel choice.  Runs the plan once on the caller's
+ * workspace and stream; on the first visit of each contraction step it times every kernel that
+ * can run the step (a warm-up launch, then reps launches between HIP events, on the step's own
+ * input and output buffers) and keeps the fastest for all later runs of this plan.  The
+ * workspace contents are undefined afterwards (no result is produced).  Choices are cached for
+ * the process by step shape (arithmetic, kS, kN, rows per tile, tile count, in place or not), so
+ * plans sharing shapes are tuned once.  Kernels sum in different orders, so a tuned plan may
+ * differ from an untuned one in the last bits; replays of a tuned plan are bitwise identical.
+ * reps <= 0 means 3.  Synchronises the stream.  Errors: JF_E_ARG, JF_E_OOM (workspace too
+ * small), JF_E_HIP.
+ */
+jf_status jf_autotune(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, int reps);
+
+/*
+ * jf_set_kernel_variant -- force one kernel (jf_kernel_variant) on every step it can run; the
+ * other steps keep the AUTO rule.  JF_KV_AUTO restores the rule everywhere (and so undoes
+ * jf_autotune).  For testing each kernel against the oracle.  Host only.  Errors: JF_E_ARG.
+ */
+jf_status jf_set_kernel_variant(jf_plan* plan, int variant);
 
 /* Definition 1: C1 and C2 are epsilon-equivalent iff F_J > 1 - eps (strict). Returns 1/0,
  * or -1 for a NULL result. */

@@ -131,9 +131,22 @@ extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len
       for (int s = cp.levels[lv].first; s < cp.levels[lv].last; ++s) {
         const Step& st = cp.steps[s];
         char line[256];
-        snprintf(line, sizeof(line), "%zu %d %zu %d %d %d %d %d %lld %s %s %s %d %.6g %.6g\n", c, s, lv, st.kS, st.kN, st.L,
+        snprintf(line, sizeof(line), "%zu %d %zu %d %d %d %d %d %lld %s %s %s %d %.6g %.6g", c, s, lv, st.kS, st.kN, st.L,
                  st.rA, st.rC, st.nTiles, pn[st.in_prec], pn[st.out_prec], cn[st.compute], st.nvar, st.flops, st.bytes);
         out += line;
+        // bit positions (in A, resp. C) of the tile rows, the summed legs and the new legs
+        auto bits = [](const std::vector<long long>& off, int n) {
+          std::string b;
+          for (int i = 0; i < n; ++i) {
+            const long long v = off[size_t(1) << i];
+            int pos = 0;
+            while ((1LL << pos) < v) ++pos;
+            b += (i ? "," : "") + std::to_string(pos);
+          }
+          return b.empty() ? std::string("-") : b;
+        };
+        out += " " + bits(st.offR_A, st.L) + " " + bits(st.offR_C, st.L) + " " + bits(st.offS_A, st.kS) + " " +
+               bits(st.offN_C, st.kN) + "\n";
       }
   }
   if (buf && len > 0) {

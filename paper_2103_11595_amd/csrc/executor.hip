@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cfloat>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -42,7 +44,11 @@ struct DevState {
   const void* graph_ws = nullptr;
   hipStream_t graph_stream = nullptr;
   std::vector<const jf_plan*> graph_plans;  // the batch the cached graph was captured for
+  std::vector<unsigned> graph_gens;         // and the kernel-choice generation of each plan
+  unsigned variant_gen = 0;                 // bumped whenever a step's kernel choice changes
 };
+
+std::atomic<unsigned> g_variant_gen{1};
 
 std::mutex g_upload_mu;
 std::map<const void*, const void*> g_last_upload;  // workspace -> plan that last uploaded into it
@@ -213,12 +219,65 @@ DevState& state_of(jf_plan* p) {
 
 struct Prof {
   std::vector<hipEvent_t> ev;  // pairs around every contraction-step launch
+  std::vector<jf_step_profile> rec;  // one per launch, ms filled in after the run
   double bytes = 0, flops = 0;
 };
 
+// Autotuning state of one run: which steps have been timed already.
+struct Tune {
+  int reps = 3;
+  std::vector<std::vector<char>> done;
+};
+
+// Process-wide cache of tuned choices, keyed by step shape.
+std::mutex g_tune_mu;
+std::map<std::vector<long long>, int> g_tune_cache;
+
+// Time every variant that can run this step (on its real input and output buffers) and keep the
+// fastest in the host descriptor.  In-place steps are re-applied to their own output: the data
+// is garbage afterwards, which is why tuning runs are never used for results.
+jf_status tune_step(StepDesc* hd, const StepDesc* dd, const void* A, void* C, const void* B, hipStream_t stream,
+                    int reps, bool inplace) {
+  const std::vector<long long> key = {hd->mode, hd->kS, hd->kN, hd->L, hd->nTiles, inplace ? 1 : 0};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      hd->variant = it->second;
+      return JF_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  int best = KV_AUTO;
+  float best_ms = FLT_MAX;
+  for (int v = KV_AUTO + 1; v < KV_COUNT; ++v) {
+    if (!variant_applies(*hd, v)) continue;
+    hd->variant = v;
+    JF_HIP(launch_step(dd, *hd, A, C, B, stream));  // warm-up
+    JF_HIP(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) JF_HIP(launch_step(dd, *hd, A, C, B, stream));
+    JF_HIP(hipEventRecord(e1, stream));
+    JF_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    JF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hd->variant = best;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = best;
+  return JF_OK;
+}
+
 // Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
 jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
-                          bool skip_lds = false) {
+                          bool skip_lds = false, Tune* tune = nullptr) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
   const DevLayout& L = S.lay;
@@ -266,6 +325,11 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
         const StepDesc* dd = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][si]);
         const StepDesc* hd = reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][si]]);
         const void* B = ws + L.step_b[c][si][var];
+        if (tune && !tune->done[c][si]) {
+          jf_status ts = tune_step(const_cast<StepDesc*>(hd), dd, cur, dst, B, stream, tune->reps, dst == cur);
+          if (ts != JF_OK) return ts;
+          tune->done[c][si] = 1;
+        }
         if (prof) {
           hipEvent_t a, b;
           JF_HIP(hipEventCreate(&a));
@@ -277,6 +341,16 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
           prof->ev.push_back(b);
           prof->bytes += st.bytes;
           prof->flops += st.flops;
+          jf_step_profile r = {};
+          r.flops = st.flops;
+          r.bytes = st.bytes;
+          r.kS = st.kS;
+          r.kN = st.kN;
+          r.L = st.L;
+          r.mode = hd->mode;
+          r.variant = resolve_variant(*hd);
+          r.component = int(c);
+          prof->rec.push_back(r);
         } else {
           JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
         }
@@ -429,6 +503,69 @@ extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void*
   return JF_OK;
 }
 
+extern "C" jf_status jf_profile_steps(jf_plan* p, void* ws, size_t ws_bytes, void* stream_v, jf_step_profile* out,
+                                      int cap, int* n_launches) {
+  if (!p || !n_launches || cap < 0 || (cap > 0 && !out)) {
+    set_error("jf_profile_steps: bad argument");
+    return JF_E_ARG;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  jf_status st = check_ws(p, ws, ws_bytes);
+  if (st != JF_OK) return st;
+  st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  Prof prof;
+  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream, &prof);
+  if (st != JF_OK) return st;
+  JF_HIP(hipStreamSynchronize(stream));
+  const int n = int(prof.rec.size());
+  for (int i = 0; i < n; ++i) {
+    float ms = 0;
+    JF_HIP(hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]));
+    prof.rec[i].ms = ms;
+    if (i < cap) out[i] = prof.rec[i];
+  }
+  for (auto ev : prof.ev) hipEventDestroy(ev);
+  *n_launches = n;
+  return JF_OK;
+}
+
+extern "C" jf_status jf_autotune(jf_plan* p, void* ws, size_t ws_bytes, void* stream_v, int reps) {
+  if (!p) {
+    set_error("jf_autotune: bad argument");
+    return JF_E_ARG;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  jf_status st = check_ws(p, ws, ws_bytes);
+  if (st != JF_OK) return st;
+  st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  Tune tune;
+  tune.reps = reps > 0 ? reps : 3;
+  tune.done.resize(p->prog.comps.size());
+  for (size_t c = 0; c < p->prog.comps.size(); ++c) tune.done[c].assign(p->prog.comps[c].steps.size(), 0);
+  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream, nullptr, false, &tune);
+  if (st != JF_OK) return st;
+  JF_HIP(hipStreamSynchronize(stream));
+  state_of(p).variant_gen = g_variant_gen.fetch_add(1);
+  return JF_OK;
+}
+
+extern "C" jf_status jf_set_kernel_variant(jf_plan* p, int variant) {
+  if (!p || variant < KV_AUTO || variant >= KV_COUNT) {
+    set_error("jf_set_kernel_variant: bad argument");
+    return JF_E_ARG;
+  }
+  DevState& S = state_of(p);
+  for (size_t c = 0; c < p->prog.comps.size(); ++c)
+    for (size_t s = 0; s < p->prog.comps[c].steps.size(); ++s) {
+      StepDesc* hd = reinterpret_cast<StepDesc*>(&S.host_image[S.lay.step_desc[c][s]]);
+      hd->variant = variant_applies(*hd, variant) ? variant : KV_AUTO;
+    }
+  S.variant_gen = g_variant_gen.fetch_add(1);
+  return JF_OK;
+}
+
 extern "C" jf_status jf_fidelity_alg2(jf_plan* p, void* ws, size_t ws_bytes, void* stream, jf_result* out) {
   if (!p || !out || p->prog.opt.alg != 2) {
     set_error("jf_fidelity_alg2: NULL argument or not an Algorithm II plan");
@@ -510,7 +647,10 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   DevState& S0 = state_of(plans[0 < n ? 0 : 0]);
   const bool use_graph = n > 0 && stream != nullptr;
   std::vector<const jf_plan*> key(plans, plans + n);
-  if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream || S0.graph_plans != key)) {
+  std::vector<unsigned> gens(n);
+  for (int i = 0; i < n; ++i) gens[i] = state_of(plans[i]).variant_gen;
+  if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream || S0.graph_plans != key ||
+                    S0.graph_gens != gens)) {
     if (S0.graph) {
       hipGraphExecDestroy(S0.graph);
       S0.graph = nullptr;
@@ -533,6 +673,7 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     S0.graph_ws = ws;
     S0.graph_stream = stream;
     S0.graph_plans = key;
+    S0.graph_gens = gens;
   }
   JF_HIP(hipEventRecord(e0, stream));
   if (use_graph) {

@@ -23,9 +23,27 @@ struct StepDesc {
   int hiC[DMAXHI];
   int nHi, kS, kN, L;
   long long nTiles;
-  int mode;       // kernel variant chosen by the executor (see KernelMode)
-  int pad[3];
+  int mode;       // arithmetic of the step (see KernelMode)
+  int variant;    // kernel used for it (see KernelVariant); read on the host only
+  int pad[2];
 };
+
+// Kernels that can run a step.  KV_AUTO applies the fixed rule of launch_step; the others are
+// used where the step's shape allows them (launch_step falls back to KV_AUTO elsewhere).
+enum KernelVariant {
+  KV_AUTO = 0,
+  KV_STAGED_256 = 1,  // MFMA, A tile staged through LDS, 256 threads
+  KV_STAGED_512 = 2,  // the same, 512 threads
+  KV_DIRECT_256 = 3,  // MFMA, A operands loaded straight into registers, 256 threads
+  KV_DIRECT_512 = 4,  // the same, 512 threads
+  KV_FMA = 5,         // plain FMA on LDS tiles
+  KV_COUNT = 6,
+};
+
+// Whether a variant can run the step described by h (mode, kS, kN, L).
+bool variant_applies(const StepDesc& h, int variant);
+// The variant launch_step actually uses for h (KV_AUTO and inapplicable choices resolved).
+int resolve_variant(const StepDesc& h);
 
 enum KernelMode {
   KM_F64 = 0,       // double2 -> double2, FP64

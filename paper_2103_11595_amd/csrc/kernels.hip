@@ -711,14 +711,18 @@ static unsigned grid_for(long long nTiles) {
   return unsigned(nTiles < cap ? nTiles : cap);
 }
 
-// MFMA step launch with the output block count (Nn / 8 blocks of 16 MFMA rows) fixed at compile time.
+// LDS-staged MFMA launch with the output block count (Nn / 8 blocks of 16 MFMA rows, at least
+// one) fixed at compile time.
 template <typename T, bool TWO_TERM, int NT>
-void launch_mfma(unsigned grid, size_t sm, hipStream_t stream, const StepDesc* d_desc, int Nn, const void* A,
-                 void* C, const void* B) {
+void launch_staged(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                   const void* B) {
   using C2 = typename Mfma<T>::c2;
   const C2* a = (const C2*)A;
   const C2* b = (const C2*)B;
   C2* c = (C2*)C;
+  const int K = 1 << h.kS, Nn = 1 << h.kN, R = 1 << h.L;
+  const unsigned grid = grid_for(h.nTiles);
+  const size_t sm = size_t((TWO_TERM ? 8 : 4) * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(T);
   switch (Nn) {
     case 1: case 2: case 4: case 8: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     case 16: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
@@ -727,86 +731,128 @@ void launch_mfma(unsigned grid, size_t sm, hipStream_t stream, const StepDesc* d
   }
 }
 
-// Register-direct launch: (MB, KQ) fixed at compile time.  Returns false when no instance covers
-// the shape (the caller then uses the LDS-staged kernel).
+// Register-direct launch with (MB, KQ) fixed at compile time.
 template <typename T, bool TWO_TERM, int NT, int MB>
-bool launch_rd_mb(long long units, hipStream_t stream, const StepDesc* d_desc, int K, const void* A, void* C,
-                  const void* B) {
+void launch_direct_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                      const void* B) {
   using C2 = typename Mfma<T>::c2;
   const C2* a = (const C2*)A;
   const C2* b = (const C2*)B;
   C2* c = (C2*)C;
-  const int KQ = (K + 3) / 4;
+  const int KQ = ((1 << h.kS) + 3) / 4;
+  const long long units = h.nTiles << (h.L - 4);
   const long long wgs = (units + NT / 64 - 1) / (NT / 64);
   const unsigned grid = unsigned(wgs < 2048 ? wgs : 2048);
   const size_t sm = size_t((TWO_TERM ? 2 : 1) * 2 * KQ * 4 * 16 * MB) * sizeof(T);
   switch (KQ) {
-    case 1: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
-    case 2: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
-    case 4: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
-    case 8: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); return true;
-    default: return false;
+    case 1: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 2: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 4: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
   }
 }
 
-// The register-direct kernel is used where it measured faster than the LDS-staged one: FP64 up
-// to Nn = 32 and FP32 for Nn <= 8 (at larger Nn the FP32 products are MFMA-bound and the staged
-// kernel's shared A tile wins).  Needs at least 16 tile rows and K <= 32.
 template <typename T, bool TWO_TERM, int NT>
-bool launch_rd(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
-               const void* B) {
-  const int K = 1 << h.kS, Nn = 1 << h.kN;
-  if (h.L < 4 || K > 32) return false;
-  const long long units = h.nTiles << (h.L - 4);
-  if (Nn <= 8) return launch_rd_mb<T, TWO_TERM, NT, 1>(units, stream, d_desc, K, A, C, B);
-  if constexpr (sizeof(T) == 8) {
-    if (Nn == 16) return launch_rd_mb<T, TWO_TERM, NT, 2>(units, stream, d_desc, K, A, C, B);
-    if (Nn == 32) return launch_rd_mb<T, TWO_TERM, NT, 4>(units, stream, d_desc, K, A, C, B);
+void launch_direct(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                   const void* B) {
+  const int Nn = 1 << h.kN;
+  if (Nn <= 8) launch_direct_mb<T, TWO_TERM, NT, 1>(h, stream, d_desc, A, C, B);
+  else if (Nn == 16) launch_direct_mb<T, TWO_TERM, NT, 2>(h, stream, d_desc, A, C, B);
+  else launch_direct_mb<T, TWO_TERM, NT, 4>(h, stream, d_desc, A, C, B);
+}
+
+static bool staged_ok(const StepDesc& h) {
+  const int K = 1 << h.kS, R = 1 << h.L;
+  return R >= 16 && K >= 2 && K * R <= 4096;
+}
+static bool direct_ok(const StepDesc& h) { return h.L >= 4 && h.kS <= 5 && h.kN <= 5; }
+
+bool variant_applies(const StepDesc& h, int v) {
+  switch (h.mode) {
+    case KM_F64:
+    case KM_F32:
+    case KM_F32X2:
+      if (v == KV_AUTO || v == KV_FMA) return true;
+      if (v == KV_STAGED_256 || v == KV_STAGED_512) return staged_ok(h);
+      if (v == KV_DIRECT_256 || v == KV_DIRECT_512) return direct_ok(h);
+      return false;
+    case KM_BF16X3:
+      return v == KV_AUTO || v == KV_FMA || (v == KV_STAGED_256 && (1 << h.kN) >= 8 && h.L >= 4 && (1 << (h.kS + h.L)) <= 4096);
+    case KM_F32_TO_F64:
+      return v == KV_AUTO || v == KV_FMA;
+    default:
+      return false;
   }
-  return false;
+}
+
+// The fixed rule (KV_AUTO), from measurements on MI355X: register-direct for FP64 up to Nn = 32
+// and for FP32 with Nn <= 8 (at larger Nn the FP32 products are MFMA-bound and the staged
+// kernel's shared A tile wins); staged MFMA otherwise; FMA for shapes no MFMA kernel takes.
+static int auto_variant(const StepDesc& h) {
+  const int Nn = 1 << h.kN;
+  switch (h.mode) {
+    case KM_F64:
+      if (direct_ok(h) && Nn <= 32) return KV_DIRECT_256;
+      return staged_ok(h) ? KV_STAGED_512 : KV_FMA;
+    case KM_F32:
+    case KM_F32X2:
+      if (direct_ok(h) && Nn <= 8) return KV_DIRECT_512;
+      return staged_ok(h) ? KV_STAGED_256 : KV_FMA;
+    case KM_BF16X3:
+      return variant_applies(h, KV_STAGED_256) ? KV_STAGED_256 : KV_FMA;
+    default:
+      return KV_FMA;
+  }
+}
+
+int resolve_variant(const StepDesc& h) {
+  return (h.variant != KV_AUTO && variant_applies(h, h.variant)) ? h.variant : auto_variant(h);
+}
+
+template <typename T, bool TWO_TERM>
+static void launch_mfma_variant(int v, const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A,
+                                void* C, const void* B) {
+  switch (v) {
+    case KV_STAGED_256: launch_staged<T, TWO_TERM, 256>(h, stream, d_desc, A, C, B); break;
+    case KV_STAGED_512: launch_staged<T, TWO_TERM, 512>(h, stream, d_desc, A, C, B); break;
+    case KV_DIRECT_256: launch_direct<T, TWO_TERM, 256>(h, stream, d_desc, A, C, B); break;
+    default: launch_direct<T, TWO_TERM, 512>(h, stream, d_desc, A, C, B); break;
+  }
 }
 
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A, void* C, const void* B,
                        hipStream_t stream) {
   const int K = 1 << h.kS, Nn = 1 << h.kN, R = 1 << h.L;
   const unsigned grid = grid_for(h.nTiles);
+  const int v = resolve_variant(h);
   switch (h.mode) {
-    case KM_F64: {
-      if (launch_rd<double, false, 256>(h, stream, d_desc, A, C, B)) break;
-      if (R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(double);
-        launch_mfma<double, false, 512>(grid, sm, stream, d_desc, Nn, A, C, B);
-        break;
+    case KM_F64:
+      if (v != KV_FMA) {
+        launch_mfma_variant<double, false>(v, h, stream, d_desc, A, C, B);
+      } else {
+        size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
+        hipLaunchKernelGGL((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
+                           (const double2*)A, (double2*)C, (const double2*)B);
       }
-      size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
-      hipLaunchKernelGGL((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
-                         (const double2*)A, (double2*)C, (const double2*)B);
       break;
-    }
-    case KM_F32: {
-      if (launch_rd<float, false, 512>(h, stream, d_desc, A, C, B)) break;
-      if (R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(4 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
-        launch_mfma<float, false, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
-        break;
+    case KM_F32:
+      if (v != KV_FMA) {
+        launch_mfma_variant<float, false>(v, h, stream, d_desc, A, C, B);
+      } else {
+        size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
+        hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
+                           (const float2*)A, (float2*)C, (const float2*)B);
       }
-      size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
-      hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
-                         (const float2*)A, (float2*)C, (const float2*)B);
       break;
-    }
-    case KM_F32X2: {
-      if (launch_rd<float, true, 512>(h, stream, d_desc, A, C, B)) break;
-      if (R >= 16 && K >= 2 && K * R <= 4096) {
-        size_t sm = size_t(8 * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(float);
-        launch_mfma<float, true, 256>(grid, sm, stream, d_desc, Nn, A, C, B);
-        break;
+    case KM_F32X2:
+      if (v != KV_FMA) {
+        launch_mfma_variant<float, true>(v, h, stream, d_desc, A, C, B);
+      } else {
+        size_t sm = size_t(2 * K * Nn + K * R) * sizeof(float2);
+        hipLaunchKernelGGL(k_absorb_f32x2, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+                           (const float2*)B);
       }
-      size_t sm = size_t(2 * K * Nn + K * R) * sizeof(float2);
-      hipLaunchKernelGGL(k_absorb_f32x2, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
-                         (const float2*)B);
       break;
-    }
     case KM_F32_TO_F64: {
       size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
       hipLaunchKernelGGL((k_absorb<float2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
@@ -814,7 +860,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       break;
     }
     case KM_BF16X3: {
-      if (Nn >= 8 && R >= 16 && K * R <= 4096) {
+      if (v == KV_STAGED_256) {
         const int KP = ((2 * K + 31) & ~31) + 8;
         size_t sm = size_t(4 * Nn + 2 * R) * KP * sizeof(unsigned short);
         hipLaunchKernelGGL(k_absorb_bf16x3_mfma<256>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,

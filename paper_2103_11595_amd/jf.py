@@ -79,10 +79,23 @@ class jf_profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class jf_step_profile(C.Structure):
+    _fields_ = [("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double), ("kS", C.c_int),
+                ("kN", C.c_int), ("L", C.c_int), ("mode", C.c_int), ("variant", C.c_int), ("component", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# jf_kernel_variant
+KV_AUTO, KV_STAGED_256, KV_STAGED_512, KV_DIRECT_256, KV_DIRECT_512, KV_FMA = range(6)
+KERNEL_VARIANTS = {"auto": KV_AUTO, "staged256": KV_STAGED_256, "staged512": KV_STAGED_512,
+                   "direct256": KV_DIRECT_256, "direct512": KV_DIRECT_512, "fma": KV_FMA}
+
 EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_stats_get",
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
-           "jf_profile_run", "jf_plan_describe"]
+           "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant"]
 
 _lib = None
 
@@ -119,6 +132,9 @@ def lib():
     L.jf_emulate_plan.argtypes = [vp, C.POINTER(C.c_double), C.c_longlong]
     L.jf_profile_run.argtypes = [vp, vp, sz, vp, C.POINTER(jf_profile)]
     L.jf_plan_describe.argtypes = [vp, C.c_char_p, C.c_longlong]
+    L.jf_profile_steps.argtypes = [vp, vp, sz, vp, C.POINTER(jf_step_profile), C.c_int, C.POINTER(C.c_int)]
+    L.jf_autotune.argtypes = [vp, vp, sz, vp, C.c_int]
+    L.jf_set_kernel_variant.argtypes = [vp, C.c_int]
     for name in EXPORTS:
         if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
@@ -177,13 +193,17 @@ class Plan:
         buf = C.create_string_buffer(int(n))
         L.jf_plan_describe(self.ptr, buf, n)
         keys = ["comp", "step", "level", "kS", "kN", "L", "rA", "rC", "tiles", "in_prec", "out_prec", "compute",
-                "nvar", "flops", "bytes"]
-        rows = []
-        for line in buf.value.decode().splitlines():
-            vals = line.split()
-            rows.append({k: (v if k in ("in_prec", "out_prec", "compute") else float(v) if k in ("flops", "bytes") else int(v))
-                         for k, v in zip(keys, vals)})
-        return rows
+                "nvar", "flops", "bytes", "rowsA", "rowsC", "sA", "nC"]
+
+        def conv(k, v):
+            if k in ("in_prec", "out_prec", "compute"):
+                return v
+            if k in ("flops", "bytes"):
+                return float(v)
+            if k in ("rowsA", "rowsC", "sA", "nC"):
+                return [] if v == "-" else [int(x) for x in v.split(",")]
+            return int(v)
+        return [{k: conv(k, v) for k, v in zip(keys, line.split())} for line in buf.value.decode().splitlines()]
 
     def emulate(self):
         """Host emulation of the lowered step program (validation aid): complex terms for Alg I,
@@ -328,6 +348,32 @@ def jf_profile_run(plan: Plan, ws=None, stream=None) -> dict:
     r = jf_profile()
     _check(lib().jf_profile_run(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
     return r.as_dict()
+
+
+def jf_profile_steps(plan: Plan, ws=None, stream=None) -> list:
+    """Per-launch durations (ms) with flops, bytes, shape, arithmetic and kernel of each step."""
+    if ws is None:
+        ws = workspace(plan.info()["workspace_bytes"])
+    n = C.c_int(0)
+    _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), None, 0,
+                                  C.byref(n)))
+    buf = (jf_step_profile * max(1, n.value))()
+    _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), buf,
+                                  n.value, C.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def jf_autotune(plan: Plan, ws=None, stream=None, reps: int = 3) -> None:
+    """Time every kernel that can run each step and keep the fastest (the workspace is clobbered)."""
+    if ws is None:
+        ws = workspace(plan.info()["workspace_bytes"])
+    _check(lib().jf_autotune(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), int(reps)))
+
+
+def jf_set_kernel_variant(plan: Plan, variant) -> None:
+    """Force one kernel (name from KERNEL_VARIANTS or its number) on every step it can run."""
+    v = KERNEL_VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    _check(lib().jf_set_kernel_variant(plan.ptr, v))
 
 
 def jf_is_equivalent(result: dict, eps: float) -> bool:

@@ -255,3 +255,92 @@ def test_batch_of_small_circuits_against_oracle():
     for i, (x, r) in enumerate(zip(insts, out)):
         want = dense.fidelity_alg1(x)["fj"]
         assert abs(r["fj"] - want) <= 1e-12, (i, r["fj"], want)
+
+
+# --- kernel variants and the autotuner ------------------------------------------------------
+
+def _variant_applies(r, v):
+    """Whether a forced kernel runs a launch with this profile record's shape and arithmetic
+    (mode 0 FP64, 1 FP32, 2 FP32 in / FP64 out, 3 3xBF16, 4 FP32 two-term): the launcher's rule,
+    restated."""
+    K, R = 1 << r["kS"], 1 << r["L"]
+    if r["mode"] == 2:
+        return v == jf.KV_FMA
+    if r["mode"] == 3:
+        return v == jf.KV_FMA or (v == jf.KV_STAGED_256 and r["kN"] >= 3 and r["L"] >= 4 and K * R <= 4096)
+    if v == jf.KV_FMA:
+        return True
+    if v in (jf.KV_STAGED_256, jf.KV_STAGED_512):
+        return R >= 16 and K >= 2 and K * R <= 4096
+    return r["L"] >= 4 and r["kS"] <= 5 and r["kN"] <= 5
+
+
+def _variant_instance(seed):
+    # n=9, 250 gates, 3 sites: wide enough (intermediates up to 2^20) that most steps are
+    # matrix-core shapes, small enough for the dense oracle
+    return gen.random_circuit(9, 250, 3, 1e-3, 0.05, 500 + seed)
+
+
+@pytest.mark.parametrize("seed", [2, 5, 17])
+@pytest.mark.parametrize("dtype", ["c128", "c64", "bf16x3"])
+def test_every_kernel_variant_against_oracle(seed, dtype):
+    inst = _variant_instance(seed)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    p = jf.plan(inst, 1, dtype)
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    variants = ["auto", "staged256", "fma"] if dtype == "bf16x3" else list(jf.KERNEL_VARIANTS)
+    for name in variants:
+        v = jf.KERNEL_VARIANTS[name]
+        say("variant", name, "seed", seed, dtype)
+        jf.jf_set_kernel_variant(p, v)
+        got = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        assert abs(got["fj"] - ref["fj"]) <= TOL[dtype], (name, got["fj"] - ref["fj"])
+        if dtype == "c128":
+            assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12, name
+        prof = jf.jf_profile_steps(p, ws)
+        for r in prof:
+            assert r["variant"] != jf.KV_AUTO
+            if v != jf.KV_AUTO and _variant_applies(r, v):
+                assert r["variant"] == v, (name, r)
+        if v != jf.KV_AUTO:
+            assert sum(_variant_applies(r, v) for r in prof) >= 3, name  # the kernel really ran
+    jf.jf_set_kernel_variant(p, "auto")
+
+
+def test_autotune_parity_and_bitwise_replay():
+    inst = _variant_instance(5)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    for dtype in ("c128", "c64"):
+        p = jf.plan(inst, 1, dtype)
+        ws = jf.workspace(p.info()["workspace_bytes"])
+        before = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        jf.jf_autotune(p, ws, reps=2)
+        a = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        b = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        assert a["fj"] == b["fj"] and np.array_equal(a["terms"], b["terms"])
+        assert abs(a["fj"] - ref["fj"]) <= TOL[dtype]
+        if dtype == "c128":
+            assert np.max(np.abs(a["terms"] - _terms(ref))) <= 1e-12
+        jf.jf_set_kernel_variant(p, "auto")  # back to the fixed rule: the untuned result again
+        c = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        assert c["fj"] == before["fj"] and np.array_equal(c["terms"], before["terms"])
+
+
+def test_autotuned_full_size_workload():
+    inst = gen.config2()
+    p128 = jf.plan(inst, 1, "c128")
+    ws = jf.workspace(p128.info()["workspace_bytes"])
+    f128 = jf.jf_fidelity_alg1(p128, ws)["fj"]
+    del ws
+    p = jf.plan(inst, 1, "c64")
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    jf.jf_autotune(p, ws)
+    a = jf.jf_fidelity_alg1(p, ws)
+    b = jf.jf_fidelity_alg1(p, ws)
+    assert a["fj"] == b["fj"]
+    assert abs(a["fj"] - f128) <= TOL["c64"]
+    prof = jf.jf_profile_steps(p, ws)
+    total = jf.jf_profile_run(p, ws)
+    assert len(prof) == total["launches"]
+    assert abs(sum(r["flops"] for r in prof) - total["flops"]) <= 1e-9 * total["flops"]
+    assert 0.5 * total["kernel_ms"] <= sum(r["ms"] for r in prof) <= 2.0 * total["kernel_ms"]
