@@ -229,9 +229,12 @@ jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* s
 /*
  * Kernels that can run a contraction step.  The staged kernels stage a tile of the input in LDS
  * and multiply it on the matrix cores; the direct kernels load every lane's matrix-core operands
- * straight into registers; FMA multiplies on the vector units.  AUTO is a fixed rule measured on
- * MI355X.  Not every kernel takes every shape: a step keeps the AUTO rule where its choice does
- * not apply.
+ * straight into registers; FMA multiplies on the vector units; the Gauss kernels are direct
+ * kernels that form each complex product from three real ones (Re.Re, Im.Im and (Re+Im).(Re+Im)),
+ * a quarter fewer matrix-core products, with the imaginary part's rounding error relative to the
+ * largest of the three (not used on noise-carrying FP32 blocks).  AUTO is a fixed rule measured
+ * on MI355X.  Not every kernel takes every shape: a step keeps the AUTO rule where its choice
+ * does not apply.
  */
 typedef enum {
   JF_KV_AUTO = 0,
@@ -239,7 +242,9 @@ typedef enum {
   JF_KV_STAGED_512 = 2,
   JF_KV_DIRECT_256 = 3,
   JF_KV_DIRECT_512 = 4,
-  JF_KV_FMA = 5
+  JF_KV_FMA = 5,
+  JF_KV_GAUSS_256 = 6,
+  JF_KV_GAUSS_512 = 7
 } jf_kernel_variant;
 
 /*

@@ -454,6 +454,103 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restric
 }
 
 
+// Gauss (3M) form of the register-direct kernel: three real products per complex one,
+//   T1 = sum Re B Re A,  T2 = sum Im B Im A,  T3 = sum (Re B + Im B)(Re A + Im A),
+//   Re C = T1 - T2,  Im C = T3 - T1 - T2,
+// a quarter fewer matrix-core products than the real embedding, at the price of a rounding
+// error relative to the larger of |T1|, |T2|, |T3| for Im C.  MFMA k runs over s directly: lane
+// group g of k-step t supplies s = 4 t + g, and the 16 MFMA rows of block mb are n = 16 mb + 0..15.
+// The operator sits in LDS as [t][lane][x][mb] (x = Re, Im, Re + Im), so that every lane reads
+// its 3 MB values of a k-step from consecutive addresses.  Units, prefetch and in-place safety as
+// in k_absorb_mfma_rd.
+template <typename T, int NT, int MB, int KQ>
+__global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __restrict__ d,
+                                                          const typename Mfma<T>::c2* A,
+                                                          typename Mfma<T>::c2* C,
+                                                          const typename Mfma<T>::c2* __restrict__ B) {
+  using M = Mfma<T>;
+  using C2 = typename M::c2;
+  constexpr int NW = NT / 64, W = 3 * MB;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int rbits = L - 4;
+  const long long nUnits = d->nTiles << rbits;
+  load_tables(d, tb, K, Nn, R, nHi);
+  T* sB = reinterpret_cast<T*>(smem);
+  for (int idx = threadIdx.x; idx < KQ * 64 * W; idx += NT) {
+    const int t = idx / (64 * W), rem = idx - t * 64 * W;
+    const int ln = rem / W, e = rem - ln * W;
+    const int x = e / MB, mb = e - x * MB;
+    const int s = 4 * t + (ln >> 4), n = mb * 16 + (ln & 15);
+    T v = 0;
+    if (s < K && n < Nn) {
+      const C2 bv = B[s * Nn + n];
+      v = x == 0 ? bv.x : x == 1 ? bv.y : bv.x + bv.y;
+    }
+    sB[idx] = v;
+  }
+  __syncthreads();  // offset tables and operator visible to every wave
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const long long wstride = (long long)gridDim.x * NW;
+  auto base = [&](long long t, const int* hi) {
+    long long b = 0;
+    for (int q = 0; q < nHi; ++q)
+      if ((t >> q) & 1) b |= 1LL << hi[q];
+    return b;
+  };
+  auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
+  C2 nxt[KQ];
+  auto fetch = [&](long long v) {
+    const long long bA = base(v >> rbits, tb.hiA) + tb.offRA[row_of_unit(v)];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) {
+      const int s = 4 * u + g;
+      nxt[u] = s < K ? A[bA + tb.offS[s]] : C2{0, 0};
+    }
+  };
+  long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
+  if (v < nUnits) fetch(v);
+  for (; v < nUnits; v += wstride) {
+    C2 cur[KQ];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) cur[u] = nxt[u];
+    if (v + wstride < nUnits) fetch(v + wstride);
+    typename M::acc_t acc[3][MB];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[x][mb] = typename M::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+      const T ar = cur[t].x, ai = cur[t].y, as = ar + ai;
+      const T* bp = sB + (t * 64 + lane) * W;
+      T bv[W];
+#pragma unroll
+      for (int e = 0; e < W; ++e) bv[e] = bp[e];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        acc[0][mb] = M::op(bv[mb], ar, acc[0][mb]);
+        acc[1][mb] = M::op(bv[MB + mb], ai, acc[1][mb]);
+        acc[2][mb] = M::op(bv[2 * MB + mb], as, acc[2][mb]);
+      }
+    }
+    const long long bC = base(v >> rbits, tb.hiC) + tb.offRC[row_of_unit(v)];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = mb * 16 + M::row_of(g, r);  // MFMA row held in accumulator register r
+        C2 o;
+        o.x = acc[0][mb][r] - acc[1][mb][r];
+        o.y = acc[2][mb][r] - acc[0][mb][r] - acc[1][mb][r];
+        if (n < Nn) C[bC + tb.offN[n]] = o;
+      }
+    }
+  }
+}
+
 // 3xBF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Every FP32 operand x is split
 // into hi = bf16(x) and lo = bf16(x - hi); a product a*b is hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b)
 // with FP32 accumulation (the cross terms in their own accumulator, added at the end).
@@ -761,6 +858,33 @@ void launch_direct(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc
   else launch_direct_mb<T, TWO_TERM, NT, 4>(h, stream, d_desc, A, C, B);
 }
 
+template <typename T, int NT, int MB>
+void launch_gauss_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                     const void* B) {
+  using C2 = typename Mfma<T>::c2;
+  const C2* a = (const C2*)A;
+  const C2* b = (const C2*)B;
+  C2* c = (C2*)C;
+  const int KQ = ((1 << h.kS) + 3) / 4;
+  const long long units = h.nTiles << (h.L - 4);
+  const long long wgs = (units + NT / 64 - 1) / (NT / 64);
+  const unsigned grid = unsigned(wgs < 2048 ? wgs : 2048);
+  const size_t sm = size_t(KQ * 64 * 3 * MB) * sizeof(T);
+  switch (KQ) {
+    case 1: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 2: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 4: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+  }
+}
+
+template <typename T, int NT>
+void launch_gauss(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                  const void* B) {
+  if (h.kN <= 4) launch_gauss_mb<T, NT, 1>(h, stream, d_desc, A, C, B);
+  else launch_gauss_mb<T, NT, 2>(h, stream, d_desc, A, C, B);
+}
+
 static bool staged_ok(const StepDesc& h) {
   const int K = 1 << h.kS, R = 1 << h.L;
   return R >= 16 && K >= 2 && K * R <= 4096;
@@ -775,6 +899,7 @@ bool variant_applies(const StepDesc& h, int v) {
       if (v == KV_AUTO || v == KV_FMA) return true;
       if (v == KV_STAGED_256 || v == KV_STAGED_512) return staged_ok(h);
       if (v == KV_DIRECT_256 || v == KV_DIRECT_512) return direct_ok(h);
+      if (v == KV_GAUSS_256 || v == KV_GAUSS_512) return h.mode != KM_F32X2 && direct_ok(h);
       return false;
     case KM_BF16X3:
       return v == KV_AUTO || v == KV_FMA || (v == KV_STAGED_256 && (1 << h.kN) >= 8 && h.L >= 4 && (1 << (h.kS + h.L)) <= 4096);
@@ -812,6 +937,10 @@ int resolve_variant(const StepDesc& h) {
 template <typename T, bool TWO_TERM>
 static void launch_mfma_variant(int v, const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A,
                                 void* C, const void* B) {
+  if constexpr (!TWO_TERM) {
+    if (v == KV_GAUSS_256) return launch_gauss<T, 256>(h, stream, d_desc, A, C, B);
+    if (v == KV_GAUSS_512) return launch_gauss<T, 512>(h, stream, d_desc, A, C, B);
+  }
   switch (v) {
     case KV_STAGED_256: launch_staged<T, TWO_TERM, 256>(h, stream, d_desc, A, C, B); break;
     case KV_STAGED_512: launch_staged<T, TWO_TERM, 512>(h, stream, d_desc, A, C, B); break;

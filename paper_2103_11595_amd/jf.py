@@ -88,9 +88,10 @@ class jf_step_profile(C.Structure):
 
 
 # jf_kernel_variant
-KV_AUTO, KV_STAGED_256, KV_STAGED_512, KV_DIRECT_256, KV_DIRECT_512, KV_FMA = range(6)
+KV_AUTO, KV_STAGED_256, KV_STAGED_512, KV_DIRECT_256, KV_DIRECT_512, KV_FMA, KV_GAUSS_256, KV_GAUSS_512 = range(8)
 KERNEL_VARIANTS = {"auto": KV_AUTO, "staged256": KV_STAGED_256, "staged512": KV_STAGED_512,
-                   "direct256": KV_DIRECT_256, "direct512": KV_DIRECT_512, "fma": KV_FMA}
+                   "direct256": KV_DIRECT_256, "direct512": KV_DIRECT_512, "fma": KV_FMA,
+                   "gauss256": KV_GAUSS_256, "gauss512": KV_GAUSS_512}
 
 EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_stats_get",
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
