@@ -874,7 +874,8 @@ void launch_gauss_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_de
     case 1: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     case 2: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
     case 4: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    default: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 8: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 16>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
   }
 }
 
@@ -882,7 +883,8 @@ template <typename T, int NT>
 void launch_gauss(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
                   const void* B) {
   if (h.kN <= 4) launch_gauss_mb<T, NT, 1>(h, stream, d_desc, A, C, B);
-  else launch_gauss_mb<T, NT, 2>(h, stream, d_desc, A, C, B);
+  else if (h.kN == 5) launch_gauss_mb<T, NT, 2>(h, stream, d_desc, A, C, B);
+  else launch_gauss_mb<T, NT, 4>(h, stream, d_desc, A, C, B);
 }
 
 static bool staged_ok(const StepDesc& h) {
@@ -890,6 +892,10 @@ static bool staged_ok(const StepDesc& h) {
   return R >= 16 && K >= 2 && K * R <= 4096;
 }
 static bool direct_ok(const StepDesc& h) { return h.L >= 4 && h.kS <= 5 && h.kN <= 5; }
+// (kS + kN <= 10: the larger blocks would spill registers)
+static bool gauss_ok(const StepDesc& h) {
+  return h.L >= 4 && h.kS <= 6 && h.kN <= 6 && h.kS + h.kN <= 10 && h.mode != KM_F32X2;
+}
 
 bool variant_applies(const StepDesc& h, int v) {
   switch (h.mode) {
@@ -899,7 +905,7 @@ bool variant_applies(const StepDesc& h, int v) {
       if (v == KV_AUTO || v == KV_FMA) return true;
       if (v == KV_STAGED_256 || v == KV_STAGED_512) return staged_ok(h);
       if (v == KV_DIRECT_256 || v == KV_DIRECT_512) return direct_ok(h);
-      if (v == KV_GAUSS_256 || v == KV_GAUSS_512) return h.mode != KM_F32X2 && direct_ok(h);
+      if (v == KV_GAUSS_256 || v == KV_GAUSS_512) return gauss_ok(h);
       return false;
     case KM_BF16X3:
       return v == KV_AUTO || v == KV_FMA || (v == KV_STAGED_256 && (1 << h.kN) >= 8 && h.L >= 4 && (1 << (h.kS + h.L)) <= 4096);
@@ -911,8 +917,9 @@ bool variant_applies(const StepDesc& h, int v) {
 }
 
 // The fixed rule (KV_AUTO), from measurements on MI355X: register-direct for FP64 up to Nn = 32
-// and for FP32 with Nn <= 8 (at larger Nn the FP32 products are MFMA-bound and the staged
-// kernel's shared A tile wins); staged MFMA otherwise; FMA for shapes no MFMA kernel takes.
+// and for FP32 with Nn <= 8; for FP32 blocks with K * Nn >= 512 (matrix-core bound at
+// 4 products per complex one) the Gauss form; staged MFMA otherwise; FMA for shapes no MFMA
+// kernel takes.
 static int auto_variant(const StepDesc& h) {
   const int Nn = 1 << h.kN;
   switch (h.mode) {
@@ -922,6 +929,7 @@ static int auto_variant(const StepDesc& h) {
     case KM_F32:
     case KM_F32X2:
       if (direct_ok(h) && Nn <= 8) return KV_DIRECT_512;
+      if (h.kS + h.kN >= 9 && gauss_ok(h)) return KV_GAUSS_512;
       return staged_ok(h) ? KV_STAGED_256 : KV_FMA;
     case KM_BF16X3:
       return variant_applies(h, KV_STAGED_256) ? KV_STAGED_256 : KV_FMA;

@@ -270,8 +270,8 @@ def _variant_applies(r, v):
         return v == jf.KV_FMA or (v == jf.KV_STAGED_256 and r["kN"] >= 3 and r["L"] >= 4 and K * R <= 4096)
     if v == jf.KV_FMA:
         return True
-    if v in (jf.KV_GAUSS_256, jf.KV_GAUSS_512) and r["mode"] == 4:
-        return False
+    if v in (jf.KV_GAUSS_256, jf.KV_GAUSS_512):
+        return r["mode"] != 4 and r["L"] >= 4 and r["kS"] <= 6 and r["kN"] <= 6 and r["kS"] + r["kN"] <= 10
     if v in (jf.KV_STAGED_256, jf.KV_STAGED_512):
         return R >= 16 and K >= 2 and K * R <= 4096
     return r["L"] >= 4 and r["kS"] <= 5 and r["kN"] <= 5
