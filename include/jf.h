@@ -195,10 +195,10 @@ jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* dev_ws, size_t w
 
 /*
  * jf_profile_run -- measurement aid: runs the plan's program once like jf_fidelity_alg1/alg2,
- * with a pair of HIP events on the launch stream around every contraction-step kernel, and
+ * with a pair of HIP events attached to the dispatch of every contraction-step kernel
+ * (hipExtLaunchKernelGGL: the events time the kernel itself, not the queue gaps around it), and
  * reports the summed kernel time together with the algorithmic bytes and flops of those
- * launches (each step reads its input tensor and writes its output once).  The events add a
- * little launch overhead; F_J is not returned.
+ * launches (each step reads its input tensor and writes its output once).  F_J is not returned.
  */
 typedef struct {
   long long launches;   /* contraction-step kernel launches */

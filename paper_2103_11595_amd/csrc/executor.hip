@@ -334,9 +334,10 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
           hipEvent_t a, b;
           JF_HIP(hipEventCreate(&a));
           JF_HIP(hipEventCreate(&b));
-          JF_HIP(hipEventRecord(a, stream));
-          JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
-          JF_HIP(hipEventRecord(b, stream));
+          set_launch_events(a, b);
+          const hipError_t le = launch_step(dd, *hd, cur, dst, B, stream);
+          set_launch_events(nullptr, nullptr);
+          JF_HIP(le);
           prof->ev.push_back(a);
           prof->ev.push_back(b);
           prof->bytes += st.bytes;

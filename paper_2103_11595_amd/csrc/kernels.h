@@ -81,6 +81,10 @@ struct LdsItem {
 };
 hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream);
 
+// Attach a start / stop event pair to the step-kernel launches of this thread (nullptr, nullptr
+// to stop): the events then bracket the kernel execution itself.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
 

@@ -7,6 +7,7 @@
 // so global loads and stores are contiguous runs) times all K contracted combinations -- in LDS,
 // multiplies it by B held in LDS, and writes the 2^L x Nn output tile.  Tiles are disjoint, so
 // a step whose output layout equals its input layout runs in place.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -803,6 +804,23 @@ __global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ 
 }
 
 // ------------------------------------------------------------------------- launchers ---
+// When a profiler has set a pair of events, step kernels are launched with them attached to the
+// dispatch itself (hipExtLaunchKernelGGL): the events then time the kernel alone, without the
+// queue gaps around it.
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+}
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+#define JF_LAUNCH(kernel, grid, block, sm, stream, ...)                                              \
+  do {                                                                                             \
+    if (t_ev_start)                                                                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(sm), stream, t_ev_start, t_ev_stop, 0, __VA_ARGS__); \
+    else                                                                                           \
+      hipLaunchKernelGGL(kernel, grid, block, sm, stream, __VA_ARGS__);                            \
+  } while (0)
 static unsigned grid_for(long long nTiles) {
   const long long cap = 256 * 16;
   return unsigned(nTiles < cap ? nTiles : cap);
@@ -821,10 +839,10 @@ void launch_staged(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc
   const unsigned grid = grid_for(h.nTiles);
   const size_t sm = size_t((TWO_TERM ? 8 : 4) * K * (Nn < 8 ? 8 : Nn) + 2 * K * R) * sizeof(T);
   switch (Nn) {
-    case 1: case 2: case 4: case 8: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 16: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 32: hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    default: /* 64, the largest Nn a step may have */ hipLaunchKernelGGL((k_absorb_mfma<T, TWO_TERM, NT, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 1: case 2: case 4: case 8: JF_LAUNCH((k_absorb_mfma<T, TWO_TERM, NT, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 16: JF_LAUNCH((k_absorb_mfma<T, TWO_TERM, NT, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 32: JF_LAUNCH((k_absorb_mfma<T, TWO_TERM, NT, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: /* 64, the largest Nn a step may have */ JF_LAUNCH((k_absorb_mfma<T, TWO_TERM, NT, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
   }
 }
 
@@ -842,10 +860,10 @@ void launch_direct_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_d
   const unsigned grid = unsigned(wgs < 2048 ? wgs : 2048);
   const size_t sm = size_t((TWO_TERM ? 2 : 1) * 2 * KQ * 4 * 16 * MB) * sizeof(T);
   switch (KQ) {
-    case 1: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 2: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 4: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    default: hipLaunchKernelGGL((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 1: JF_LAUNCH((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 2: JF_LAUNCH((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 4: JF_LAUNCH((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: JF_LAUNCH((k_absorb_mfma_rd<T, TWO_TERM, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
   }
 }
 
@@ -871,11 +889,11 @@ void launch_gauss_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_de
   const unsigned grid = unsigned(wgs < 2048 ? wgs : 2048);
   const size_t sm = size_t(KQ * 64 * 3 * MB) * sizeof(T);
   switch (KQ) {
-    case 1: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 2: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 4: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    case 8: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
-    default: hipLaunchKernelGGL((k_absorb_mfma_gauss<T, NT, MB, 16>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 1: JF_LAUNCH((k_absorb_mfma_gauss<T, NT, MB, 1>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 2: JF_LAUNCH((k_absorb_mfma_gauss<T, NT, MB, 2>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 4: JF_LAUNCH((k_absorb_mfma_gauss<T, NT, MB, 4>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    case 8: JF_LAUNCH((k_absorb_mfma_gauss<T, NT, MB, 8>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
+    default: JF_LAUNCH((k_absorb_mfma_gauss<T, NT, MB, 16>), dim3(grid), dim3(NT), sm, stream, d_desc, a, c, b); break;
   }
 }
 
@@ -968,7 +986,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
         launch_mfma_variant<double, false>(v, h, stream, d_desc, A, C, B);
       } else {
         size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
-        hipLaunchKernelGGL((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
+        JF_LAUNCH((k_absorb<double2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
                            (const double2*)A, (double2*)C, (const double2*)B);
       }
       break;
@@ -977,7 +995,7 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
         launch_mfma_variant<float, false>(v, h, stream, d_desc, A, C, B);
       } else {
         size_t sm = size_t(K * Nn + K * R) * sizeof(float2);
-        hipLaunchKernelGGL((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
+        JF_LAUNCH((k_absorb<float2, float2, float2>), dim3(grid), dim3(256), sm, stream, d_desc,
                            (const float2*)A, (float2*)C, (const float2*)B);
       }
       break;
@@ -986,13 +1004,13 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
         launch_mfma_variant<float, true>(v, h, stream, d_desc, A, C, B);
       } else {
         size_t sm = size_t(2 * K * Nn + K * R) * sizeof(float2);
-        hipLaunchKernelGGL(k_absorb_f32x2, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+        JF_LAUNCH(k_absorb_f32x2, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
                            (const float2*)B);
       }
       break;
     case KM_F32_TO_F64: {
       size_t sm = size_t(K * Nn + K * R) * sizeof(double2);
-      hipLaunchKernelGGL((k_absorb<float2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
+      JF_LAUNCH((k_absorb<float2, double2, double2>), dim3(grid), dim3(256), sm, stream, d_desc,
                          (const float2*)A, (double2*)C, (const double2*)B);
       break;
     }
@@ -1000,12 +1018,12 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
       if (v == KV_STAGED_256) {
         const int KP = ((2 * K + 31) & ~31) + 8;
         size_t sm = size_t(4 * Nn + 2 * R) * KP * sizeof(unsigned short);
-        hipLaunchKernelGGL(k_absorb_bf16x3_mfma<256>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,
+        JF_LAUNCH(k_absorb_bf16x3_mfma<256>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A,
                            (float2*)C, (const float2*)B);
         break;
       }
       size_t sm = size_t(K * Nn + K * R) * sizeof(SplitC);
-      hipLaunchKernelGGL(k_absorb_bf16x3, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+      JF_LAUNCH(k_absorb_bf16x3, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
                          (const float2*)B);
       break;
     }

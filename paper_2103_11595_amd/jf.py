@@ -157,8 +157,9 @@ class Circuit:
         self.n_sites = n_sites
 
     def __del__(self):
-        if getattr(self, "ptr", None):
-            lib().jf_free_circuit(self.ptr)
+        # at interpreter exit the module's globals may already be gone: then the process frees it
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.jf_free_circuit(self.ptr)
             self.ptr = None
 
 
@@ -170,8 +171,8 @@ class Plan:
         self.circuit = circuit
 
     def __del__(self):
-        if getattr(self, "ptr", None):
-            lib().jf_free_plan(self.ptr)
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.jf_free_plan(self.ptr)
             self.ptr = None
 
     def info(self):

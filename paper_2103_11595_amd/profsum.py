@@ -1,0 +1,166 @@
+"""Summaries of rocprofv3 output for the contraction-step kernels (measurement tooling; reads CSV
+files only, runs nothing on the GPU).
+
+    python -m paper_2103_11595_amd.profsum trace  --dir D --log L --out profiles/X.md --command "..."
+    python -m paper_2103_11595_amd.profsum traffic --fetch D1 --write D2 --log L --copy-mib M \
+        --out profiles/Y.md --json profiles/Z.json --command "..."
+
+``trace`` reads a ``--kernel-trace`` run of bench.py and reports, per kernel name, the launches of
+the last clean program runs (the passes after the autotuner, identified from the end of the
+trace: every program run has the same number of step launches, taken from bench.py's JSON line),
+and their average duration next to the live HIP-event average bench.py printed.
+
+``traffic`` reads two ``--pmc`` runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of bench.py with
+``--copy-calibration-mib M``: the copy of M MiB (one ``__amd_rocclr_copyBuffer`` dispatch that reads
+and writes M MiB) gives the factor from counter units to bytes, which then scales the counters of
+the last program run's step launches.  The result is HBM bytes per launch beside the algorithmic
+bytes per launch.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+STEP_PREFIXES = ("k_absorb",)
+
+
+def kernels_sha() -> str:
+    path = os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def bench_line(log: str) -> dict:
+    lines = [x for x in open(log) if x.startswith("{")]
+    if not lines:
+        raise SystemExit(f"no JSON line in {log}")
+    return json.loads(lines[-1])
+
+
+def short(name: str) -> str:
+    return name.replace("void ", "").split("(jf::StepDesc")[0].split("(HIP_vector_type")[0].replace("jf::", "")
+
+
+def is_step(name: str) -> bool:
+    return any(p in name for p in STEP_PREFIXES)
+
+
+def last_passes(rows, per_pass: int, passes: int):
+    steps = [r for r in rows if is_step(r["Kernel_Name"])]
+    take = per_pass * passes
+    if len(steps) < take:
+        raise SystemExit(f"trace holds {len(steps)} step launches, fewer than {passes} x {per_pass}")
+    return steps[-take:]
+
+
+def trace(args):
+    b = bench_line(args.log)
+    n = int(b["roofline"]["launches"])
+    rows = list(csv.DictReader(open(os.path.join(args.dir, "bench_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = last_passes(rows, n, args.passes)
+    by = {}
+    for r in sel:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        k = short(r["Kernel_Name"])
+        c, t = by.get(k, (0, 0.0))
+        by[k] = (c + 1, t + d)
+    total = sum(t for _, t in by.values())
+    out = [f"# {args.title}", "", "Command (from the repository root, on one MI355X):", "", "    " + args.command, "",
+           f"kernels.hip sha256[:16] = {kernels_sha()}", "",
+           f"Last {args.passes} program runs after autotuning, {n} contraction-step launches each "
+           f"(the launches of the autotuner itself are excluded).", "",
+           "| kernel | launches | avg (us) | total (ms) | % |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k}` | {c} | {t / c:.1f} | {t / 1e3:.3f} | {100 * t / total:.2f} |")
+    avg = total / len(sel)
+    live = b["roofline"]["avg_launch_us"]
+    out += ["", f"All contraction-step launches: {len(sel)} launches, average **{avg:.1f} us** per launch, "
+            f"{total / 1e3 / args.passes:.3f} ms of step kernels per program run.",
+            f"bench.py in the profiled run (HIP events attached to every step dispatch of one program run, "
+            f"perturbed by the profiler's own instrumentation): {live:.1f} us per launch, "
+            f"{b['roofline']['kernel_ms']:.3f} ms per run; value {b['value']:.0f} {b['unit']} "
+            f"({b['ms_per_step']:.3f} ms per pass)."]
+    if args.live_log:
+        c = bench_line(args.live_log)
+        lv = c["roofline"]["avg_launch_us"]
+        out += [f"bench.py without the profiler (`{args.live_command}`): **{lv:.1f} us** per launch "
+                f"(`roofline.avg_launch_us`, {c['roofline']['kernel_ms']:.3f} ms per run; trace / live = {avg / lv:.3f}); "
+                f"value {c['value']:.0f} {c['unit']} ({c['ms_per_step']:.3f} ms per pass)."]
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def counters(path, name):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def traffic(args):
+    b = bench_line(args.log)
+    n = int(b["roofline"]["launches"])
+    res = {}
+    for key, d, cname in (("fetch", args.fetch, "FETCH_SIZE"), ("write", args.write, "WRITE_SIZE")):
+        rows = counters(os.path.join(d, "bench_counter_collection.csv"), cname)
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1024]
+        if not copies:
+            raise SystemExit(f"no calibration copy in {d}")
+        scale = args.copy_mib * 1024.0 / float(copies[0]["Counter_Value"])   # true KiB / counter KiB
+        steps = last_passes(rows, n, 1)
+        kib = sum(float(r["Counter_Value"]) for r in steps)
+        res[key] = {"scale": scale, "bytes": kib * 1024.0 * scale, "raw_kib": kib}
+    alg = b["roofline"]["algorithmic_bytes"]
+    tr = res["fetch"]["bytes"] + res["write"]["bytes"]
+    rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "launches": n,
+           "traffic_bytes_per_launch": tr / n, "fetch_bytes_per_launch": res["fetch"]["bytes"] / n,
+           "write_bytes_per_launch": res["write"]["bytes"] / n, "algorithmic_bytes_per_launch": alg / n,
+           "fetch_scale": res["fetch"]["scale"], "write_scale": res["write"]["scale"]}
+    json.dump(rec, open(args.json, "w"), indent=1)
+    out = [f"# {args.title}", "", "Commands (from the repository root, on one MI355X; one counter per run):", ""]
+    out += ["    " + c for c in args.command.split(" ;; ")]
+    out += ["", f"kernels.hip sha256[:16] = {rec['kernels_sha']}", "",
+            f"Calibration: one copy of {args.copy_mib} MiB (`__amd_rocclr_copyBuffer`, reads and writes "
+            f"{args.copy_mib} MiB): FETCH_SIZE x {res['fetch']['scale']:.4f}, WRITE_SIZE x {res['write']['scale']:.4f} "
+            "give bytes.", "",
+            f"Last program run ({n} contraction-step launches, after autotuning):", "",
+            "| quantity | per program run | per launch |", "|---|---|---|",
+            f"| HBM fetch (scaled FETCH_SIZE) | {res['fetch']['bytes'] / 1e9:.3f} GB | {res['fetch']['bytes'] / n / 1e6:.1f} MB |",
+            f"| HBM write (scaled WRITE_SIZE) | {res['write']['bytes'] / 1e9:.3f} GB | {res['write']['bytes'] / n / 1e6:.1f} MB |",
+            f"| HBM traffic | {tr / 1e9:.3f} GB | {tr / n / 1e6:.1f} MB |",
+            f"| algorithmic bytes (planner) | {alg / 1e9:.3f} GB | {alg / n / 1e6:.1f} MB |", "",
+            f"Traffic / algorithmic = **{tr / alg:.4f}**."]
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--dir", required=True)
+    t.add_argument("--log", required=True)
+    t.add_argument("--passes", type=int, default=6)
+    t.add_argument("--out", required=True)
+    t.add_argument("--title", default="Contraction-step kernels")
+    t.add_argument("--command", required=True)
+    t.add_argument("--live-log", default=None, help="log of a bench.py run without the profiler")
+    t.add_argument("--live-command", default="python3 bench.py")
+    f = sub.add_parser("traffic")
+    f.add_argument("--fetch", required=True)
+    f.add_argument("--write", required=True)
+    f.add_argument("--log", required=True)
+    f.add_argument("--copy-mib", type=int, required=True)
+    f.add_argument("--out", required=True)
+    f.add_argument("--json", required=True)
+    f.add_argument("--title", default="HBM traffic of the contraction-step kernels")
+    f.add_argument("--command", required=True)
+    a = ap.parse_args()
+    trace(a) if a.cmd == "trace" else traffic(a)
+
+
+if __name__ == "__main__":
+    main()
