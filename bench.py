@@ -59,6 +59,166 @@ def traffic_record(kernel_sha: str):
     return rec.get("traffic_bytes_per_launch")
 
 
+OTHER = {
+    "cfg1": (1, "alg1: n=5 qubits, 50 random gates (70% H/S/T/RZ, 30% CX), 2 depolarising sites p=0.01, 16 Kraus terms"),
+    "cfg3": (2, "alg2 doubled network: n=25 chain, brickwork depth 20 (RZ+SX layers, CX), 30 sites "
+                "(depolarising 1e-3 / amplitude damping 1e-3 alternating)"),
+    "cfg5": (2, "alg2 doubled network: n=36 chain, brickwork depth 8 (Haar SU(2) layers, CX), 40 depolarising sites p=1e-4"),
+}
+
+
+def _timed(torch, fn, n):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t0) / n
+
+
+def run_single(args, torch, gen, jf, stream):
+    """The n=5 Alg I workload and the two Alg II chains: one network (or 16 miters) per step."""
+    import numpy as np
+    alg, desc = OTHER[args.config]
+    inst = getattr(gen, "config" + args.config[-1])()
+    covered = 1
+    for site in inst["noise"]:
+        covered *= 4 if site["channel"] == "depolarizing" else 2
+    res = {}
+    for dt in (args.dtype,) + tuple(d for d in ("c128", "c64", "bf16x3") if d != args.dtype):
+        p = jf.plan(inst, alg, dt)
+        info = p.info()
+        ws = jf.workspace(info["workspace_bytes"])
+        run = (lambda: jf.jf_fidelity_alg1(p, ws, stream)) if alg == 1 else (lambda: jf.jf_fidelity_alg2(p, ws, stream))
+        if not args.no_autotune:
+            jf.jf_autotune(p, ws, stream)
+        r, sec = _timed(torch, run, args.steps if dt == args.dtype else max(3, args.steps // 4))
+        res[dt] = {"r": r, "sec": sec, "info": info, "prof": jf.jf_profile_run(p, ws, stream)}
+    m = res[args.dtype]
+    unit = "Kraus-term contractions/s" if alg == 1 else "networks/s"
+    value = (m["info"]["kraus_terms"] if alg == 1 else 1) / m["sec"]
+    out = {"metric": "Kraus-term contractions/s + contraction TFLOP/s, c64 vs c128 at |dF_J|<=1e-6" if alg == 1
+           else "doubled networks/s (and Kraus terms covered/s) + contraction TFLOP/s, c64 vs c128",
+           "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": m["sec"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+           "data": "synthetic (seeded generator, no datasets)",
+           "config": {"workload": desc, "alg": alg, "kraus_terms_covered": covered},
+           "kraus_terms_covered_per_s": covered / m["sec"],
+           "forms": {dt: {"per_s": (v["info"]["kraus_terms"] if alg == 1 else 1) / v["sec"], "ms_per_step": v["sec"] * 1e3,
+                          "fj": v["r"]["fj"], "one_minus_fj": v["r"]["one_minus_fj"],
+                          "abs_dfj_vs_c128": abs(v["r"]["fj"] - res["c128"]["r"]["fj"]),
+                          "imag_residual": v["r"].get("imag_residual"), "max_log2_intermediate": v["info"]["max_log2_intermediate"],
+                          "path_flops": v["info"]["path_flops"], "path_bytes": v["info"]["path_bytes"],
+                          "step_launches": v["prof"]["launches"], "kernel_ms": v["prof"]["kernel_ms"],
+                          "tflops": v["info"]["path_flops"] / v["sec"] / 1e12}
+                     for dt, v in res.items()},
+           "autotuned": not args.no_autotune}
+    if args.config == "cfg1" and not args.no_cpu:
+        from oracle import dense
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10.0:
+            dense.fidelity_alg1(inst)
+            k += 1
+        dt_ = (time.perf_counter() - t0) / k
+        out["cpu_baseline"] = {"value": 16 / dt_, "unit": "Kraus-term contractions/s", "cores": os.cpu_count(),
+                               "kind": "oracle", "sample": f"dense FP64 oracle on this workload, {k} runs"}
+        ref = dense.fidelity_alg1(inst)["fj"]
+        for dt, v in out["forms"].items():
+            v["abs_dfj_vs_oracle"] = abs(v["fj"] - ref)
+    print(json.dumps(out))
+
+
+def run_batch(args, torch, gen, jf, stream):
+    """The 512-circuit batch under the budget rule: plan every member (reduced search effort), run
+    the feasible ones in cost order -- the small ones together in one captured jf_fidelity_batch
+    launch, then one at a time -- until the GPU time budget is spent, and project the rest."""
+    insts = gen.config4()
+    t0 = time.perf_counter()
+    plans, infeasible = [], []
+    for inst in insts:
+        try:
+            p = jf.plan(inst, 1, args.dtype, flags=jf.JF_FLAG_EFFORT(3))
+            plans.append((p.info(), p, inst))
+        except jf.JfError as e:
+            infeasible.append({"name": inst["name"], "reason": str(e)[:100]})
+    plan_s = time.perf_counter() - t0
+    plans.sort(key=lambda x: x[0]["path_bytes"])
+    small = [x for x in plans if x[0]["workspace_bytes"] <= (64 << 20) and x[0]["path_bytes"] <= 2e8]
+    large = [x for x in plans if x not in small]
+    done_terms, gpu_s, done = 0, 0.0, 0
+    # the small members: one batch (persistent launch for the tiny ones + every step program),
+    # captured in a hipGraph on the first call and replayed
+    bp = [x[1] for x in small]
+    need = jf.jf_batch_workspace(bp)
+    ws = jf.workspace(need)
+    side = torch.cuda.Stream()  # a non-null stream (default priority): the batch is graph-captured there
+    jf.jf_fidelity_batch(bp, ws, side)
+    torch.cuda.synchronize()
+    reps = 5
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        out_small = jf.jf_fidelity_batch(bp, ws, side)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t1) / reps
+    del ws
+    done_terms += sum(x[0]["kraus_terms"] for x in small)
+    gpu_s += batch_s
+    done += len(small)
+    # the large members, cheapest first, until the budget is spent
+    rate_bytes = []
+    ws = None
+    for info, p, inst in large:
+        if gpu_s >= args.budget_s:
+            break
+        if ws is None or ws.numel() < info["workspace_bytes"]:
+            ws = None
+            ws = jf.workspace(info["workspace_bytes"])
+        jf.jf_fidelity_alg1(p, ws, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        jf.jf_fidelity_alg1(p, ws, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        gpu_s += dt
+        done += 1
+        done_terms += info["kraus_terms"]
+        rate_bytes.append(info["path_bytes"] / dt)
+    # parity of the completed members (not timed): complex64 against complex128
+    worst = 0.0
+    if args.dtype != "c128":
+        ws = None
+        res_b = dict(zip([id(x[1]) for x in small], out_small))
+        for info, p, inst in small + large[:done - len(small)]:
+            q = jf.plan(inst, 1, "c128", flags=jf.JF_FLAG_EFFORT(3))
+            need = max(info["workspace_bytes"], q.info()["workspace_bytes"])
+            if ws is None or ws.numel() < need:
+                ws = None
+                ws = jf.workspace(need)
+            f64 = res_b[id(p)]["fj"] if id(p) in res_b else jf.jf_fidelity_alg1(p, ws, stream)["fj"]
+            worst = max(worst, abs(f64 - jf.jf_fidelity_alg1(q, ws, stream)["fj"]))
+    rest = large[done - len(small):]
+    bw = (sum(rate_bytes) / len(rate_bytes)) if rate_bytes else 4e12
+    projected = sum(x[0]["path_bytes"] for x in rest) / bw
+    out = {"metric": "Kraus-term contractions/s + contraction TFLOP/s, c64 vs c128 at |dF_J|<=1e-6",
+           "value": done_terms / gpu_s, "unit": "Kraus-term contractions/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": gpu_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.dtype, "data": "synthetic (seeded generator, no datasets)",
+           "config": {"workload": "512 circuits: n~U{8..20}, gates~U{100..800} (70% H/S/T/RZ, 30% CX), "
+                                  "1-6 depolarising sites p~U[1e-4,1e-2]; budget rule (cost-sorted, time budget)",
+                      "budget_s": args.budget_s},
+           "members": len(insts), "feasible": len(plans), "infeasible_at_cap_2^28": len(infeasible),
+           "completed": done, "completed_terms": done_terms, "gpu_seconds": gpu_s,
+           "small_batch": {"members": len(small), "terms": sum(x[0]["kraus_terms"] for x in small),
+                           "seconds_per_replay": batch_s,
+                           "terms_per_s": sum(x[0]["kraus_terms"] for x in small) / batch_s},
+           "remaining_feasible": len(rest), "projected_seconds_for_remaining": projected,
+           "max_abs_dfj_vs_c128_completed": worst if args.dtype != "c128" else 0.0,
+           "planning_seconds": plan_s, "infeasible_examples": infeasible[:5]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +228,10 @@ def main():
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"], help="form reported as value")
     ap.add_argument("--only", action="store_true", help="run only the reported form (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true", help="time the fixed kernel rule only")
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="workload: cfg2 (default) the n=16 Alg I workload; cfg1 n=5 Alg I; cfg3 n=25 chain Alg II; "
+                         "cfg4 the 512-circuit batch (budget rule); cfg5 n=36 chain Alg II")
+    ap.add_argument("--budget-s", type=float, default=60.0, help="cfg4: GPU time budget for the cost-sorted work list")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB with torch (a plain copy kernel of known size, "
                          "the reference for hardware byte counters)")
@@ -85,6 +249,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.config == "cfg4":
+        return run_batch(args, torch, gen, jf, stream)
+    if args.config != "cfg2":
+        return run_single(args, torch, gen, jf, stream)
     inst = gen.config2()
 
     if args.copy_calibration_mib > 0:

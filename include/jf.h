@@ -163,7 +163,8 @@ jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 /* Text description of the lowered program, one line per device step:
  * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes rowsA rowsC sA nC",
  * the last four being comma-separated bit positions (A for tile rows and summed legs, C for tile
- * rows and new legs; "-" when empty).
+ * rows and new legs; "-" when empty).  compute is f64, f32, f32x2 (FP32 with the operator kept as
+ * an FP32 pair) or bf16x3.
  * Writes at most len bytes (NUL-terminated) and returns the full length needed. Host only. */
 long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
 

@@ -132,7 +132,8 @@ extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len
         const Step& st = cp.steps[s];
         char line[256];
         snprintf(line, sizeof(line), "%zu %d %zu %d %d %d %d %d %lld %s %s %s %d %.6g %.6g", c, s, lv, st.kS, st.kN, st.L,
-                 st.rA, st.rC, st.nTiles, pn[st.in_prec], pn[st.out_prec], cn[st.compute], st.nvar, st.flops, st.bytes);
+                 st.rA, st.rC, st.nTiles, pn[st.in_prec], pn[st.out_prec],
+                 (st.compute == C_F32 && st.two_term) ? "f32x2" : cn[st.compute], st.nvar, st.flops, st.bytes);
         out += line;
         // bit positions (in A, resp. C) of the tile rows, the summed legs and the new legs
         auto bits = [](const std::vector<long long>& off, int n) {

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cfloat>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -57,6 +58,45 @@ int mode_of(const Step& st) {
   if (st.compute == C_F64) return st.in_prec == P_C64 ? KM_F32_TO_F64 : KM_F64;
   if (st.compute == C_F32) return st.two_term ? KM_F32X2 : KM_F32;
   return KM_BF16X3;
+}
+
+// FP32 image of a complex FP64 operator block for single-term FP32 steps.  Every entry is one of
+// its two FP32 neighbours; among those choices the rounding keeps Re<B, fl(B) - B> (summed over
+// real and imaginary parts) near zero.  In a miter network the rest of the network around a block
+// is close to the block's inverse, so that inner product is the first-order change the rounding
+// makes to the traces.  Round-to-nearest alone biases it whenever many entries share a value
+// (the 1/sqrt(2) of H and T rounds down by 1.7e-8 in FP32, so such blocks shrink every trace by
+// the same factor, step after step).  Start from round-to-nearest, then move single entries to
+// their other neighbour, largest effect first, while that brings the sum closer to zero.
+void balanced_round(const std::vector<cd>& M, std::vector<float>& out) {
+  const size_t n = 2 * M.size();
+  out.resize(n);
+  struct Flip {
+    double dT;
+    size_t k;
+    float alt;
+  };
+  std::vector<Flip> flips;
+  double T = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const double x = (i & 1) ? M[i / 2].imag() : M[i / 2].real();
+    const float f = float(x);
+    out[i] = f;
+    const double d = double(f) - x;
+    T += x * d;
+    if (d != 0) {
+      const float alt = std::nextafter(f, d > 0 ? -INFINITY : INFINITY);
+      flips.push_back({x * (double(alt) - x - d), i, alt});
+    }
+  }
+  std::sort(flips.begin(), flips.end(), [](const Flip& a, const Flip& b) {
+    return std::fabs(a.dT) != std::fabs(b.dT) ? std::fabs(a.dT) > std::fabs(b.dT) : a.k < b.k;
+  });
+  for (const Flip& f : flips)
+    if (std::fabs(T + f.dT) < std::fabs(T)) {
+      T += f.dT;
+      out[f.k] = f.alt;
+    }
 }
 
 void build_layout(const Program& P, DevState& S) {
@@ -153,11 +193,18 @@ void build_layout(const Program& P, DevState& S) {
           }
         } else {
           const size_t nb = st.B[v].size();
+          std::vector<float> bal;
+          const bool single = !(st.compute == C_F32 && st.two_term);
+          if (single) balanced_round(st.B[v], bal);
           for (size_t i = 0; i < nb; ++i) {
             float re = float(st.B[v][i].real()), im = float(st.B[v][i].imag());
+            if (single) {
+              re = bal[2 * i];
+              im = bal[2 * i + 1];
+            }
             std::memcpy(dst + 8 * i, &re, 4);
             std::memcpy(dst + 8 * i + 4, &im, 4);
-            if (st.compute == C_F32 && st.two_term) {
+            if (!single) {
               float rl = float(st.B[v][i].real() - double(re)), il = float(st.B[v][i].imag() - double(im));
               std::memcpy(dst + 8 * (nb + i), &rl, 4);
               std::memcpy(dst + 8 * (nb + i) + 4, &il, 4);
