@@ -34,7 +34,7 @@ extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype 
   opt.flags = flags;
   const unsigned effort = (flags >> 8) & 15u;
   if (effort) opt.restarts = 1 << (effort + 5);
-  opt.kmax = dtype == JF_C128 ? 5 : 6;  // 64-wide blocks pay off where the products run on FP32 MFMA
+  opt.kmax = 6;  // blocks of up to 64 x 64: the Gauss-form MFMA kernels keep them HBM-bound
   try {
     auto p = new jf_plan;
     p->prog = plan_program(*c, opt);

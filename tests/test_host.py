@@ -71,10 +71,10 @@ def test_cap_forces_slicing_not_failure():
     inst = gen.random_circuit(3, 40, 6, 0.01, 0.1, 8)   # 12 Kraus-index bits dominate the width
     c = jf.jf_load_circuit(inst)
     free = jf.jf_plan_contraction(c, 1, "c128")
-    need = int(free.info()["max_log2_intermediate"])
+    need = int(free.info()["max_log2_intermediate"])   # 2^10 (the gate part alone needs 2^6)
     ref = dense.fidelity_alg1(inst, want_terms=True)
     want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
-    for cut in (2, 4, 6):
+    for cut in (2, 4):
         tight = jf.jf_plan_contraction(c, 1, "c128", max_log2=need - cut)
         assert tight.stats()["n_sliced_sites"] >= cut // 2
         assert tight.info()["max_log2_intermediate"] <= need - cut
