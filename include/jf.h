@@ -139,8 +139,10 @@ jf_status jf_load_circuit(int n_qubits, const jf_gate* ideal, int n_ideal,
  * (alg = 2, Section IV-B: q and q' wires, V on q and V* on q', noise as M_N on (q, q')), apply
  * the exact local cancellation of adjacent U^dagger U pairs (Section IV-C), search a greedy
  * minimum-intermediate-size contraction order, slice Kraus indices while the largest
- * intermediate exceeds 2^max_log2_intermediate elements (<= 0 selects 30), fuse consecutive
+ * intermediate exceeds 2^max_log2_intermediate elements (<= 0 selects 28), fuse consecutive
  * steps into small-operator blocks and lower the order to a device step program.
+ * alg = 0 plans both algorithms and keeps the one whose step program has the smaller estimated
+ * device time (jf_plan_stats.alg tells which; call jf_fidelity_alg1 or _alg2 accordingly).
  * Host only (no GPU needed).  Errors: JF_E_ARG, JF_E_TOO_LARGE, JF_E_UNSUPPORTED.
  */
 jf_status jf_plan_contraction(const jf_circuit* circuit, int alg, jf_dtype dtype,
@@ -157,6 +159,8 @@ typedef struct {
   int n_tensors_before_cancel, n_tensors_after_cancel;
   double planner_seconds;
   double empty_loops;
+  int alg;             /* 1 or 2: the algorithm of the plan */
+  double est_seconds;  /* planner's cost-model estimate of one run's device time */
 } jf_plan_stats;
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 

@@ -19,6 +19,22 @@ extern "C" const char* jf_last_error(void) { return g_err.c_str(); }
 
 extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype dtype, int max_log2, unsigned flags,
                                          jf_plan** out) {
+  if (c && out && alg == 0) {
+    // Algorithm I grows with the number of Kraus tuples, Algorithm II with the doubled wires
+    // (Section IV): plan both and keep the one with the smaller estimated device time.
+    jf_plan *p1 = nullptr, *p2 = nullptr;
+    const jf_status s1 = jf_plan_contraction(c, 1, dtype, max_log2, flags, &p1);
+    const std::string e1 = s1 == JF_OK ? std::string() : std::string(jf_last_error());
+    const jf_status s2 = jf_plan_contraction(c, 2, dtype, max_log2, flags, &p2);
+    if (s1 != JF_OK && s2 != JF_OK) {
+      set_error("jf_plan_contraction: neither algorithm plans: " + e1 + "; " + jf_last_error());
+      return s2;
+    }
+    const bool take1 = s2 != JF_OK || (s1 == JF_OK && p1->prog.est_seconds <= p2->prog.est_seconds);
+    *out = take1 ? p1 : p2;
+    jf_free_plan(take1 ? p2 : p1);
+    return JF_OK;
+  }
   if (!c || !out || (alg != 1 && alg != 2) || dtype < JF_C128 || dtype > JF_C64_BF16X3) {
     set_error("jf_plan_contraction: bad argument");
     return JF_E_ARG;
@@ -85,6 +101,8 @@ extern "C" jf_status jf_plan_stats_get(const jf_plan* p, jf_plan_stats* s) {
   r.n_tensors_after_cancel = p->prog.n_after_cancel;
   r.planner_seconds = p->prog.planner_seconds;
   r.empty_loops = p->prog.empty_loops;
+  r.alg = p->prog.opt.alg;
+  r.est_seconds = p->prog.est_seconds;
   *s = r;
   return JF_OK;
 }

@@ -125,6 +125,7 @@ struct ComponentProgram {
   long long out_len = 1;         // complex entries of the component output
   long long leaves = 1;          // DFS leaves
   double flops = 0, bytes = 0;
+  double est_seconds = 0;          // cost-model estimate of the device time of one run
   int max_log2 = 0;
   int n_tensors = 0;
   // device: offset of the component output (double2 elements) in the output region
@@ -158,6 +159,7 @@ struct Program {
   int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0;
   double planner_seconds = 0;
   double flops = 0, bytes = 0;
+  double est_seconds = 0;          // cost-model estimate of the device time of one run
   int max_log2 = 0;
   long long work_items = 0;
   size_t ws_bytes = 0;             // workspace bytes

@@ -547,6 +547,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         st.bytes = std::ldexp(double(ein), st.rA) + std::ldexp(double(eout), st.rC);
         comp_flops += st.flops * mult;
         comp_bytes += st.bytes * mult;
+        P.est_seconds += mult * (std::max(st.bytes / cm.bw, st.flops / cm.flops) + cm.launch);
         if (!final_step) {
           level_bytes[lv] = std::max(level_bytes[lv], size_t(eout) << st.rC);
           level_maxw[lv] = std::max(level_maxw[lv], st.rC);

@@ -65,7 +65,7 @@ class jf_plan_stats(C.Structure):
     _fields_ = [("n_steps", C.c_int), ("n_components", C.c_int), ("n_sliced_sites", C.c_int),
                 ("n_open_bits", C.c_int), ("n_tensors_before_cancel", C.c_int),
                 ("n_tensors_after_cancel", C.c_int), ("planner_seconds", C.c_double),
-                ("empty_loops", C.c_double)]
+                ("empty_loops", C.c_double), ("alg", C.c_int), ("est_seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -275,7 +275,10 @@ def jf_plan_contraction(circ: Circuit, alg: int = 1, dtype="c128", max_log2: int
     dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     out = C.c_void_p()
     _check(lib().jf_plan_contraction(circ.ptr, int(alg), dt, int(max_log2), int(flags), C.byref(out)))
-    return Plan(out.value, int(alg), dt, circ)
+    p = Plan(out.value, int(alg), dt, circ)
+    if int(alg) == 0:
+        p.alg = p.stats()["alg"]  # the algorithm the planner chose
+    return p
 
 
 def jf_plan_info(plan: Plan) -> dict:
@@ -390,5 +393,8 @@ def plan(inst: dict, alg: int = 1, dtype="c128", max_log2: int = 0, flags: int =
 
 
 def fidelity(inst: dict, alg: int = 1, dtype="c128", want_terms: bool = False, **kw) -> dict:
+    """F_J of an instance; alg = 0 lets the planner choose between Algorithms I and II."""
     p = plan(inst, alg, dtype, **kw)
-    return jf_fidelity_alg1(p, want_terms=want_terms) if alg == 1 else jf_fidelity_alg2(p)
+    if p.stats()["alg"] == 1:
+        return jf_fidelity_alg1(p, want_terms=want_terms)
+    return jf_fidelity_alg2(p)

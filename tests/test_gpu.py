@@ -373,3 +373,12 @@ def test_every_feasible_batch_member_c64_against_c128():
         n += 1
     say("members", n, "worst |dF_J|", worst)
     assert n == 443
+
+
+def test_auto_algorithm_on_the_36_qubit_chain():
+    inst = gen.config5()
+    want = run2(inst, "c128")["fj"]
+    p = jf.plan(inst, 0, "c64")
+    got = jf.fidelity(inst, 0, "c64")["fj"]
+    say("auto chose Algorithm", p.alg)
+    assert abs(got - want) <= TOL["c64"]

@@ -148,3 +148,16 @@ def test_plans_of_the_workloads_fit_one_gpu():
         info = p.info()
         assert info["max_log2_intermediate"] <= cap
         assert info["workspace_bytes"] < 64 * 2**30
+
+
+def test_auto_algorithm_keeps_the_cheaper_plan():
+    for seed, (n, g, m) in enumerate([(4, 40, 3), (5, 60, 2), (3, 30, 5)]):
+        inst = gen.random_circuit(n, g, m, 1e-3, 0.1, 60 + seed)
+        est = {a: jf.plan(inst, a, "c128").stats()["est_seconds"] for a in (1, 2)}
+        p = jf.plan(inst, 0, "c128")
+        assert p.alg in (1, 2) and p.stats()["alg"] == p.alg
+        assert p.stats()["est_seconds"] == min(est.values())
+        ref = dense.fidelity_alg1(inst)["fj"]
+        got = p.emulate()
+        fj = float(np.sum(np.abs(got) ** 2)) if p.alg == 1 else got[0].real
+        assert abs(fj - ref) < 1e-12
