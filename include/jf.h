@@ -277,6 +277,33 @@ jf_status jf_set_kernel_variant(jf_plan* plan, int variant);
  * or -1 for a NULL result. */
 int jf_is_equivalent(const jf_result* result, double eps);
 
+/*
+ * jf_decide_equivalence -- Definition 1 with early stopping (Algorithm I, Section IV-A: the terms
+ * |tr(U^dagger E_k)|^2 / d^2 are nonnegative, so a partial sum above 1 - eps decides equivalence).
+ * For an Algorithm I plan with sliced Kraus sites, every component but the one with the most
+ * depth-first leaves runs in full and that one runs leaf by leaf; after each leaf the library
+ * holds a two-sided bound on F_J:
+ *   fj_lower = the terms computed so far (complete for the other components),
+ *   fj_upper = fj_lower + (the mass of the leaves not yet run) x (the mass of every other site),
+ * where the mass of a Kraus tuple is prod_i ||K_{k_i}||^2 (operator norms; w_k for Pauli
+ * channels), an upper bound on its term.  It stops as soon as fj_lower - margin > 1 - eps
+ * (decision 1: equivalent) or fj_upper + margin <= 1 - eps (decision 0: not equivalent), where
+ * margin is the parity bar of the plan's form (1e-12 complex128, 1e-6 complex64, 3e-5 3xBF16).
+ * Plans with one leaf (and Algorithm II plans) run once and decide from F_J; decision -1 means
+ * F_J lies within the margin of 1 - eps.  Leaves run in depth-first order (Kraus operator 0 of
+ * each sliced site first: the no-error operator for the built-in channels).  Synchronises the
+ * stream after every leaf.  Errors: JF_E_ARG (eps outside (0, 1]), JF_E_OOM, JF_E_HIP.
+ */
+typedef struct {
+  int decision;           /* 1 equivalent, 0 not equivalent, -1 within the margin of 1 - eps */
+  double fj_lower, fj_upper;
+  double margin;
+  long long leaves_run, leaves_total;  /* depth-first leaves (work items) run / in the plan */
+  double seconds;         /* device time, HIP events */
+} jf_decision;
+jf_status jf_decide_equivalence(jf_plan* plan, double eps, void* dev_ws, size_t ws_bytes, void* stream,
+                                jf_decision* out);
+
 void jf_free_circuit(jf_circuit* circuit);
 void jf_free_plan(jf_plan* plan);
 const char* jf_last_error(void);

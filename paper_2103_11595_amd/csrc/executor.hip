@@ -322,91 +322,116 @@ jf_status tune_step(StepDesc* hd, const StepDesc* dd, const void* A, void* C, co
   return JF_OK;
 }
 
+// Enqueue the steps of level lv of component c for Kraus variant v of the level's sliced site,
+// starting from `parent` (nullptr: the constant 1 of the first step's precision), the component's
+// output at element offset `base`; *end receives the level's last output (no synchronisation).
+jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, int lv, int v,
+                        const void* parent, long long base, const void** end, Prof* prof, Tune* tune) {
+  const ComponentProgram& cp = p->prog.comps[c];
+  DevState& S = state_of(p);
+  const DevLayout& L = S.lay;
+  const Level& lev = cp.levels[lv];
+  unsigned char* out = ws + L.out_off + size_t(cp.out_off) * 16;
+  const void* cur = parent;
+  if (!cur) {
+    const Step& s0 = cp.steps[lev.first < lev.last ? lev.first : 0];
+    cur = ws + L.const_off + (s0.in_prec == P_C64 ? 16 : 0);
+  }
+  unsigned char* b0 = ws + L.level_buf[c][2 * lv];
+  unsigned char* b1 = ws + L.level_buf[c][2 * lv + 1];
+  for (int si = lev.first; si < lev.last; ++si) {
+    const Step& st = cp.steps[si];
+    void* dst;
+    if (st.final_step) {
+      dst = out + size_t(base) * 16;
+    } else if (st.inplace_ok && st.in_prec == st.out_prec && (cur == b0 || cur == b1)) {
+      dst = const_cast<void*>(cur);
+    } else {
+      dst = (cur == b0) ? b1 : b0;
+    }
+    const int var = (si == lev.first && lev.site >= 0) ? v : 0;
+    const StepDesc* dd = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][si]);
+    const StepDesc* hd = reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][si]]);
+    const void* B = ws + L.step_b[c][si][var];
+    if (tune && !tune->done[c][si]) {
+      jf_status ts = tune_step(const_cast<StepDesc*>(hd), dd, cur, dst, B, stream, tune->reps, dst == cur);
+      if (ts != JF_OK) return ts;
+      tune->done[c][si] = 1;
+    }
+    if (prof) {
+      hipEvent_t a, b;
+      JF_HIP(hipEventCreate(&a));
+      JF_HIP(hipEventCreate(&b));
+      set_launch_events(a, b);
+      const hipError_t le = launch_step(dd, *hd, cur, dst, B, stream);
+      set_launch_events(nullptr, nullptr);
+      JF_HIP(le);
+      prof->ev.push_back(a);
+      prof->ev.push_back(b);
+      prof->bytes += st.bytes;
+      prof->flops += st.flops;
+      jf_step_profile r = {};
+      r.flops = st.flops;
+      r.bytes = st.bytes;
+      r.kS = st.kS;
+      r.kN = st.kN;
+      r.L = st.L;
+      r.mode = hd->mode;
+      r.variant = resolve_variant(*hd);
+      r.component = int(c);
+      prof->rec.push_back(r);
+    } else {
+      JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
+    }
+    cur = dst;
+  }
+  *end = cur;
+  return JF_OK;
+}
+
+// Clear component c's output and walk its levels depth first: every prefix is computed once and
+// kept in its level buffer while the Kraus operators of the next sliced site are iterated.
+jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, Prof* prof, Tune* tune) {
+  const ComponentProgram& cp = p->prog.comps[c];
+  const DevLayout& L = state_of(p).lay;
+  JF_HIP(launch_zero(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len, stream));
+  struct Frame {
+    int lv;
+    int v;
+    const void* parent;
+    long long base;
+  };
+  std::vector<Frame> stack;
+  stack.push_back({0, 0, nullptr, 0});
+  while (!stack.empty()) {
+    Frame f = stack.back();
+    stack.pop_back();
+    const Level& lev = cp.levels[f.lv];
+    if (f.v + 1 < lev.nvar) stack.push_back({f.lv, f.v + 1, f.parent, f.base});
+    const long long base = f.base + f.v * lev.out_stride;
+    const void* cur = nullptr;
+    jf_status st = enqueue_level(p, ws, stream, c, f.lv, f.v, f.parent, base, &cur, prof, tune);
+    if (st != JF_OK) return st;
+    if (f.lv + 1 < (int)cp.levels.size()) stack.push_back({f.lv + 1, 0, cur, base});
+  }
+  return JF_OK;
+}
+
 // Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
 jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
                           bool skip_lds = false, Tune* tune = nullptr) {
   const Program& P = p->prog;
-  DevState& S = state_of(p);
-  const DevLayout& L = S.lay;
+  const DevLayout& L = state_of(p).lay;
   if (!skip_lds && !L.lds_comps.empty())
     JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off), int(L.lds_comps.size()),
                              reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), stream));
   for (size_t c = 0; c < P.comps.size(); ++c) {
     const ComponentProgram& cp = P.comps[c];
     if (cp.lds_resident) continue;
-    unsigned char* out = ws + L.out_off + size_t(cp.out_off) * 16;
-    JF_HIP(launch_zero(out, cp.out_len, stream));
-    // depth-first walk over the levels
-    struct Frame {
-      int lv;
-      int v;
-      const void* parent;
-      long long base;
-    };
-    std::vector<Frame> stack;
-    stack.push_back({0, 0, nullptr, 0});
-    while (!stack.empty()) {
-      Frame f = stack.back();
-      stack.pop_back();
-      const Level& lev = cp.levels[f.lv];
-      if (f.v + 1 < lev.nvar) stack.push_back({f.lv, f.v + 1, f.parent, f.base});
-      const void* cur = f.parent;
-      if (!cur) {
-        const Step& s0 = cp.steps[lev.first < lev.last ? lev.first : 0];
-        cur = ws + L.const_off + (s0.in_prec == P_C64 ? 16 : 0);
-      }
-      unsigned char* b0 = ws + L.level_buf[c][2 * f.lv];
-      unsigned char* b1 = ws + L.level_buf[c][2 * f.lv + 1];
-      const long long base = f.base + f.v * lev.out_stride;
-      for (int si = lev.first; si < lev.last; ++si) {
-        const Step& st = cp.steps[si];
-        void* dst;
-        if (st.final_step) {
-          dst = out + size_t(base) * 16;
-        } else if (st.inplace_ok && st.in_prec == st.out_prec && (cur == b0 || cur == b1)) {
-          dst = const_cast<void*>(cur);
-        } else {
-          dst = (cur == b0) ? b1 : b0;
-        }
-        const int var = (si == lev.first && lev.site >= 0) ? f.v : 0;
-        const StepDesc* dd = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][si]);
-        const StepDesc* hd = reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][si]]);
-        const void* B = ws + L.step_b[c][si][var];
-        if (tune && !tune->done[c][si]) {
-          jf_status ts = tune_step(const_cast<StepDesc*>(hd), dd, cur, dst, B, stream, tune->reps, dst == cur);
-          if (ts != JF_OK) return ts;
-          tune->done[c][si] = 1;
-        }
-        if (prof) {
-          hipEvent_t a, b;
-          JF_HIP(hipEventCreate(&a));
-          JF_HIP(hipEventCreate(&b));
-          set_launch_events(a, b);
-          const hipError_t le = launch_step(dd, *hd, cur, dst, B, stream);
-          set_launch_events(nullptr, nullptr);
-          JF_HIP(le);
-          prof->ev.push_back(a);
-          prof->ev.push_back(b);
-          prof->bytes += st.bytes;
-          prof->flops += st.flops;
-          jf_step_profile r = {};
-          r.flops = st.flops;
-          r.bytes = st.bytes;
-          r.kS = st.kS;
-          r.kN = st.kN;
-          r.L = st.L;
-          r.mode = hd->mode;
-          r.variant = resolve_variant(*hd);
-          r.component = int(c);
-          prof->rec.push_back(r);
-        } else {
-          JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
-        }
-        cur = dst;
-      }
-      if (f.lv + 1 < (int)cp.levels.size()) stack.push_back({f.lv + 1, 0, cur, base});
-    }
-    JF_HIP(launch_sumsq(out, cp.out_len, reinterpret_cast<double*>(ws + L.sums_off) + 4 * c, stream));
+    jf_status st = enqueue_component(p, ws, stream, c, prof, tune);
+    if (st != JF_OK) return st;
+    JF_HIP(launch_sumsq(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
+                        reinterpret_cast<double*>(ws + L.sums_off) + 4 * c, stream));
   }
   return JF_OK;
 }
@@ -611,6 +636,153 @@ extern "C" jf_status jf_set_kernel_variant(jf_plan* p, int variant) {
       hd->variant = variant_applies(*hd, variant) ? variant : KV_AUTO;
     }
   S.variant_gen = g_variant_gen.fetch_add(1);
+  return JF_OK;
+}
+
+// Definition 1 decided with early stopping (Algorithm I, Section IV-A: the terms are
+// nonnegative, so a running sum above 1 - eps proves equivalence).  Every component but the one
+// with the most depth-first leaves runs in full; that one runs leaf by leaf.  After each leaf:
+//   lower = a * prod_{other c} S_c * S_last(partial)           (the terms done so far)
+//   upper = lower + (mass of the leaves not run) * prod_{sites outside} sum_j ||K_j||^2
+// because |t_k|^2 = |tr(U^dagger E_k)|^2 / d^2 <= prod_i ||K_{k_i}||^2 for every Kraus tuple.
+extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, size_t ws_bytes, void* stream_v,
+                                           jf_decision* out) {
+  if (!p || !out || !(eps > 0.0) || !(eps <= 1.0)) {
+    set_error("jf_decide_equivalence: NULL argument or eps outside (0, 1]");
+    return JF_E_ARG;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  jf_status st = check_ws(p, ws, ws_bytes);
+  if (st != JF_OK) return st;
+  st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  const Program& P = p->prog;
+  const DevLayout& L = state_of(p).lay;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  // arithmetic margin of the form (the parity bar of its results)
+  const double margin = P.opt.dtype == JF_C128 ? 1e-12 : P.opt.dtype == JF_C64 ? 1e-6 : 3e-5;
+  const double thr = 1.0 - eps;
+  jf_decision d = {};
+  d.margin = margin;
+  d.leaves_total = P.work_items;
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  JF_HIP(hipEventRecord(e0, stream));
+  auto decide = [&](double lo, double hi) {
+    if (lo - margin > thr) return 1;
+    if (hi + margin <= thr) return 0;
+    return -1;
+  };
+  int last = -1;
+  long long most = 1;
+  if (P.opt.alg == 1)
+    for (size_t c = 0; c < P.comps.size(); ++c)
+      if (!P.comps[c].lds_resident && P.comps[c].leaves > most) {
+        most = P.comps[c].leaves;
+        last = int(c);
+      }
+  if (last < 0) {  // one pass computes every term
+    st = enqueue_program(p, w, stream);
+    if (st != JF_OK) return st;
+    jf_result r;
+    st = read_results(p, w, stream, &r, nullptr);
+    if (st != JF_OK) return st;
+    d.fj_lower = d.fj_upper = r.fj;
+    d.leaves_run = d.leaves_total;
+    d.decision = decide(r.fj, r.fj);
+  } else {
+    // everything except the last component, in full
+    if (!L.lds_comps.empty())
+      JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(w + L.lds_items_off), int(L.lds_comps.size()),
+                               reinterpret_cast<const LdsStep*>(w + L.lds_steps_off), stream));
+    for (size_t c = 0; c < P.comps.size(); ++c) {
+      const ComponentProgram& cp = P.comps[c];
+      if (cp.lds_resident || int(c) == last) continue;
+      st = enqueue_component(p, w, stream, c, nullptr, nullptr);
+      if (st != JF_OK) return st;
+      JF_HIP(launch_sumsq(w + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
+                          reinterpret_cast<double*>(w + L.sums_off) + 4 * c, stream));
+    }
+    std::vector<double> sums(4 * P.comps.size());
+    JF_HIP(hipMemcpyAsync(sums.data(), w + L.sums_off, sums.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    JF_HIP(hipStreamSynchronize(stream));
+    const double sc = std::exp2(P.log2_scale);
+    double prod_other = sc * sc * std::norm(P.scalar);
+    for (size_t c = 0; c < P.comps.size(); ++c)
+      if (int(c) != last) prod_other *= sums[4 * c] + sums[4 * c + 1];
+    // masses: sites of the last component, and the rest
+    const ComponentProgram& cp = P.comps[last];
+    double mass_outside = 1.0, mass_unsliced = 1.0;
+    std::vector<char> sliced(P.site_norm2.size(), 0);
+    for (const Level& lev : cp.levels)
+      if (lev.site >= 0) sliced[lev.site] = 1;
+    for (size_t i = 0; i < P.site_norm2.size(); ++i) {
+      double t = 0;
+      for (double x : P.site_norm2[i]) t += x;
+      if (P.site_comp[i] != last) mass_outside *= t;
+      else if (!sliced[i]) mass_unsliced *= t;
+    }
+    double mass_total = mass_unsliced;
+    for (const Level& lev : cp.levels)
+      if (lev.site >= 0) {
+        double t = 0;
+        for (double x : P.site_norm2[lev.site]) t += x;
+        mass_total *= t;
+      }
+    // the last component, leaf by leaf (depth first, prefixes kept in the level buffers)
+    unsigned char* out_last = w + L.out_off + size_t(cp.out_off) * 16;
+    double* sums_last = reinterpret_cast<double*>(w + L.sums_off) + 4 * last;
+    JF_HIP(launch_zero(out_last, cp.out_len, stream));
+    const int nl = int(cp.levels.size());
+    std::vector<int> v(nl, 0);
+    std::vector<const void*> end(nl, nullptr);
+    std::vector<long long> base(nl, 0);
+    int from = 0;
+    double mass_done = 0;
+    d.decision = -1;
+    while (true) {
+      for (int lv = from; lv < nl; ++lv) {
+        base[lv] = (lv ? base[lv - 1] : 0) + v[lv] * cp.levels[lv].out_stride;
+        st = enqueue_level(p, w, stream, size_t(last), lv, v[lv], lv ? end[lv - 1] : nullptr, base[lv], &end[lv],
+                           nullptr, nullptr);
+        if (st != JF_OK) return st;
+      }
+      JF_HIP(launch_sumsq(out_last, cp.out_len, sums_last, stream));
+      double part[2];
+      JF_HIP(hipMemcpyAsync(part, sums_last, sizeof(part), hipMemcpyDeviceToHost, stream));
+      JF_HIP(hipStreamSynchronize(stream));
+      double m = mass_unsliced;
+      for (int lv = 0; lv < nl; ++lv)
+        if (cp.levels[lv].site >= 0) {
+          const auto& nrm = P.site_norm2[cp.levels[lv].site];
+          m *= v[lv] < int(nrm.size()) ? nrm[v[lv]] : 0.0;  // padding variants are zero operators
+        }
+      mass_done += m;
+      ++d.leaves_run;
+      d.fj_lower = prod_other * (part[0] + part[1]);
+      d.fj_upper = d.fj_lower + std::max(0.0, mass_total - mass_done) * mass_outside;
+      d.decision = decide(d.fj_lower, d.fj_upper);
+      if (d.decision >= 0) break;
+      // next leaf in depth-first order
+      int lv = nl - 1;
+      while (lv >= 0 && v[lv] + 1 >= cp.levels[lv].nvar) --lv;
+      if (lv < 0) break;
+      ++v[lv];
+      for (int k = lv + 1; k < nl; ++k) v[k] = 0;
+      from = lv;
+    }
+    d.leaves_run += P.work_items - cp.leaves;  // the other components ran in full
+    if (d.leaves_run == P.work_items) d.fj_upper = d.fj_lower;  // every term is in
+  }
+  JF_HIP(hipEventRecord(e1, stream));
+  JF_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  JF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  d.seconds = ms * 1e-3;
+  *out = d;
   return JF_OK;
 }
 

@@ -155,6 +155,7 @@ struct Program {
   std::vector<ComponentProgram> comps;
   std::vector<int> site_nk;        // actual Kraus counts per site (time order)
   std::vector<int> site_comp;      // component holding each site (-1: none)
+  std::vector<std::vector<double>> site_norm2;  // squared operator norm of every Kraus operator
   long long kraus_terms = 1;
   int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0;
   double planner_seconds = 0;

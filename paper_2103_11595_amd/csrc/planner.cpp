@@ -169,6 +169,17 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   P.scalar = net.scalar;
   P.site_nk = net.site_nk;
   P.site_comp.assign(c.sites.size(), -1);
+  // ||K||^2 (largest eigenvalue of K^dagger K) of every Kraus operator: |t_k|^2 <= prod_i ||K_{k_i}||^2
+  for (const NoiseSite& ns : c.sites) {
+    std::vector<double> v;
+    for (int j = 0; j < ns.nk; ++j) {
+      const cd* K = &ns.kraus[size_t(4) * j];
+      const double a = std::norm(K[0]) + std::norm(K[2]), d = std::norm(K[1]) + std::norm(K[3]);
+      const cd b = std::conj(K[0]) * K[1] + std::conj(K[2]) * K[3];
+      v.push_back(0.5 * (a + d) + std::sqrt(0.25 * (a - d) * (a - d) + std::norm(b)));
+    }
+    P.site_norm2.push_back(v);
+  }
   for (int nk : net.site_nk) P.kraus_terms *= nk;
 
   const bool low = opt.dtype != JF_C128;

@@ -87,6 +87,14 @@ class jf_step_profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class jf_decision(C.Structure):
+    _fields_ = [("decision", C.c_int), ("fj_lower", C.c_double), ("fj_upper", C.c_double), ("margin", C.c_double),
+                ("leaves_run", C.c_longlong), ("leaves_total", C.c_longlong), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # jf_kernel_variant
 KV_AUTO, KV_STAGED_256, KV_STAGED_512, KV_DIRECT_256, KV_DIRECT_512, KV_FMA, KV_GAUSS_256, KV_GAUSS_512 = range(8)
 KERNEL_VARIANTS = {"auto": KV_AUTO, "staged256": KV_STAGED_256, "staged512": KV_STAGED_512,
@@ -96,7 +104,8 @@ KERNEL_VARIANTS = {"auto": KV_AUTO, "staged256": KV_STAGED_256, "staged512": KV_
 EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_stats_get",
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
-           "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant"]
+           "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant",
+           "jf_decide_equivalence"]
 
 _lib = None
 
@@ -136,6 +145,7 @@ def lib():
     L.jf_profile_steps.argtypes = [vp, vp, sz, vp, C.POINTER(jf_step_profile), C.c_int, C.POINTER(C.c_int)]
     L.jf_autotune.argtypes = [vp, vp, sz, vp, C.c_int]
     L.jf_set_kernel_variant.argtypes = [vp, C.c_int]
+    L.jf_decide_equivalence.argtypes = [vp, C.c_double, vp, sz, vp, C.POINTER(jf_decision)]
     for name in EXPORTS:
         if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
@@ -379,6 +389,16 @@ def jf_set_kernel_variant(plan: Plan, variant) -> None:
     """Force one kernel (name from KERNEL_VARIANTS or its number) on every step it can run."""
     v = KERNEL_VARIANTS[variant] if isinstance(variant, str) else int(variant)
     _check(lib().jf_set_kernel_variant(plan.ptr, v))
+
+
+def jf_decide_equivalence(plan: Plan, eps: float, ws=None, stream=None) -> dict:
+    """Definition 1 with early stopping and a two-sided bound (decision 1 / 0 / -1)."""
+    if ws is None:
+        ws = workspace(plan.info()["workspace_bytes"])
+    r = jf_decision()
+    _check(lib().jf_decide_equivalence(plan.ptr, float(eps), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_ptr(stream), C.byref(r)))
+    return r.as_dict()
 
 
 def jf_is_equivalent(result: dict, eps: float) -> bool:

@@ -382,3 +382,28 @@ def test_auto_algorithm_on_the_36_qubit_chain():
     got = jf.fidelity(inst, 0, "c64")["fj"]
     say("auto chose Algorithm", p.alg)
     assert abs(got - want) <= TOL["c64"]
+
+
+def test_decide_equivalence_early_stop_and_bounds():
+    """Definition 1 with early stopping on a plan sliced into depth-first leaves: the bounds
+    bracket the oracle's F_J whenever the call returns, and the decision agrees with it."""
+    inst = gen.random_circuit(5, 80, 5, 1e-3, 0.1, 77)
+    ref = dense.fidelity_alg1(inst)["fj"]
+    need = int(jf.plan(inst, 1, "c128").info()["max_log2_intermediate"])
+    for dtype in ("c128", "c64"):
+        p = jf.plan(inst, 1, dtype, max_log2=need - 2)
+        assert p.info()["work_items"] > 1
+        ws = jf.workspace(p.info()["workspace_bytes"])
+        for eps in (0.5, 1 - ref + 0.01, 1 - ref - 0.01, 1e-6):
+            d = jf.jf_decide_equivalence(p, eps, ws)
+            say("eps", eps, d)
+            m = d["margin"]
+            assert d["fj_lower"] - m <= ref <= d["fj_upper"] + m
+            assert d["decision"] == (1 if ref > 1 - eps else 0)
+            if eps == 0.5:
+                assert d["leaves_run"] < d["leaves_total"]   # the no-error leaf alone decides it
+    # one-leaf plan: one pass, F_J decides
+    p = jf.plan(gen.config1(), 1, "c128")
+    d = jf.jf_decide_equivalence(p, 0.05)
+    assert d["decision"] == 1 and abs(d["fj_lower"] - dense.fidelity_alg1(gen.config1())["fj"]) < 1e-12
+    assert jf.jf_decide_equivalence(p, 0.019)["decision"] == 0   # F_J = 0.9801 < 0.981
