@@ -113,6 +113,8 @@ typedef struct jf_plan jf_plan;
                                   Section IV-C that cancels adjacent mutually inverse gates) */
 #define JF_FLAG_NO_FUSE   2u   /* one contraction step per network tensor (no block fusion) */
 #define JF_FLAG_NO_BATCH  4u   /* slice every Kraus index (one DFS leaf per Kraus tuple) */
+#define JF_FLAG_GRAPH     8u   /* jf_fidelity_alg1 / alg2 capture the step program into a hipGraph
+                                  and replay it (see there) */
 /* Search effort of the planner: JF_FLAG_EFFORT(e), e = 1..15, runs 2^(e+5) randomised greedy
  * restarts per component (default, e = 0 in the flags: 2^16).  More restarts find cheaper
  * contraction orders; the plan is reproducible for a given effort. */
@@ -178,12 +180,18 @@ long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
  *   term_traces      optional host array of 2*kraus_terms doubles: t_k/d = tr(U^dagger E_k)/d
  *                    as (re, im), tuples in lexicographic order of the site indices with the
  *                    first site (in time order) most significant.
+ * Plans made with JF_FLAG_GRAPH capture the step program into a hipGraph on the first call for a
+ * (workspace, stream, kernel choice) and replay it in later calls; with the NULL stream such a
+ * plan uses a stream of its own, ordered after the work already on the NULL stream.  (On MI355X
+ * replay measured no faster than eager launches for these programs, whose cost per step is on
+ * the GPU side, and the NULL-stream hand-off adds ~40 us.)  The call synchronises before returning.
  * Errors: JF_E_ARG (not an Alg I plan), JF_E_OOM (workspace too small), JF_E_HIP.
  */
 jf_status jf_fidelity_alg1(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
                            jf_result* out, double* term_traces);
 
-/* jf_fidelity_alg2 -- run an Algorithm II plan: F_J = Re(T)/d^2, |Im T|/d^2 reported. */
+/* jf_fidelity_alg2 -- run an Algorithm II plan: F_J = Re(T)/d^2, |Im T|/d^2 reported.  Graph
+ * capture and streams as jf_fidelity_alg1. */
 jf_status jf_fidelity_alg2(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
                            jf_result* out);
 

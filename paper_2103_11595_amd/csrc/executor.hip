@@ -47,6 +47,13 @@ struct DevState {
   std::vector<const jf_plan*> graph_plans;  // the batch the cached graph was captured for
   std::vector<unsigned> graph_gens;         // and the kernel-choice generation of each plan
   unsigned variant_gen = 0;                 // bumped whenever a step's kernel choice changes
+  // single-plan runs: the step program captured once per (workspace, stream, kernel choice)
+  hipGraphExec_t run_graph = nullptr;
+  const void* run_graph_ws = nullptr;
+  hipStream_t run_graph_stream = nullptr;
+  unsigned run_graph_gen = 0;
+  hipStream_t own_stream = nullptr;         // used when the caller passes the null stream
+  hipEvent_t ev_order = nullptr, ev0 = nullptr, ev1 = nullptr;
 };
 
 std::atomic<unsigned> g_variant_gen{1};
@@ -496,26 +503,69 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
   return JF_OK;
 }
 
+// One run of a plan.  With JF_FLAG_GRAPH the step program is captured into a hipGraph on the first
+// run for a (workspace, stream, kernel choice) and replayed after that (the per-step cost here is
+// on the GPU side, so replay saves little; see the flag).  The null stream cannot be captured: then
+// the plan's own stream runs the graph, ordered after the work already on the null stream.
 jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_result* out, double* terms) {
   jf_status st = check_ws(p, ws, ws_bytes);
   if (st != JF_OK) return st;
   st = upload(p, ws, stream);
   if (st != JF_OK) return st;
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
-  JF_HIP(hipEventRecord(e0, stream));
-  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream);
-  if (st != JF_OK) return st;
-  JF_HIP(hipEventRecord(e1, stream));
+  DevState& S = state_of(p);
+  if (!S.ev0) {
+    JF_HIP(hipEventCreate(&S.ev0));
+    JF_HIP(hipEventCreate(&S.ev1));
+    JF_HIP(hipEventCreateWithFlags(&S.ev_order, hipEventDisableTiming));
+  }
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const bool graph = (p->prog.opt.flags & JF_FLAG_GRAPH) != 0;
+  hipStream_t s = stream;
+  if (graph && stream == nullptr) {
+    if (!S.own_stream) JF_HIP(hipStreamCreateWithFlags(&S.own_stream, hipStreamNonBlocking));
+    JF_HIP(hipEventRecord(S.ev_order, nullptr));
+    JF_HIP(hipStreamWaitEvent(S.own_stream, S.ev_order, 0));
+    s = S.own_stream;
+  }
+  if (graph && (!S.run_graph || S.run_graph_ws != ws || S.run_graph_stream != s || S.run_graph_gen != S.variant_gen)) {
+    if (S.run_graph) {
+      hipGraphExecDestroy(S.run_graph);
+      S.run_graph = nullptr;
+    }
+    hipGraph_t g;
+    JF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    st = enqueue_program(p, w, s);
+    const hipError_t ce = hipStreamEndCapture(s, &g);
+    if (st != JF_OK) return st;
+    if (ce != hipSuccess) {
+      set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      return JF_E_HIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&S.run_graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      S.run_graph = nullptr;
+      set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      return JF_E_HIP;
+    }
+    S.run_graph_ws = ws;
+    S.run_graph_stream = s;
+    S.run_graph_gen = S.variant_gen;
+  }
+  JF_HIP(hipEventRecord(S.ev0, s));
+  if (graph) {
+    JF_HIP(hipGraphLaunch(S.run_graph, s));
+  } else {
+    st = enqueue_program(p, w, s);
+    if (st != JF_OK) return st;
+  }
+  JF_HIP(hipEventRecord(S.ev1, s));
   jf_result r;
-  st = read_results(p, static_cast<unsigned char*>(ws), stream, &r, terms);
+  st = read_results(p, w, s, &r, terms);
   if (st != JF_OK) return st;
   float ms = 0;
-  JF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  JF_HIP(hipEventElapsedTime(&ms, S.ev0, S.ev1));
   r.seconds = ms * 1e-3;
-  JF_HIP(hipEventDestroy(e0));
-  JF_HIP(hipEventDestroy(e1));
   *out = r;
   return JF_OK;
 }
@@ -925,6 +975,13 @@ extern "C" void jf_free_plan(jf_plan* p) {
   if (p->dev) {
     auto* s = static_cast<DevState*>(p->dev);
     if (s->graph) hipGraphExecDestroy(s->graph);
+    if (s->run_graph) hipGraphExecDestroy(s->run_graph);
+    if (s->own_stream) {
+      hipStreamSynchronize(s->own_stream);
+      hipStreamDestroy(s->own_stream);
+    }
+    for (hipEvent_t e : {s->ev0, s->ev1, s->ev_order})
+      if (e) hipEventDestroy(e);
     {
       std::lock_guard<std::mutex> g(g_upload_mu);
       for (auto it = g_last_upload.begin(); it != g_last_upload.end();)

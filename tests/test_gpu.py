@@ -407,3 +407,29 @@ def test_decide_equivalence_early_stop_and_bounds():
     d = jf.jf_decide_equivalence(p, 0.05)
     assert d["decision"] == 1 and abs(d["fj_lower"] - dense.fidelity_alg1(gen.config1())["fj"]) < 1e-12
     assert jf.jf_decide_equivalence(p, 0.019)["decision"] == 0   # F_J = 0.9801 < 0.981
+
+
+def test_graph_replays_match_eager_runs():
+    """Plans made with JF_FLAG_GRAPH replay a captured hipGraph: every replay, with eager runs,
+    autotuning (which re-captures) and host synchronisations in between, equals the eager result
+    bitwise."""
+    import torch
+    inst = _variant_instance(2)
+    for dtype in ("c128", "c64"):
+        eager_plan = jf.plan(inst, 1, dtype)
+        ws = jf.workspace(eager_plan.info()["workspace_bytes"])
+        want = jf.jf_fidelity_alg1(eager_plan, ws, want_terms=True)
+        p = jf.plan(inst, 1, dtype, flags=jf.JF_FLAG_GRAPH)
+        ws2 = jf.workspace(p.info()["workspace_bytes"])
+        side = torch.cuda.Stream()
+        for i in range(4):
+            stream = side if i % 2 else None          # the null stream takes the plan's own stream
+            got = jf.jf_fidelity_alg1(p, ws2, stream, want_terms=True)
+            assert got["fj"] == want["fj"] and np.array_equal(got["terms"], want["terms"]), (dtype, i)
+            jf.jf_fidelity_alg1(eager_plan, ws, want_terms=True)
+            torch.cuda.synchronize()
+        jf.jf_autotune(p, ws2)
+        a = jf.jf_fidelity_alg1(p, ws2, want_terms=True)
+        b = jf.jf_fidelity_alg1(p, ws2, side, want_terms=True)
+        assert a["fj"] == b["fj"] and np.array_equal(a["terms"], b["terms"])
+        assert abs(a["fj"] - want["fj"]) <= TOL[dtype]
