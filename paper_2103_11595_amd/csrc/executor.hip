@@ -1,7 +1,10 @@
 // GPU executor: uploads a plan's step descriptors and operator blocks into the caller's
 // workspace, walks the depth-first tree of sliced Kraus sites (every prefix computed once and
-// kept in its level buffer), launches one k_absorb per step, reduces each component's output in
-// FP64 and assembles F_J on the host from the few FP64 numbers copied back.
+// kept in its level buffer), launches one step kernel per step, reduces each component's output
+// in FP64 and assembles F_J on the host from the few FP64 numbers copied back.  Also here: the
+// batched submission (one persistent launch for the small components, hipGraph capture), the
+// kernel autotuner, per-launch profiling, the early Definition 1 decision, and the FP32 rounding
+// of operator blocks.
 //
 // Workspace layout (every region 256-byte aligned):
 //   [step descriptors][operator pools][constants][level buffers][component outputs][sums]

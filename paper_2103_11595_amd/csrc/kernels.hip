@@ -1,12 +1,20 @@
 // HIP kernels (gfx950) of the contraction executor.
 //
-// k_absorb: one contraction step of the running intermediate A with a small operator B,
+// Every step kernel computes one contraction step of the running intermediate A with a small
+// operator B,
 //   C[f, n] = sum_s A[f, s] * B[s, n],
 // where f, s, n are bit-fields of the tensors' element indices scattered over arbitrary bit
-// positions (see StepDesc).  A workgroup stages a tile of A -- 2^L rows (the lowest free bits,
-// so global loads and stores are contiguous runs) times all K contracted combinations -- in LDS,
-// multiplies it by B held in LDS, and writes the 2^L x Nn output tile.  Tiles are disjoint, so
-// a step whose output layout equals its input layout runs in place.
+// positions (see StepDesc).  The work is cut into tiles of 2^L rows (the lowest free bits, so
+// 16 consecutive rows are one contiguous run) times all K contracted combinations; tiles are
+// disjoint, so a step whose output layout equals its input layout runs in place.  Kernels:
+//   k_absorb, k_absorb_f32x2, k_absorb_bf16x3   vector FMA on a tile staged in LDS
+//   k_absorb_mfma        matrix cores on the real embedding, tile staged in LDS
+//   k_absorb_mfma_rd     matrix cores on the real embedding, operands straight into registers
+//   k_absorb_mfma_gauss  matrix cores, three real products per complex one, register-direct
+//   k_absorb_bf16x3_mfma BF16 matrix cores, three products per real product
+//   k_persistent         whole small components in one workgroup's LDS
+//   k_sumsq, k_zero      the FP64 double-double sum of |t|^2 and a graph-safe fill
+// launch_step picks the kernel of a step (its variant, or the fixed rule).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
