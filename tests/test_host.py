@@ -161,3 +161,40 @@ def test_auto_algorithm_keeps_the_cheaper_plan():
         got = p.emulate()
         fj = float(np.sum(np.abs(got) ** 2)) if p.alg == 1 else got[0].real
         assert abs(fj - ref) < 1e-12
+
+
+def test_plans_are_reproducible():
+    inst = gen.random_circuit(6, 120, 3, 1e-3, 0.05, 31)
+    a, b = jf.plan(inst, 1, "c64"), jf.plan(inst, 1, "c64")
+    assert a.describe() == b.describe()
+    sa, sb = a.stats(), b.stats()
+    assert {k: v for k, v in sa.items() if k != "planner_seconds"} == {k: v for k, v in sb.items() if k != "planner_seconds"}
+
+
+@pytest.mark.parametrize("effort", [1, 4, 9])
+def test_reduced_search_effort_still_exact(effort):
+    inst = gen.random_circuit(5, 70, 3, 1e-3, 0.1, 40 + effort)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    p = jf.plan(inst, 1, "c128", flags=jf.JF_FLAG_EFFORT(effort))
+    assert np.max(np.abs(p.emulate() - want)) < 1e-12
+
+
+def test_describe_bit_positions_are_consistent():
+    for inst, alg in [(gen.config2(), 1), (gen.config3(), 2), (gen.random_circuit(7, 150, 4, 1e-3, 0.05, 3), 1)]:
+        for d in jf.plan(inst, alg, "c64").describe():
+            assert len(d["rowsA"]) == len(d["rowsC"]) == d["L"]
+            assert len(d["sA"]) == d["kS"] and len(d["nC"]) == d["kN"]
+            a = d["rowsA"] + d["sA"]
+            assert len(set(a)) == len(a) and all(0 <= x < d["rA"] for x in a)
+            c = d["rowsC"] + d["nC"]
+            assert len(set(c)) == len(c) and all(0 <= x < d["rC"] for x in c)
+            assert d["compute"] in ("f64", "f32", "f32x2", "bf16x3")
+
+
+def test_estimated_time_grows_with_the_work():
+    small = jf.plan(gen.random_circuit(6, 80, 2, 1e-3, 0.05, 5), 1, "c64").stats()["est_seconds"]
+    large = jf.plan(gen.config2(), 1, "c64").stats()["est_seconds"]
+    assert 0 < small < large
+    # complex128 moves twice the bytes of complex64 on the same order
+    assert jf.plan(gen.config2(), 1, "c128").stats()["est_seconds"] > large
