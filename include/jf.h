@@ -141,7 +141,7 @@ jf_status jf_load_circuit(int n_qubits, const jf_gate* ideal, int n_ideal,
  * (alg = 2, Section IV-B: q and q' wires, V on q and V* on q', noise as M_N on (q, q')), apply
  * the exact local cancellation of adjacent U^dagger U pairs (Section IV-C), search a greedy
  * minimum-intermediate-size contraction order, slice Kraus indices while the largest
- * intermediate exceeds 2^max_log2_intermediate elements (<= 0 selects 28), fuse consecutive
+ * intermediate exceeds 2^max_log2_intermediate elements (<= 0 selects 30), fuse consecutive
  * steps into small-operator blocks and lower the order to a device step program.
  * alg = 0 plans both algorithms and keeps the one whose step program has the smaller estimated
  * device time (jf_plan_stats.alg tells which; call jf_fidelity_alg1 or _alg2 accordingly).

@@ -42,7 +42,7 @@ extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype 
   PlanOptions opt;
   opt.alg = alg;
   opt.dtype = dtype;
-  opt.cap_log2 = max_log2 > 0 ? max_log2 : 28;
+  opt.cap_log2 = max_log2 > 0 ? max_log2 : 30;  // 8 GiB (c64) / 16 GiB (c128) per buffer: MI355X holds 288 GB
   if (opt.cap_log2 > 36) {
     set_error("jf_plan_contraction: max_log2_intermediate above 36");
     return JF_E_ARG;
