@@ -49,12 +49,16 @@ def cpu_baseline(budget_s: float = 25.0) -> dict:
                       f"(same generator; n=16 infeasible densely), {dt:.1f} s"}
 
 
-def traffic_record(kernel_sha: str):
+def traffic_record(kernel_sha: str, launches: int, algorithmic_bytes: float):
+    """HBM bytes per launch from the committed counter record, if it was taken with the same
+    kernels on the same program (same launches and algorithmic bytes); else None."""
     path = os.path.join(ROOT, "profiles", "traffic_absorb_cfg2.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernels_sha") != kernel_sha:
+    if rec.get("kernels_sha") != kernel_sha or rec.get("launches") != launches:
+        return None
+    if abs(rec.get("algorithmic_bytes_per_launch", 0) * launches - algorithmic_bytes) > 1e-6 * algorithmic_bytes:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -372,7 +376,7 @@ def main():
     for x in main_form["per_step"]:
         kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
     ksha = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
-    traffic = traffic_record(ksha)
+    traffic = traffic_record(ksha, prof["launches"], byts)
     out = {
         "metric": "Kraus-term contractions/s + contraction TFLOP/s, c64 vs c128 at |dF_J|<=1e-6",
         "value": value,

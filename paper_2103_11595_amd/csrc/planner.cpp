@@ -15,6 +15,7 @@
 // the path is computed once and reused by all its Kraus operators -- the shared "computed table"
 // of Section IV-C in the form of a prefix stack.
 #include <algorithm>
+#include <iterator>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -67,7 +68,8 @@ struct Path {
   std::vector<int> order;
   std::vector<int> width;   // width of T after each step (all legs, open included)
   std::vector<int> uni;     // legs touched by each step (|T| + new)
-  double cost = 0;
+  double cost = 0;          // sum of 2^uni: the unfused work, used to guide the greedy search
+  double est = 0;           // cost-model time of the fused, sliced program (ranks the restarts)
   int maxw = 0;
 };
 
@@ -227,7 +229,8 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
 
     // ---- greedy path search with restarts
     // A path is feasible when slicing every Kraus index brings it under the cap; among the
-    // feasible paths the cheapest wins (ties: the narrower).
+    // feasible paths the one whose fused, sliced program the cost model prices lowest wins
+    // (ties: the smaller unfused work).
     Path best;
     best.cost = 1e300;
     bool have = false;
@@ -240,6 +243,134 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
       return w;
     };
+    // Cost-model time of the program a path lowers to: the slicing, precision switch and block
+    // fusion below, decided on leg sets only (no tensor data), each step priced like the real
+    // lowering prices it.  Used only to rank candidate paths; the lowering itself decides again.
+    // Legs are the component's local ids; per tensor, its legs with and without Kraus-index legs.
+    std::vector<std::vector<int>> legs_novar(N);
+    for (int i = 0; i < N; ++i) {
+      const Tensor* t = L.ts[i];
+      for (size_t j = 0; j < t->legs.size(); ++j)
+        if (std::find(t->var_legs.begin(), t->var_legs.end(), t->legs[j]) == t->var_legs.end())
+          legs_novar[i].push_back(L.legs[i][j]);
+    }
+    auto fused_estimate = [&](const Path& p) -> double {
+      std::vector<int> sstep(c.sites.size(), -1);
+      for (int k = 0; k < N; ++k) {
+        const Tensor* t = L.ts[p.order[k]];
+        if (opt.alg == 1 && t->site >= 0) sstep[t->site] = k;
+      }
+      std::vector<char> sl(c.sites.size(), 0);
+      std::vector<int> drop(N + 1, 0);  // Kraus legs of sliced sites leaving the width from step k on
+      auto effw = [&](int k) {
+        int w = p.width[k];
+        for (int si : comp_sites)
+          if (sl[si] && sstep[si] <= k) w -= int(net.site_var_legs[si].size());
+        return w;
+      };
+      if (opt.flags & JF_FLAG_NO_BATCH)
+        for (int si : comp_sites)
+          if (!net.site_var_legs[si].empty()) sl[si] = 1;
+      while (true) {
+        int worst = -1, ww = -1;
+        for (int k = 0; k < N; ++k) {
+          const int w = effw(k);
+          if (w > ww) { ww = w; worst = k; }
+        }
+        if (ww <= opt.cap_log2) break;
+        int pickc = -1;
+        for (int si : comp_sites)
+          if (!sl[si] && !net.site_var_legs[si].empty() && sstep[si] <= worst && (pickc < 0 || sstep[si] < sstep[pickc]))
+            pickc = si;
+        if (pickc < 0) return 1e300;
+        sl[pickc] = 1;
+      }
+      int sw = N;
+      if (low) {
+        sw = 0;
+        int prev = 0;
+        std::vector<int> w(N);
+        for (int k = 0; k < N; ++k) w[k] = effw(k);
+        for (int k = N - 1; k >= 0; --k) {
+          prev = k > 0 ? w[k - 1] : 0;
+          if (w[k] > opt.switch_log2 || prev > opt.switch_log2) { sw = k + 1; break; }
+        }
+      }
+      std::vector<char> inT(L.nl, 0), inB(L.nl, 0);
+      int rT = 0;
+      double est = 0, mult = 1;
+      int in_e = low ? 8 : 16;
+      int k = 0, lvstart = 0;
+      std::vector<int> blk, trial;
+      while (k < N) {
+        // a sliced slot starts a level: its Kraus operator is fixed, its Kraus legs are gone
+        const Tensor* t0 = L.ts[p.order[k]];
+        const bool level_head = opt.alg == 1 && t0->site >= 0 && sl[t0->site];
+        if (level_head) {
+          mult *= net.site_nk[t0->site];
+          lvstart = k;
+        }
+        int kend = N;
+        for (int j = k + 1; j < N; ++j) {
+          const Tensor* tj = L.ts[p.order[j]];
+          if (opt.alg == 1 && tj->site >= 0 && sl[tj->site]) { kend = j; break; }
+        }
+        (void)lvstart;
+        while (k < kend) {
+          const bool head = level_head && k == lvstart;
+          blk = head ? legs_novar[p.order[k]] : L.legs[p.order[k]];
+          for (int l : blk) inB[l] = 1;
+          const int rA = rT;
+          int kS = 0;
+          for (int l : blk) kS += inT[l];
+          int kN = int(blk.size()) - kS;
+          int e = k + 1;
+          while (!(opt.flags & JF_FLAG_NO_FUSE) && e < kend) {
+            if (low && e == sw) break;
+            const std::vector<int>& nx = L.legs[p.order[e]];
+            // trial = blk xor nx
+            trial.clear();
+            for (int l : blk)
+              if (std::find(nx.begin(), nx.end(), l) == nx.end()) trial.push_back(l);
+            for (int l : nx)
+              if (!inB[l]) trial.push_back(l);
+            int s2 = 0;
+            for (int l : trial) s2 += inT[l];
+            const int n2 = int(trial.size()) - s2;
+            if (s2 > opt.kmax || n2 > opt.kmax) break;
+            if ((1 << s2) * ((1 << n2) + 16) > 3840) break;
+            const int ein = (low && k >= sw) ? 16 : elem_lo;
+            const int rmid = rA - kS + kN;
+            int s3 = 0;  // legs of nx in T xor blk
+            for (int l : nx) s3 += inT[l] ^ inB[l];
+            const int n3 = int(nx.size()) - s3;
+            const double sep = cm.step(rA, rmid, kS, kN, ein, ein) + cm.step(rmid, rmid - s3 + n3, s3, n3, ein, ein);
+            const double fused = cm.step(rA, rA - s2 + n2, s2, n2, ein, ein);
+            if (fused > sep) break;
+            for (int l : blk) inB[l] = 0;
+            blk.swap(trial);
+            for (int l : blk) inB[l] = 1;
+            kS = s2;
+            kN = n2;
+            ++e;
+          }
+          const bool final_step = (e == N);
+          const int out_e = low ? (((k >= sw) || final_step) ? 16 : 8) : 16;
+          const int rC = rA - kS + kN;
+          const double by = std::ldexp(double(in_e), rA) + std::ldexp(double(out_e), rC);
+          const double fl = 8.0 * std::ldexp(1.0, rA + kN);
+          est += mult * (std::max(by / cm.bw, fl / cm.flops) + cm.launch);
+          for (int l : blk) {
+            inT[l] ^= 1;
+            inB[l] = 0;
+          }
+          rT = rC;
+          in_e = out_e;
+          k = e;
+        }
+      }
+      return est;
+    };
     auto consider = [&](const Path& p) {
       int bw = base_width(p);
       min_base_seen = std::min(min_base_seen, bw);
@@ -249,7 +380,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       if (!have) better = true;
       else if (feas != best_feas) better = feas;
       else if (!feas) better = bw < best_base;
-      else better = p.cost < best.cost * (1 - 1e-12) || (p.cost <= best.cost * (1 + 1e-12) && p.maxw < best.maxw);
+      else better = p.est < best.est * (1 - 1e-12) || (p.est <= best.est * (1 + 1e-12) && p.cost < best.cost);
       if (better) {
         best = p;
         best_base = bw;
@@ -261,7 +392,11 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       if (L.ts[i]->site >= 0) starts.push_back(i);
     if (N <= 24)
       for (int i = 0; i < N; ++i) starts.push_back(i);
-    for (int s : starts) consider(greedy(L, s, rng, 0.0));
+    for (int s : starts) {
+      Path p = greedy(L, s, rng, 0.0);
+      if (base_width(p) <= opt.cap_log2) p.est = fused_estimate(p);
+      consider(p);
+    }
     {
       // Randomised restarts on a thread pool.  Each worker draws its starts and Boltzmann noise
       // from its own seeded generator and keeps its best path; the winner is chosen by the same
@@ -285,10 +420,11 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           Path p = greedy(L, s, wr, 0.5 + ((tries + w) % 5) * 0.5);
           int bw = base_width(p);
           bool feas = bw <= opt.cap_log2, bfeas = bw_base <= opt.cap_log2;
+          if (feas) p.est = fused_estimate(p);
           bool better = !hv || (feas != bfeas ? feas
                                               : (!feas ? bw < bw_base
-                                                       : (p.cost < bestw.cost * (1 - 1e-12) ||
-                                                          (p.cost <= bestw.cost * (1 + 1e-12) && p.maxw < bestw.maxw))));
+                                                       : (p.est < bestw.est * (1 - 1e-12) ||
+                                                          (p.est <= bestw.est * (1 + 1e-12) && p.cost < bestw.cost))));
           if (better) {
             bestw = std::move(p);
             bw_base = bw;
