@@ -116,8 +116,9 @@ typedef struct jf_plan jf_plan;
 #define JF_FLAG_GRAPH     8u   /* jf_fidelity_alg1 / alg2 capture the step program into a hipGraph
                                   and replay it (see there) */
 /* Search effort of the planner: JF_FLAG_EFFORT(e), e = 1..15, runs 2^(e+5) randomised greedy
- * restarts per component (default, e = 0 in the flags: 2^16).  More restarts find cheaper
- * contraction orders; the plan is reproducible for a given effort. */
+ * restarts per component.  The default (e = 0 in the flags) sizes the search to the network:
+ * min(2^17, max(2^12, 8e7 / tensors)) restarts, i.e. 2^17 up to ~600 tensors and 2^16 at ~1200.
+ * More restarts find cheaper contraction orders; the plan is reproducible for a given effort. */
 #define JF_FLAG_EFFORT(e) (((unsigned)(e) & 15u) << 8)
 
 /*

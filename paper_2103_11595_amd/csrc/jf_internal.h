@@ -141,8 +141,8 @@ struct PlanOptions {
   unsigned flags = 0;
   int kmax = 5;                  // fused block limit on |S| and |N|
   int switch_log2 = 12;          // steps whose tensors stay <= 2^switch run in FP64 (closing part)
-  double time_budget_s = 10.0;   // safety cap on the restart search (plans are reproducible below it)
-  int restarts = 65536;          // randomised greedy restarts per component
+  double time_budget_s = 60.0;   // safety cap on the restart search (plans are reproducible below it)
+  int restarts = 0;              // randomised greedy restarts per component (0: sized to the network)
   int threads = 8;               // planner worker threads
   unsigned seed = 12345;
 };

@@ -403,7 +403,10 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       // rule in worker order, so the plan does not depend on timing (the time cap only guards
       // pathological inputs).
       const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
-      const int tries_total = N <= 24 ? 256 : opt.restarts;
+      // default: a fixed amount of search work, ~8e7 tensor absorptions per component (2^17
+      // restarts for a 600-tensor network, 2^16 for 1200), so the plan depends on the network only
+      const int auto_tries = int(std::min(131072.0, std::max(4096.0, 8.0e7 / N)));
+      const int tries_total = N <= 24 ? 256 : (opt.restarts > 0 ? opt.restarts : auto_tries);
       std::vector<Path> wbest(workers);
       std::vector<int> whave(workers, 0);
       auto work = [&](int w) {
