@@ -445,6 +445,47 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         if (whave[w]) consider(wbest[w]);
     }
 
+    // ---- local search on the winner: swap adjacent absorptions while the fused estimate drops
+    // (the greedy choice is made one absorption at a time; a swap can undo a locally narrow but
+    // globally costly choice).  Deterministic; converges in a few sweeps.
+    if (have && best_base <= opt.cap_log2) {
+      auto recompute = [&](Path& p) {
+        std::vector<char> inT(L.nl, 0);
+        int width = 0;
+        p.width.clear();
+        p.uni.clear();
+        p.cost = 0;
+        p.maxw = 0;
+        for (int ci : p.order) {
+          int shared = 0;
+          for (int l : L.legs[ci]) shared += inT[l];
+          const int nnew = int(L.legs[ci].size()) - shared;
+          const int uni = width + nnew;
+          for (int l : L.legs[ci]) inT[l] ^= 1;
+          width = width - shared + nnew;
+          p.width.push_back(width);
+          p.uni.push_back(uni);
+          p.cost += std::ldexp(1.0, uni);
+          p.maxw = std::max(p.maxw, width);
+        }
+      };
+      bool improved = true;
+      for (int sweep = 0; improved && sweep < 8; ++sweep) {
+        improved = false;
+        for (int i = 0; i + 1 < N; ++i) {
+          Path q = best;
+          std::swap(q.order[i], q.order[i + 1]);
+          recompute(q);
+          if (base_width(q) > opt.cap_log2) continue;
+          q.est = fused_estimate(q);
+          if (q.est < best.est * (1 - 1e-9)) {
+            best = std::move(q);
+            improved = true;
+          }
+        }
+      }
+    }
+
     // ---- slicing of Kraus indices
     const Path& pth = best;
     std::vector<int> site_step(c.sites.size(), -1);   // path position of each site's slot
