@@ -445,9 +445,9 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         if (whave[w]) consider(wbest[w]);
     }
 
-    // ---- local search on the winner: swap adjacent absorptions while the fused estimate drops
-    // (the greedy choice is made one absorption at a time; a swap can undo a locally narrow but
-    // globally costly choice).  Deterministic; converges in a few sweeps.
+    // ---- local search on the winner: move single absorptions by up to four places while the
+    // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
+    // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
     if (have && best_base <= opt.cap_log2) {
       auto recompute = [&](Path& p) {
         std::vector<char> inT(L.nl, 0);
@@ -472,17 +472,22 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       bool improved = true;
       for (int sweep = 0; improved && sweep < 8; ++sweep) {
         improved = false;
-        for (int i = 0; i + 1 < N; ++i) {
-          Path q = best;
-          std::swap(q.order[i], q.order[i + 1]);
-          recompute(q);
-          if (base_width(q) > opt.cap_log2) continue;
-          q.est = fused_estimate(q);
-          if (q.est < best.est * (1 - 1e-9)) {
-            best = std::move(q);
-            improved = true;
+        for (int i = 0; i < N; ++i)
+          for (int d = -4; d <= 4; ++d) {  // move absorption i by up to four places
+            const int j = i + d;
+            if (d == 0 || j < 0 || j >= N) continue;
+            Path q = best;
+            const int v = q.order[i];
+            q.order.erase(q.order.begin() + i);
+            q.order.insert(q.order.begin() + j, v);
+            recompute(q);
+            if (base_width(q) > opt.cap_log2) continue;
+            q.est = fused_estimate(q);
+            if (q.est < best.est * (1 - 1e-9)) {
+              best = std::move(q);
+              improved = true;
+            }
           }
-        }
       }
     }
 
