@@ -387,6 +387,10 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         have = true;
       }
     };
+    // restarts: by default a fixed amount of search work, ~8e7 tensor absorptions per component
+    // (2^17 restarts for a 600-tensor network, 2^16 for 1200), so the plan depends on the network only
+    const int auto_tries = int(std::min(131072.0, std::max(4096.0, 8.0e7 / N)));
+    const int restarts_total = N <= 24 ? 256 : (opt.restarts > 0 ? opt.restarts : auto_tries);
     std::vector<int> starts;
     for (int i = 0; i < N; ++i)
       if (L.ts[i]->site >= 0) starts.push_back(i);
@@ -403,10 +407,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       // rule in worker order, so the plan does not depend on timing (the time cap only guards
       // pathological inputs).
       const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
-      // default: a fixed amount of search work, ~8e7 tensor absorptions per component (2^17
-      // restarts for a 600-tensor network, 2^16 for 1200), so the plan depends on the network only
-      const int auto_tries = int(std::min(131072.0, std::max(4096.0, 8.0e7 / N)));
-      const int tries_total = N <= 24 ? 256 : (opt.restarts > 0 ? opt.restarts : auto_tries);
+      const int tries_total = restarts_total;
       std::vector<Path> wbest(workers);
       std::vector<int> whave(workers, 0);
       auto work = [&](int w) {
@@ -448,7 +449,8 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // ---- local search on the winner: move single absorptions by up to four places while the
     // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
     // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
-    if (have && best_base <= opt.cap_log2) {
+    // Part of a thorough search only (>= 2^12 restarts): its sweeps cost O(tensors^2).
+    if (have && best_base <= opt.cap_log2 && (restarts_total >= 4096 || N <= 24)) {
       auto recompute = [&](Path& p) {
         std::vector<char> inT(L.nl, 0);
         int width = 0;
