@@ -124,6 +124,34 @@ __device__ __forceinline__ void load_tables(const StepDesc* __restrict__ d, Tabl
   }
 }
 
+// Tile base addresses of the MFMA kernels by table look-up: the tile index t is cut into 4-bit
+// digits and ch[c][m] holds the address bits that digit c with value m sets (bit b of the digit
+// sets bit hi[4 c + b]).  base(t) is then the OR of DMAXHI / 4 independent LDS reads (rows past
+// the tile bits are zero), where a loop over the bits of t would chain nHi dependent ones.
+constexpr int NDIG = DMAXHI / 4;
+struct TileBases {
+  long long chA[NDIG][16], chC[NDIG][16];
+};
+__device__ __forceinline__ void load_tile_bases(const StepDesc* __restrict__ d, TileBases& tbb, int nHi) {
+  for (int i = threadIdx.x; i < NDIG * 16; i += blockDim.x) {
+    const int c = i >> 4, m = i & 15;
+    long long a = 0, o = 0;
+    for (int b = 0; b < 4; ++b)
+      if (((m >> b) & 1) && 4 * c + b < nHi) {
+        a |= 1LL << d->hiA[4 * c + b];
+        o |= 1LL << d->hiC[4 * c + b];
+      }
+    tbb.chA[c][m] = a;
+    tbb.chC[c][m] = o;
+  }
+}
+__device__ __forceinline__ long long tile_base(const long long (*ch)[16], long long t) {
+  long long b = 0;
+#pragma unroll
+  for (int c = 0; c < NDIG; ++c) b |= ch[c][(t >> (4 * c)) & 15];
+  return b;
+}
+
 // Generic FMA path (FP64, FP32 and the FP32->FP64 closing switch).
 template <typename TI, typename TO, typename TC>
 __global__ __launch_bounds__(256) void k_absorb(const StepDesc* __restrict__ d, const TI* A, TO* C,
@@ -294,12 +322,14 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   constexpr int NW = NT / 64;      // waves
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
+  __shared__ TileBases tbb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
   // M2: MFMA rows of the operator, at least one 16-row block (rows past 2Nn are zero)
   const int K2 = 2 * K, M2 = 2 * Nn < 16 ? 16 : 2 * Nn, KR = K * R;
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
   T* sBt = reinterpret_cast<T*>(smem);            // [k][i] (hi), then [k][i] (lo)
   T* sAr = sBt + (TWO_TERM ? 2 : 1) * K2 * M2;    // [s][r]
   T* sAi = sAr + KR;
@@ -321,15 +351,9 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int Nb = R >> 4;  // MB = M2 / 16 output blocks per row block (the launcher checks)
-  auto base = [&](long long t, const int* hi) {
-    long long b = 0;
-    for (int q = 0; q < nHi; ++q)
-      if ((t >> q) & 1) b |= 1LL << hi[q];
-    return b;
-  };
   C2 stage[MAXE];
   auto fetch = [&](long long t) {
-    const long long bA = base(t, tb.hiA);
+    const long long bA = tile_base(tbb.chA, t);
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
       const int i = threadIdx.x + NT * e;
@@ -339,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   long long t = blockIdx.x;
   if (t < nTiles) fetch(t);
   for (; t < nTiles; t += gridDim.x) {
-    const long long bC = base(t, tb.hiC);
+    const long long bC = tile_base(tbb.chC, t);
     __syncthreads();  // every wave is done with the previous tile's planes
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
@@ -407,11 +431,13 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restric
   constexpr int BT = KT * 4 * M2;                         // operator entries per copy
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
+  __shared__ TileBases tbb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
   const int rbits = L - 4;
   const long long nUnits = d->nTiles << rbits;
   load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
   T* sBt = reinterpret_cast<T*>(smem);  // [4 t + g][i] (hi), then the same for lo
   for (int idx = threadIdx.x; idx < BT; idx += NT) {
     const int kr = idx / M2, i = idx - kr * M2;
@@ -435,20 +461,15 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restric
   __syncthreads();  // offset tables and operator visible to every wave
   const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
   const long long wstride = (long long)gridDim.x * NW;
-  auto base = [&](long long t, const int* hi) {
-    long long b = 0;
-    for (int q = 0; q < nHi; ++q)
-      if ((t >> q) & 1) b |= 1LL << hi[q];
-    return b;
-  };
   auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
   C2 nxt[KQ];
   auto fetch = [&](long long v) {
-    const long long bA = base(v >> rbits, tb.hiA) + tb.offRA[row_of_unit(v)];
+    const long long bA = tile_base(tbb.chA, v >> rbits) + tb.offRA[row_of_unit(v)];
 #pragma unroll
     for (int u = 0; u < KQ; ++u) {
       const int s = 4 * u + g;
-      nxt[u] = s < K ? ld_stream(&A[bA + tb.offS[s]]) : C2{0, 0};
+      const C2 x = ld_stream(&A[bA + tb.offS[s < K ? s : K - 1]]);  // in-bounds address for every lane
+      nxt[u] = s < K ? x : C2{0, 0};
     }
   };
   long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
@@ -477,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restric
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[16 * mb], a, acc[mb]);
     }
-    const long long bC = base(v >> rbits, tb.hiC) + tb.offRC[row_of_unit(v)];
+    const long long bC = tile_base(tbb.chC, v >> rbits) + tb.offRC[row_of_unit(v)];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -512,11 +533,13 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
   constexpr int NW = NT / 64, W = 3 * MB;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
+  __shared__ TileBases tbb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
   const int rbits = L - 4;
   const long long nUnits = d->nTiles << rbits;
   load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
   T* sB = reinterpret_cast<T*>(smem);
   for (int idx = threadIdx.x; idx < KQ * 64 * W; idx += NT) {
     const int t = idx / (64 * W), rem = idx - t * 64 * W;
@@ -533,20 +556,15 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
   __syncthreads();  // offset tables and operator visible to every wave
   const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
   const long long wstride = (long long)gridDim.x * NW;
-  auto base = [&](long long t, const int* hi) {
-    long long b = 0;
-    for (int q = 0; q < nHi; ++q)
-      if ((t >> q) & 1) b |= 1LL << hi[q];
-    return b;
-  };
   auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
   C2 nxt[KQ];
   auto fetch = [&](long long v) {
-    const long long bA = base(v >> rbits, tb.hiA) + tb.offRA[row_of_unit(v)];
+    const long long bA = tile_base(tbb.chA, v >> rbits) + tb.offRA[row_of_unit(v)];
 #pragma unroll
     for (int u = 0; u < KQ; ++u) {
       const int s = 4 * u + g;
-      nxt[u] = s < K ? ld_stream(&A[bA + tb.offS[s]]) : C2{0, 0};
+      const C2 x = ld_stream(&A[bA + tb.offS[s < K ? s : K - 1]]);  // in-bounds address for every lane
+      nxt[u] = s < K ? x : C2{0, 0};
     }
   };
   long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
@@ -575,7 +593,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
         acc[2][mb] = M::op(bv[2 * MB + mb], as, acc[2][mb]);
       }
     }
-    const long long bC = base(v >> rbits, tb.hiC) + tb.offRC[row_of_unit(v)];
+    const long long bC = tile_base(tbb.chC, v >> rbits) + tb.offRC[row_of_unit(v)];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
 #pragma unroll
@@ -618,12 +636,14 @@ __global__ __launch_bounds__(NT) void k_absorb_bf16x3_mfma(const StepDesc* __res
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
+  __shared__ TileBases tbb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
   const int K2 = 2 * K, M2 = 2 * Nn, KR = K * R;
   const int K2c = (K2 + 31) & ~31, KP = K2c + 8;  // k chunks of 32, row pitch in BF16 elements
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
   unsigned short* sBh = reinterpret_cast<unsigned short*>(smem);  // [i][KP], i < M2
   unsigned short* sBl = sBh + M2 * KP;
   unsigned short* sAh = sBl + M2 * KP;                            // [j][KP], j < R
@@ -645,15 +665,9 @@ __global__ __launch_bounds__(NT) void k_absorb_bf16x3_mfma(const StepDesc* __res
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int Mb = M2 >> 4, Nb = R >> 4;
-  auto base = [&](long long t, const int* hi) {
-    long long b = 0;
-    for (int q = 0; q < nHi; ++q)
-      if ((t >> q) & 1) b |= 1LL << hi[q];
-    return b;
-  };
   float2 stage[MAXE];
   auto fetch = [&](long long t) {
-    const long long bA = base(t, tb.hiA);
+    const long long bA = tile_base(tbb.chA, t);
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
       const int i = threadIdx.x + NT * e;
@@ -663,7 +677,7 @@ __global__ __launch_bounds__(NT) void k_absorb_bf16x3_mfma(const StepDesc* __res
   long long t = blockIdx.x;
   if (t < nTiles) fetch(t);
   for (; t < nTiles; t += gridDim.x) {
-    const long long bC = base(t, tb.hiC);
+    const long long bC = tile_base(tbb.chC, t);
     __syncthreads();  // every wave is done with the previous tile
 #pragma unroll
     for (int e = 0; e < MAXE; ++e) {
@@ -884,8 +898,8 @@ static unsigned resident_grid(const void* kernel, int nt, size_t sm, long long i
   static std::mutex mu;
   static std::map<Key, long long> cache;
   int dev = 0;
-  hipGetDevice(&dev);
   long long cap = 2048;
+  if (hipGetDevice(&dev) != hipSuccess) return unsigned(items < cap ? (items < 1 ? 1 : items) : cap);
   {
     std::lock_guard<std::mutex> lk(mu);
     const Key key{dev, kernel, nt, sm};
