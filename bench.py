@@ -372,6 +372,7 @@ def main():
                             "frac_of_hbm_peak": (sum(x["bytes"] for x in rest) / (rest_ms * 1e-3) / 1e9) / PEAK_HBM_GBS if rest_ms else 0},
     }
     kv_names = {v: k for k, v in jf.KERNEL_VARIANTS.items()}
+    kv_names[jf.KV_CHAIN] = "chain"
     kernels_used = {}
     for x in main_form["per_step"]:
         kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
@@ -410,7 +411,7 @@ def main():
         "kernels_used": kernels_used,
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_absorb (contraction step)", "launches": prof["launches"],
+                     "kernel": "contraction steps (k_absorb*, k_chain)", "launches": prof["launches"],
                      "algorithmic_bytes": byts, "flops": flops, "kernel_ms": kms,
                      "avg_launch_us": kms * 1e3 / max(1, prof["launches"])},
     }

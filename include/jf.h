@@ -115,6 +115,9 @@ typedef struct jf_plan jf_plan;
 #define JF_FLAG_NO_BATCH  4u   /* slice every Kraus index (one DFS leaf per Kraus tuple) */
 #define JF_FLAG_GRAPH     8u   /* jf_fidelity_alg1 / alg2 capture the step program into a hipGraph
                                   and replay it (see there) */
+#define JF_FLAG_NO_CHAIN 16u   /* run every step as its own launch: no chains of in-place complex64
+                                  steps applied to one LDS tile per HBM pass (same results bit for
+                                  bit; chains are the default) */
 /* Search effort of the planner: JF_FLAG_EFFORT(e), e = 1..15, runs 2^(e+5) randomised greedy
  * restarts per component.  The default (e = 0 in the flags) sizes the search to the network:
  * min(2^17, max(2^12, 8e7 / tensors)) restarts, i.e. 2^17 up to ~600 tensors and 2^16 at ~1200.
@@ -168,10 +171,11 @@ typedef struct {
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 
 /* Text description of the lowered program, one line per device step:
- * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes rowsA rowsC sA nC",
- * the last four being comma-separated bit positions (A for tile rows and summed legs, C for tile
- * rows and new legs; "-" when empty).  compute is f64, f32, f32x2 (FP32 with the operator kept as
- * an FP32 pair) or bf16x3.
+ * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes rowsA rowsC sA nC
+ *  chain", rowsA .. nC being comma-separated bit positions (A for tile rows and summed legs, C for
+ * tile rows and new legs; "-" when empty).  compute is f64, f32, f32x2 (FP32 with the operator kept
+ * as an FP32 pair) or bf16x3.  chain is the index (within the component) of the chain the step
+ * belongs to, -1 if it runs as its own launch (see JF_FLAG_NO_CHAIN).
  * Writes at most len bytes (NUL-terminated) and returns the full length needed. Host only. */
 long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
 
@@ -228,7 +232,10 @@ jf_status jf_profile_run(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* str
  * jf_profile_steps -- the same run, reported per launch: out[i] for the i-th contraction-step
  * launch in program order (i < cap), *n_launches = number of launches.  mode is the step's
  * arithmetic (0 FP64, 1 FP32, 2 FP32 in / FP64 out, 3 3xBF16, 4 FP32 with a two-term operator);
- * variant the kernel that ran it (jf_kernel_variant, never AUTO).
+ * variant the kernel that ran it (jf_kernel_variant, never AUTO); steps the number of program
+ * steps the launch ran (1, or the length of a chain: variant JF_KV_CHAIN, kS = kN the largest
+ * summed extent of its steps, L the log2 of its LDS tile, flops the chain's, bytes one read and
+ * one write of the intermediate).
  */
 typedef struct {
   double ms;     /* event-measured duration */
@@ -236,6 +243,7 @@ typedef struct {
   double bytes;  /* algorithmic bytes: input tensor read once, output written once */
   int kS, kN, L; /* log2 of summed, new and per-tile row extents */
   int mode, variant, component;
+  int steps;     /* program steps run by this launch */
 } jf_step_profile;
 jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, jf_step_profile* out,
                            int cap, int* n_launches);
@@ -258,17 +266,23 @@ typedef enum {
   JF_KV_DIRECT_512 = 4,
   JF_KV_FMA = 5,
   JF_KV_GAUSS_256 = 6,
-  JF_KV_GAUSS_512 = 7
+  JF_KV_GAUSS_512 = 7,
+  JF_KV_CHAIN = 8   /* reported by jf_profile_steps only: a chain of in-place complex64 steps
+                       applied to one LDS tile per HBM pass (not a choice for
+                       jf_set_kernel_variant) */
 } jf_kernel_variant;
 
 /*
  * jf_autotune -- the autotuner of the tile / kernel choice.  Runs the plan once on the caller's
  * workspace and stream; on the first visit of each contraction step it times every kernel that
  * can run the step (a warm-up launch, then reps launches between HIP events, on the step's own
- * input and output buffers) and keeps the fastest for all later runs of this plan.  The
+ * input and output buffers) and keeps the fastest for all later runs of this plan; a chain of
+ * steps is timed as one launch against its steps run one launch each (with their tuned kernels)
+ * and the faster is kept.  The
  * workspace contents are undefined afterwards (no result is produced).  Choices are cached for
- * the process by step shape (arithmetic, kS, kN, rows per tile, tile count, in place or not), so
- * plans sharing shapes are tuned once.  Kernels sum in different orders, so a tuned plan may
+ * the process by step shape (arithmetic, kS, kN, rows per tile, tile count, in place or not) and
+ * by chain shape, so plans sharing shapes are tuned once.  A chain computes exactly what its steps
+ * compute with the Gauss kernels (same products in the same order).  Kernels sum in different orders, so a tuned plan may
  * differ from an untuned one in the last bits; replays of a tuned plan are bitwise identical.
  * reps <= 0 means 3.  Synchronises the stream.  Errors: JF_E_ARG, JF_E_OOM (workspace too
  * small), JF_E_HIP.
@@ -277,8 +291,9 @@ jf_status jf_autotune(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream
 
 /*
  * jf_set_kernel_variant -- force one kernel (jf_kernel_variant) on every step it can run; the
- * other steps keep the AUTO rule.  JF_KV_AUTO restores the rule everywhere (and so undoes
- * jf_autotune).  For testing each kernel against the oracle.  Host only.  Errors: JF_E_ARG.
+ * other steps keep the AUTO rule, and chains are split into their steps.  JF_KV_AUTO restores
+ * the rule and the chains everywhere (and so undoes jf_autotune).  For testing each kernel against
+ * the oracle.  Host only.  Errors: JF_E_ARG (JF_KV_CHAIN is not a per-step kernel).
  */
 jf_status jf_set_kernel_variant(jf_plan* plan, int variant);
 

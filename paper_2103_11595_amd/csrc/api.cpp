@@ -165,7 +165,7 @@ extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len
           return b.empty() ? std::string("-") : b;
         };
         out += " " + bits(st.offR_A, st.L) + " " + bits(st.offR_C, st.L) + " " + bits(st.offS_A, st.kS) + " " +
-               bits(st.offN_C, st.kN) + "\n";
+               bits(st.offN_C, st.kN) + " " + std::to_string(st.chain) + "\n";
       }
   }
   if (buf && len > 0) {

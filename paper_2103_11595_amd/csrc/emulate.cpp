@@ -48,6 +48,40 @@ bool validate_program(const Program& P, std::string& why) {
           return false;
         }
     }
+    for (size_t q = 0; q < cp.chains.size(); ++q) {
+      const Chain& ch = cp.chains[q];
+      const int rA = (ch.first >= 0 && ch.first < (int)cp.steps.size()) ? cp.steps[ch.first].rA : -1;
+      bool ok = ch.first >= 0 && ch.last <= (int)cp.steps.size() && ch.last - ch.first >= 2 &&
+                ch.last - ch.first <= CHAIN_MAX_STEPS && ch.T >= 4 && ch.T <= CHAIN_MAX_T &&
+                (int)ch.P.size() == ch.T && (int)ch.hi.size() <= MAXHI && ch.nTiles == (1LL << ch.hi.size()) &&
+                ch.T + (int)ch.hi.size() == rA;
+      std::vector<char> seen(rA > 0 ? rA : 0, 0);
+      for (int b : ch.P) ok = ok && b >= 0 && b < rA && !seen[b] && (seen[b] = 1);
+      for (int b : ch.hi) ok = ok && b >= 0 && b < rA && !seen[b] && (seen[b] = 1);
+      int ops = 0, lvl = -1;
+      for (int s = ch.first; ok && s < ch.last; ++s) {
+        const Step& st = cp.steps[s];
+        ok = chainable(st) && st.chain == int(q) && st.rA == rA && ch.T - st.kS >= 4;
+        for (int b : step_s_positions(st)) ok = ok && std::count(ch.P.begin(), ch.P.end(), b) == 1;
+        ops += 1 << (2 * st.kS);
+        for (size_t l = 0; l < cp.levels.size(); ++l)
+          if (s >= cp.levels[l].first && s < cp.levels[l].last) {
+            if (lvl < 0) lvl = int(l);
+            ok = ok && lvl == int(l);
+          }
+      }
+      if (!ok || ops > CHAIN_MAX_OPS) {
+        why = "chain " + std::to_string(q) + " of component " + std::to_string(c) + " is malformed";
+        return false;
+      }
+    }
+    for (size_t s = 0; s < cp.steps.size(); ++s) {
+      const int q = cp.steps[s].chain;
+      if (q >= 0 && (q >= (int)cp.chains.size() || (int)s < cp.chains[q].first || (int)s >= cp.chains[q].last)) {
+        why = "step " + std::to_string(s) + " names a chain that does not hold it";
+        return false;
+      }
+    }
     for (auto& lv : cp.levels)
       for (int s = lv.first; s < lv.last; ++s) {
         const Step& st = cp.steps[s];
@@ -139,6 +173,41 @@ void emulate_step(const Step& st, const std::vector<cd>& B, const cd* A, cd* C) 
   }
 }
 
+// A chain on the host with the tile-local tables of the chain kernel: per tile, gather 2^T
+// elements, apply every step of the chain in place on the tile, scatter the tile back.
+void emulate_chain(const ComponentProgram& cp, const Chain& ch, const std::vector<const std::vector<cd>*>& Bs,
+                   std::vector<cd>& X) {
+  ChainTables tb;
+  chain_tables(cp, ch, tb);
+  const int E = 1 << ch.T;
+  std::vector<cd> tile(E);
+  for (long long t = 0; t < ch.nTiles; ++t) {
+    long long base = 0;
+    for (size_t b = 0; b < ch.hi.size(); ++b)
+      if ((t >> b) & 1) base |= 1LL << ch.hi[b];
+    auto goff = [&](int l) { return tb.gDig[0][l & 15] + tb.gDig[1][(l >> 4) & 15] + tb.gDig[2][(l >> 8) & 15]; };
+    for (int l = 0; l < E; ++l) tile[l] = X[base + goff(l)];
+    for (int j = 0; j < ch.last - ch.first; ++j) {
+      const Step& st = cp.steps[ch.first + j];
+      const int K = 1 << st.kS, nf = 1 << (ch.T - st.kS);
+      const std::vector<unsigned short>& so = tb.sOff[j];
+      const std::vector<unsigned short>& fd = tb.fDig[j];
+      const std::vector<cd>& B = *Bs[j];
+      std::vector<cd> a(K);
+      for (int f = 0; f < nf; ++f) {
+        const int fl = fd[f & 15] + fd[16 + ((f >> 4) & 15)] + fd[32 + ((f >> 8) & 15)];
+        for (int s = 0; s < K; ++s) a[s] = tile[fl + so[s]];
+        for (int n = 0; n < K; ++n) {
+          cd acc = 0;
+          for (int s = 0; s < K; ++s) acc += a[s] * B[size_t(s) * K + n];
+          tile[fl + so[n]] = acc;
+        }
+      }
+    }
+    for (int l = 0; l < E; ++l) X[base + goff(l)] = tile[l];
+  }
+}
+
 void emulate_level(const ComponentProgram& cp, int lv, const std::vector<cd>& parent, long long out_base,
                    std::vector<cd>& out) {
   const Level& L = cp.levels[lv];
@@ -147,6 +216,14 @@ void emulate_level(const ComponentProgram& cp, int lv, const std::vector<cd>& pa
     for (int si = L.first; si < L.last; ++si) {
       const Step& st = cp.steps[si];
       const std::vector<cd>& B = st.B[si == L.first && L.site >= 0 ? v : 0];
+      if (st.chain >= 0 && cp.chains[st.chain].first == si) {
+        const Chain& ch = cp.chains[st.chain];
+        std::vector<const std::vector<cd>*> Bs;
+        for (int q = ch.first; q < ch.last; ++q) Bs.push_back(&cp.steps[q].B[q == L.first && L.site >= 0 ? v : 0]);
+        emulate_chain(cp, ch, Bs, cur);
+        si = ch.last - 1;
+        continue;
+      }
       if (st.final_step) {
         emulate_step(st, B, cur.data(), out.data() + out_base + v * L.out_stride);
       } else {

@@ -35,6 +35,7 @@ struct DevLayout {
   std::vector<int> lds_comps;                             // components run by the persistent kernel
   int lds_steps = 0;
   std::vector<std::vector<size_t>> step_desc;             // per component, per step: descriptor offset
+  std::vector<std::vector<size_t>> chain_desc;            // per component, per chain: descriptor offset
   std::vector<std::vector<std::vector<size_t>>> step_b;   // per component, step, variant: B offset
   std::vector<std::vector<size_t>> level_buf;             // per component: 2 buffers per level
 };
@@ -56,6 +57,9 @@ struct DevState {
   hipStream_t run_graph_stream = nullptr;
   unsigned run_graph_gen = 0;
   hipStream_t own_stream = nullptr;         // used when the caller passes the null stream
+  // per component, per chain: 1 = run its steps one launch each (the autotuner found the chain
+  // slower, or a kernel variant was forced on every step)
+  std::vector<std::vector<char>> chain_off;
   hipEvent_t ev_order = nullptr, ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -119,6 +123,15 @@ void build_layout(const Program& P, DevState& S) {
       L.step_desc[c].push_back(off);
       off += align256(sizeof(StepDesc));
     }
+  L.chain_desc.resize(P.comps.size());
+  S.chain_off.resize(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    S.chain_off[c].assign(P.comps[c].chains.size(), 0);
+    for (size_t q = 0; q < P.comps[c].chains.size(); ++q) {
+      L.chain_desc[c].push_back(off);
+      off += align256(sizeof(ChainDesc));
+    }
+  }
   L.pool_off = off;
   L.step_b.resize(P.comps.size());
   for (size_t c = 0; c < P.comps.size(); ++c) {
@@ -222,6 +235,31 @@ void build_layout(const Program& P, DevState& S) {
           }
         }
       }
+    }
+  for (size_t c = 0; c < P.comps.size(); ++c)
+    for (size_t q = 0; q < P.comps[c].chains.size(); ++q) {
+      const Chain& ch = P.comps[c].chains[q];
+      ChainTables tb;
+      chain_tables(P.comps[c], ch, tb);
+      ChainDesc d;
+      std::memset(&d, 0, sizeof(d));
+      for (int i = 0; i < 48; ++i) d.gDig[i] = tb.gDig[i / 16][i % 16];
+      for (size_t i = 0; i < ch.hi.size(); ++i) d.hi[i] = ch.hi[i];
+      d.nTiles = ch.nTiles;
+      d.nsteps = ch.last - ch.first;
+      d.T = ch.T;
+      d.nHi = int(ch.hi.size());
+      int boff = 0;
+      for (int j = 0; j < d.nsteps; ++j) {
+        const Step& st = P.comps[c].steps[ch.first + j];
+        d.st[j].kS = st.kS;
+        d.st[j].boff = boff;
+        boff += 1 << (2 * st.kS);
+        for (size_t i = 0; i < tb.sOff[j].size(); ++i) d.st[j].sOff[i] = tb.sOff[j][i];
+        for (int i = 0; i < 48; ++i) d.st[j].fDig[i] = tb.fDig[j][i];
+      }
+      d.ops = boff;
+      std::memcpy(&S.host_image[L.chain_desc[c][q]], &d, sizeof(d));
     }
   double one = 1.0, zero = 0.0;
   float onef = 1.0f, zerof = 0.0f;
@@ -332,6 +370,56 @@ jf_status tune_step(StepDesc* hd, const StepDesc* dd, const void* A, void* C, co
   return JF_OK;
 }
 
+// Process-wide cache of chain decisions (1 = run the steps one launch each), keyed by the chain's
+// tile shape and its steps' shapes and kernels.
+std::map<std::vector<long long>, int> g_chain_cache;
+
+// Time a chain against its steps run one launch each (every step with its tuned kernel, in place
+// on the chain's output after the first) and keep the faster.  Like tune_step, this clobbers the
+// data.
+jf_status tune_chain(jf_plan* p, DevState& S, size_t c, int q, const ChainDesc* dd, const ChainDesc& hd,
+                     const void* A, void* C, const ChainOps& ops, const std::vector<const StepDesc*>& sdd,
+                     const std::vector<const StepDesc*>& shd, hipStream_t stream, int reps) {
+  std::vector<long long> key = {hd.T, hd.nTiles, A == C ? 1 : 0};
+  for (const StepDesc* h : shd) {
+    key.push_back(h->kS);
+    key.push_back(resolve_variant(*h));
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_chain_cache.find(key);
+    if (it != g_chain_cache.end()) {
+      S.chain_off[c][q] = char(it->second);
+      return JF_OK;
+    }
+  }
+  auto run_steps = [&]() -> hipError_t {
+    for (size_t j = 0; j < shd.size(); ++j) {
+      const hipError_t e = launch_step(sdd[j], *shd[j], j == 0 ? A : C, C, ops.B[j], stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0, e1;
+  JF_HIP(hipEventCreate(&e0));
+  JF_HIP(hipEventCreate(&e1));
+  float ms[2] = {0, 0};
+  for (int mode = 0; mode < 2; ++mode) {
+    JF_HIP(mode == 0 ? launch_chain(dd, hd, A, C, ops, stream) : run_steps());  // warm-up
+    JF_HIP(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) JF_HIP(mode == 0 ? launch_chain(dd, hd, A, C, ops, stream) : run_steps());
+    JF_HIP(hipEventRecord(e1, stream));
+    JF_HIP(hipEventSynchronize(e1));
+    JF_HIP(hipEventElapsedTime(&ms[mode], e0, e1));
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  S.chain_off[c][q] = ms[0] <= ms[1] ? 0 : 1;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_chain_cache[key] = S.chain_off[c][q];
+  return JF_OK;
+}
+
 // Enqueue the steps of level lv of component c for Kraus variant v of the level's sliced site,
 // starting from `parent` (nullptr: the constant 1 of the first step's precision), the component's
 // output at element offset `base`; *end receives the level's last output (no synchronisation).
@@ -351,6 +439,62 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
   unsigned char* b1 = ws + L.level_buf[c][2 * lv + 1];
   for (int si = lev.first; si < lev.last; ++si) {
     const Step& st = cp.steps[si];
+    if (st.chain >= 0 && cp.chains[st.chain].first == si && (tune || !S.chain_off[c][st.chain])) {
+      // a chain: steps [first, last) in one launch, in place when the input is this level's
+      const Chain& ch = cp.chains[st.chain];
+      void* dst = (cur == b0 || cur == b1) ? const_cast<void*>(cur) : b0;
+      ChainOps ops = {};
+      std::vector<const StepDesc*> sdd, shd;
+      for (int q = ch.first; q < ch.last; ++q) {
+        const int var = (q == lev.first && lev.site >= 0) ? v : 0;
+        ops.B[q - ch.first] = reinterpret_cast<const float2*>(ws + L.step_b[c][q][var]);
+        sdd.push_back(reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][q]));
+        shd.push_back(reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][q]]));
+      }
+      const ChainDesc* dd = reinterpret_cast<const ChainDesc*>(ws + L.chain_desc[c][st.chain]);
+      const ChainDesc& hd = *reinterpret_cast<const ChainDesc*>(&S.host_image[L.chain_desc[c][st.chain]]);
+      if (tune && !tune->done[c][si]) {
+        for (int q = ch.first; q < ch.last; ++q) {  // the steps' own kernels first
+          jf_status ts = tune_step(const_cast<StepDesc*>(shd[q - ch.first]), sdd[q - ch.first], q == ch.first ? cur : dst,
+                                   dst, ops.B[q - ch.first], stream, tune->reps, q == ch.first ? dst == cur : true);
+          if (ts != JF_OK) return ts;
+          tune->done[c][q] = 1;
+        }
+        jf_status ts = tune_chain(p, S, c, st.chain, dd, hd, cur, dst, ops, sdd, shd, stream, tune->reps);
+        if (ts != JF_OK) return ts;
+      }
+      if (!S.chain_off[c][st.chain]) {
+        if (prof) {
+          hipEvent_t a, b;
+          JF_HIP(hipEventCreate(&a));
+          JF_HIP(hipEventCreate(&b));
+          set_launch_events(a, b);
+          const hipError_t le = launch_chain(dd, hd, cur, dst, ops, stream);
+          set_launch_events(nullptr, nullptr);
+          JF_HIP(le);
+          prof->ev.push_back(a);
+          prof->ev.push_back(b);
+          prof->bytes += ch.bytes;
+          prof->flops += ch.flops;
+          jf_step_profile r = {};
+          r.flops = ch.flops;
+          r.bytes = ch.bytes;
+          for (const StepDesc* h : shd) r.kS = std::max(r.kS, h->kS);
+          r.kN = r.kS;
+          r.L = ch.T;
+          r.mode = KM_F32;
+          r.variant = KV_CHAIN;
+          r.component = int(c);
+          r.steps = ch.last - ch.first;
+          prof->rec.push_back(r);
+        } else {
+          JF_HIP(launch_chain(dd, hd, cur, dst, ops, stream));
+        }
+        cur = dst;
+        si = ch.last - 1;
+        continue;
+      }
+    }
     void* dst;
     if (st.final_step) {
       dst = out + size_t(base) * 16;
@@ -389,6 +533,7 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
       r.mode = hd->mode;
       r.variant = resolve_variant(*hd);
       r.component = int(c);
+      r.steps = 1;
       prof->rec.push_back(r);
     } else {
       JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
@@ -688,6 +833,8 @@ extern "C" jf_status jf_set_kernel_variant(jf_plan* p, int variant) {
       StepDesc* hd = reinterpret_cast<StepDesc*>(&S.host_image[S.lay.step_desc[c][s]]);
       hd->variant = variant_applies(*hd, variant) ? variant : KV_AUTO;
     }
+  // a forced kernel runs every step on its own; AUTO brings the chains back
+  for (auto& v : S.chain_off) std::fill(v.begin(), v.end(), char(variant != KV_AUTO));
   S.variant_gen = g_variant_gen.fetch_add(1);
   return JF_OK;
 }

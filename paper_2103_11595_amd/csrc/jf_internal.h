@@ -106,6 +106,34 @@ struct Step {
   double flops = 0, bytes = 0;
   // device-side B offsets (filled at upload), per variant, in the pool of the compute type
   std::vector<long long> b_off;
+  int chain = -1;                // index into ComponentProgram::chains, -1: runs on its own
+};
+
+// A chain: consecutive in-place FP32 steps of one level [first, last) whose contracted bits
+// together span few positions.  It runs as one launch: a workgroup loads a tile of 2^T elements
+// (positions P: the union of the steps' contracted positions plus the lowest other positions as
+// rows) into LDS, applies every step of the chain there and writes the tile back, so the
+// intermediate crosses HBM once for the whole chain.
+constexpr int CHAIN_MAX_STEPS = 8;   // steps per chain
+constexpr int CHAIN_MAX_T = 12;      // log2 elements of a tile (32 KB of complex64)
+constexpr int CHAIN_MAX_U = 9;       // contracted positions of a chain
+constexpr int CHAIN_MAX_OPS = 4096;  // sum of K^2 over the chain's steps (operators in LDS)
+struct Chain {
+  int first = 0, last = 0;       // steps of the component
+  int T = 0;                     // tile bits
+  std::vector<int> P;            // tile positions, ascending (tile-local index = compressed over P)
+  std::vector<int> hi;           // the other positions, ascending (tile index bits)
+  long long nTiles = 1;
+  double flops = 0, bytes = 0;   // algorithmic cost of one launch (the tensor read and written once)
+};
+// Tile-local addressing of a chain, as the chain kernel reads it:
+//   global offset of tile-local index l = gDig[0][l & 15] + gDig[1][(l >> 4) & 15] + gDig[2][l >> 8]
+//   step j, contracted index s and the others f:  local index = sOff[j][s] + fDig[j][0][f & 15] +
+//   fDig[j][1][(f >> 4) & 15] + fDig[j][2][f >> 8]  (the output index n uses sOff like s)
+struct ChainTables {
+  long long gDig[3][16] = {};
+  std::vector<std::vector<unsigned short>> sOff;   // per step: 2^kS entries
+  std::vector<std::vector<unsigned short>> fDig;   // per step: 3 x 16 entries
 };
 
 struct Level {
@@ -132,7 +160,14 @@ struct ComponentProgram {
   long long out_off = 0;
   // one level and every intermediate <= 2^11 elements: runs whole in one workgroup (LDS)
   bool lds_resident = false;
+  std::vector<Chain> chains;
 };
+
+void chain_tables(const ComponentProgram& cp, const Chain& ch, ChainTables& out);
+// positions of a step's contracted bits in A (offS_A is their scatter), in its s-bit order
+std::vector<int> step_s_positions(const Step& st);
+// in-place complex64 step with a single-term FP32 operator of at most 32 x 32
+bool chainable(const Step& st);
 
 struct PlanOptions {
   int alg = 1;

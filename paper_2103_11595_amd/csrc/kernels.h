@@ -40,6 +40,7 @@ enum KernelVariant {
   KV_GAUSS_256 = 6,   // register-direct, three real products per complex one (not for two-term steps)
   KV_GAUSS_512 = 7,   // the same, 512 threads
   KV_COUNT = 8,
+  KV_CHAIN = 8,       // (profiles only) a chain of steps in one launch, k_chain
 };
 
 // Whether a variant can run the step described by h (mode, kS, kN, L).
@@ -60,6 +61,37 @@ enum KernelMode {
 // (double2 for FP64 modes, float2 otherwise).
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h_desc, const void* A, void* C, const void* B,
                        hipStream_t stream);
+
+// Chains: up to CHAIN_STEPS consecutive in-place FP32 steps of one level (each K = Nn <= 32, every
+// step keeping the intermediate's layout) applied to one LDS tile of 2^T <= 2^CHAIN_T elements per
+// HBM pass.  Tile-local index l (compressed over the tile's positions) sits in the tensor at
+//   tile base + gDig[l & 15] + gDig[16 + ((l >> 4) & 15)] + gDig[32 + (l >> 8)],
+// the tile base being the scatter of the tile index over hi[0 .. nHi).  Step j contracts its K
+// indices s at tile-local sOff[s] against the remaining tile bits f at
+//   fDig[f & 15] + fDig[16 + ((f >> 4) & 15)] + fDig[32 + (f >> 8)],
+// and writes n at the same places (sOff[n]).  Its operator (K x K, float2, row-major [s][n]) is
+// ops.B[j]; in LDS it sits at entry boff.
+constexpr int CHAIN_STEPS = 8;
+constexpr int CHAIN_T = 12;
+constexpr int CHAIN_OPS = 4096;  // float2 entries of all operators of a chain
+struct ChainStepDesc {
+  int kS, boff;
+  unsigned short sOff[32];
+  unsigned short fDig[48];
+};
+struct ChainDesc {
+  long long gDig[48];
+  int hi[DMAXHI];
+  long long nTiles;
+  int nsteps, T, nHi, ops;
+  ChainStepDesc st[CHAIN_STEPS];
+};
+struct ChainOps {
+  const float2* B[CHAIN_STEPS];
+};
+// A and C may alias (in place): a tile is read whole before any of it is written.
+hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h_desc, const void* A, void* C, const ChainOps& ops,
+                        hipStream_t stream);
 
 // Persistent executor of small component programs (every intermediate <= 2^11 elements, one
 // level): one workgroup per item, both ping-pong buffers in LDS, FP64 throughout.  A step entry

@@ -12,6 +12,7 @@
 //   k_absorb_mfma_rd     matrix cores on the real embedding, operands straight into registers
 //   k_absorb_mfma_gauss  matrix cores, three real products per complex one, register-direct
 //   k_absorb_bf16x3_mfma BF16 matrix cores, three products per real product
+//   k_chain              several in-place FP32 steps applied to one LDS tile per HBM pass
 //   k_persistent         whole small components in one workgroup's LDS
 //   k_sumsq, k_zero      the FP64 double-double sum of |t|^2 and a graph-safe fill
 // launch_step picks the kernel of a step (its variant, or the fixed rule).
@@ -608,6 +609,142 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
   }
 }
 
+// One step of a chain on the LDS tile: the Gauss-form products of k_absorb_mfma_gauss (lane
+// group g of k-step t supplies s = 4 t + g; the 16 MFMA rows of block mb are n = 16 mb + 0..15;
+// the same k order and the same FP32 operations, so the same results).  A unit is 16 values of
+// the step's untouched tile bits f; its outputs overwrite exactly the elements it read, after the
+// wave has read all of them (the products consume every read before any write), and the units of
+// different waves are disjoint.
+template <int NT, int KQ, int MB>
+__device__ __forceinline__ void chain_step(float2* tile, const float2* __restrict__ B, const ChainStepDesc& sd,
+                                           int T) {
+  using M = Mfma<float>;
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+  const int K = 1 << sd.kS;
+  const int units = 1 << (T - sd.kS - 4);
+  for (int u = wave; u < units; u += NW) {
+    const int f = (u << 4) + l16;
+    const int fl = sd.fDig[f & 15] + sd.fDig[16 + ((f >> 4) & 15)] + sd.fDig[32 + ((f >> 8) & 15)];
+    float2 a[KQ];
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+      const int s = 4 * t + g;
+      const float2 x = tile[fl + sd.sOff[s < K ? s : K - 1]];
+      a[t] = s < K ? x : float2{0.f, 0.f};
+    }
+    M::acc_t acc[3][MB];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[x][mb] = M::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < KQ; ++t) {
+      const float ar = a[t].x, ai = a[t].y, as = ar + ai;
+      const int s = 4 * t + g;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const int n = mb * 16 + l16;
+        const float2 bv = (s < K && n < K) ? B[s * K + n] : float2{0.f, 0.f};
+        acc[0][mb] = M::op(bv.x, ar, acc[0][mb]);
+        acc[1][mb] = M::op(bv.y, ai, acc[1][mb]);
+        acc[2][mb] = M::op(bv.x + bv.y, as, acc[2][mb]);
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = mb * 16 + M::row_of(g, r);
+        if (n < K) {
+          float2 o;
+          o.x = acc[0][mb][r] - acc[1][mb][r];
+          o.y = acc[2][mb][r] - acc[0][mb][r] - acc[1][mb][r];
+          tile[fl + sd.sOff[n]] = o;
+        }
+      }
+    }
+  }
+}
+
+// A chain of in-place FP32 steps, one HBM pass (see ChainDesc).  Each workgroup loops over tiles
+// with the grid stride: the tile's 2^T elements go from registers into LDS, the next tile's loads
+// are issued, every step of the chain runs on the LDS tile (a barrier after each), and the tile
+// goes back to HBM.  Element l of the tile belongs to thread l % NT throughout the loads, the LDS
+// fill and the stores, so the store phase and the next fill need no barrier between them.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_chain(const ChainDesc* __restrict__ d, const float2* A, float2* C,
+                                              ChainOps ops) {
+  static_assert(NT == 256, "element l of a tile is loaded by thread l % 256 (gDig digit 2 = l >> 8)");
+  constexpr int EPT = (1 << CHAIN_T) / NT;
+  __shared__ float2 tile[1 << CHAIN_T];
+  __shared__ ChainStepDesc sd[CHAIN_STEPS];
+  __shared__ long long gd[48];
+  __shared__ long long hb[NDIG][16];
+  extern __shared__ __align__(16) unsigned char smem[];
+  float2* sOp = reinterpret_cast<float2*>(smem);
+  const int nsteps = d->nsteps, T = d->T, nHi = d->nHi;
+  const long long nTiles = d->nTiles;
+  for (int i = threadIdx.x; i < 48; i += NT) gd[i] = d->gDig[i];
+  for (int i = threadIdx.x; i < NDIG * 16; i += NT) {
+    const int c = i >> 4, m = i & 15;
+    long long o = 0;
+    for (int b = 0; b < 4; ++b)
+      if (((m >> b) & 1) && 4 * c + b < nHi) o |= 1LL << d->hi[4 * c + b];
+    hb[c][m] = o;
+  }
+  {
+    const int* src = reinterpret_cast<const int*>(d->st);
+    int* dst = reinterpret_cast<int*>(sd);
+    const int words = int(sizeof(ChainStepDesc) / sizeof(int)) * nsteps;
+    for (int i = threadIdx.x; i < words; i += NT) dst[i] = src[i];
+  }
+  for (int j = 0; j < nsteps; ++j) {
+    const int KK = 1 << (2 * d->st[j].kS), bo = d->st[j].boff;
+    for (int i = threadIdx.x; i < KK; i += NT) sOp[bo + i] = ops.B[j][i];
+  }
+  __syncthreads();  // tables and operators visible to every wave
+  const int E = 1 << T;
+  const int tid = threadIdx.x;
+  const long long own = gd[tid & 15] + gd[16 + ((tid >> 4) & 15)];
+  auto base = [&](long long t) {
+    long long b = 0;
+#pragma unroll
+    for (int c = 0; c < NDIG; ++c) b |= hb[c][(t >> (4 * c)) & 15];
+    return b;
+  };
+  float2 pre[EPT];
+  auto fetch = [&](long long t) {
+    const long long b = base(t) + own;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (tid + NT * k < E) pre[k] = ld_stream(&A[b + gd[32 + k]]);
+  };
+  long long t = blockIdx.x;
+  if (t < nTiles) fetch(t);
+  for (; t < nTiles; t += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (tid + NT * k < E) tile[tid + NT * k] = pre[k];
+    __syncthreads();  // the whole tile is in LDS
+    if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
+    for (int j = 0; j < nsteps; ++j) {
+      const float2* Bj = sOp + sd[j].boff;
+      switch (sd[j].kS) {
+        case 5: chain_step<NT, 8, 2>(tile, Bj, sd[j], T); break;
+        case 4: chain_step<NT, 4, 1>(tile, Bj, sd[j], T); break;
+        case 3: chain_step<NT, 2, 1>(tile, Bj, sd[j], T); break;
+        default: chain_step<NT, 1, 1>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+      }
+      __syncthreads();  // step j complete on the whole tile
+    }
+    const long long b = base(t) + own;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+      if (tid + NT * k < E) st_stream(&C[b + gd[32 + k]], tile[tid + NT * k]);
+  }
+}
+
 // 3xBF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Every FP32 operand x is split
 // into hi = bf16(x) and lo = bf16(x - hi); a product a*b is hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b)
 // with FP32 accumulation (the cross terms in their own accumulator, added at the end).
@@ -1123,6 +1260,20 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
     }
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void* A, void* C, const ChainOps& ops,
+                        hipStream_t stream) {
+  if (h.nsteps < 1 || h.nsteps > CHAIN_STEPS || h.T < 4 || h.T > CHAIN_T || h.ops > CHAIN_OPS || h.nHi > DMAXHI)
+    return hipErrorInvalidValue;
+  for (int j = 0; j < h.nsteps; ++j)
+    if (h.st[j].kS < 1 || h.st[j].kS > 5 || h.T - h.st[j].kS < 4 || h.st[j].boff + (1 << (2 * h.st[j].kS)) > h.ops)
+      return hipErrorInvalidValue;
+  constexpr int NT = 256;
+  const size_t sm = size_t(h.ops) * sizeof(float2);
+  JF_LAUNCH(k_chain<NT>, dim3(JF_RESIDENT(k_chain<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
+            (const float2*)A, (float2*)C, ops);
   return hipGetLastError();
 }
 

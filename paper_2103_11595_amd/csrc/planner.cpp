@@ -156,6 +156,142 @@ struct CostModel {
 
 }  // namespace
 
+std::vector<int> step_s_positions(const Step& st) {
+  std::vector<int> pos;
+  for (int i = 0; i < st.kS; ++i) {
+    const long long o = st.offS_A[size_t(1) << i];
+    int b = 0;
+    while ((1LL << b) != o) ++b;
+    pos.push_back(b);
+  }
+  return pos;
+}
+
+// In-place complex64 step with a single-term FP32 operator of at most 32 x 32 (the Gauss-form
+// products the chain kernel applies).
+bool chainable(const Step& st) {
+  return st.inplace_ok && !st.final_step && st.compute == C_F32 && !st.two_term && st.in_prec == P_C64 &&
+         st.out_prec == P_C64 && st.kS == st.kN && st.kS >= 1 && st.kS <= 5;
+}
+
+namespace {
+
+// Tile of a chain over the contracted positions U of its steps (tensor of 2^rA elements): U plus
+// the lowest other positions as rows, 2^12 elements at most, at least 16 rows of every step's
+// other bits in a tile (T - kS >= 4).  False if no such tile exists.
+bool chain_tile(const std::set<int>& U, int rA, int ksmax, Chain& ch) {
+  const int u = int(U.size());
+  if (u > CHAIN_MAX_U || rA < u) return false;
+  const int rows = std::min(CHAIN_MAX_T - u, rA - u);
+  const int T = u + rows;
+  if (T - ksmax < 4) return false;
+  ch.P.clear();
+  ch.hi.clear();
+  int taken = 0;
+  for (int b = 0; b < rA; ++b) {
+    if (U.count(b)) {
+      ch.P.push_back(b);
+    } else if (taken < rows) {
+      ch.P.push_back(b);
+      ++taken;
+    } else {
+      ch.hi.push_back(b);
+    }
+  }
+  ch.T = T;
+  ch.nTiles = 1LL << ch.hi.size();
+  return int(ch.hi.size()) <= MAXHI;
+}
+
+// Group the steps of every level into chains: greedily extend a run of chainable steps while the
+// union of their contracted positions still has a tile, the operators fit the LDS budget and the
+// run has at most CHAIN_MAX_STEPS steps; runs of two or more become chains.
+void build_chains(ComponentProgram& cp) {
+  for (auto& lv : cp.levels) {
+    int i = lv.first;
+    while (i < lv.last) {
+      const Step& s0 = cp.steps[i];
+      if (!chainable(s0)) {
+        ++i;
+        continue;
+      }
+      std::set<int> U;
+      for (int b : step_s_positions(s0)) U.insert(b);
+      int ops = 1 << (2 * s0.kS), ksmax = s0.kS;
+      Chain best;
+      bool have = chain_tile(U, s0.rA, ksmax, best);
+      int j = i + 1;
+      while (have && j < lv.last && j - i < CHAIN_MAX_STEPS) {
+        const Step& sj = cp.steps[j];
+        if (!chainable(sj) || sj.rA != s0.rA) break;
+        std::set<int> U2 = U;
+        for (int b : step_s_positions(sj)) U2.insert(b);
+        const int ops2 = ops + (1 << (2 * sj.kS)), ks2 = std::max(ksmax, sj.kS);
+        Chain c2;
+        if (ops2 > CHAIN_MAX_OPS || !chain_tile(U2, s0.rA, ks2, c2)) break;
+        U = U2;
+        ops = ops2;
+        ksmax = ks2;
+        best = c2;
+        ++j;
+      }
+      if (have && j - i >= 2) {
+        best.first = i;
+        best.last = j;
+        best.bytes = 2.0 * std::ldexp(8.0, s0.rA);
+        for (int q = i; q < j; ++q) {
+          best.flops += cp.steps[q].flops;
+          cp.steps[q].chain = int(cp.chains.size());
+        }
+        cp.chains.push_back(best);
+        i = j;
+      } else {
+        ++i;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void chain_tables(const ComponentProgram& cp, const Chain& ch, ChainTables& out) {
+  std::map<int, int> local;  // position -> tile-local bit
+  for (int i = 0; i < ch.T; ++i) local[ch.P[i]] = i;
+  for (int d = 0; d < 3; ++d)
+    for (int m = 0; m < 16; ++m) {
+      long long o = 0;
+      for (int b = 0; b < 4; ++b)
+        if (((m >> b) & 1) && 4 * d + b < ch.T) o |= 1LL << ch.P[4 * d + b];
+      out.gDig[d][m] = o;
+    }
+  out.sOff.clear();
+  out.fDig.clear();
+  for (int q = ch.first; q < ch.last; ++q) {
+    const Step& st = cp.steps[q];
+    std::vector<int> sl;
+    for (int b : step_s_positions(st)) sl.push_back(local.at(b));
+    std::vector<int> fl;
+    for (int i = 0; i < ch.T; ++i)
+      if (!std::count(sl.begin(), sl.end(), i)) fl.push_back(i);
+    std::vector<unsigned short> so(size_t(1) << st.kS), fd(48, 0);
+    for (int s = 0; s < (1 << st.kS); ++s) {
+      int o = 0;
+      for (int b = 0; b < st.kS; ++b)
+        if ((s >> b) & 1) o |= 1 << sl[b];
+      so[s] = (unsigned short)o;
+    }
+    for (int d = 0; d < 3; ++d)
+      for (int m = 0; m < 16; ++m) {
+        int o = 0;
+        for (int b = 0; b < 4; ++b)
+          if (((m >> b) & 1) && 4 * d + b < (int)fl.size()) o |= 1 << fl[4 * d + b];
+        fd[size_t(d) * 16 + m] = (unsigned short)o;
+      }
+    out.sOff.push_back(so);
+    out.fDig.push_back(fd);
+  }
+}
+
 Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   auto t0 = std::chrono::steady_clock::now();
   Program P;
@@ -766,6 +902,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       cp.levels.push_back(Lv);
     }
     cp.leaves = mult;
+    if (!(opt.flags & JF_FLAG_NO_CHAIN)) build_chains(cp);
     cp.lds_resident = cp.levels.size() == 1 && cp.levels[0].nvar == 1;
     for (auto& st : cp.steps)
       if (st.rA > 11 || (!st.final_step && st.rC > 11)) cp.lds_resident = false;

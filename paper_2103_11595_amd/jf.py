@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libjf.so")
 
 JF_C128, JF_C64, JF_C64_BF16X3 = 0, 1, 2
 DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x3": JF_C64_BF16X3}
-JF_FLAG_NO_CANCEL, JF_FLAG_NO_FUSE, JF_FLAG_NO_BATCH, JF_FLAG_GRAPH = 1, 2, 4, 8
+JF_FLAG_NO_CANCEL, JF_FLAG_NO_FUSE, JF_FLAG_NO_BATCH, JF_FLAG_GRAPH, JF_FLAG_NO_CHAIN = 1, 2, 4, 8, 16
 
 
 def JF_FLAG_EFFORT(e: int) -> int:
@@ -81,7 +81,8 @@ class jf_profile(C.Structure):
 
 class jf_step_profile(C.Structure):
     _fields_ = [("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double), ("kS", C.c_int),
-                ("kN", C.c_int), ("L", C.c_int), ("mode", C.c_int), ("variant", C.c_int), ("component", C.c_int)]
+                ("kN", C.c_int), ("L", C.c_int), ("mode", C.c_int), ("variant", C.c_int), ("component", C.c_int),
+                ("steps", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,6 +98,7 @@ class jf_decision(C.Structure):
 
 # jf_kernel_variant
 KV_AUTO, KV_STAGED_256, KV_STAGED_512, KV_DIRECT_256, KV_DIRECT_512, KV_FMA, KV_GAUSS_256, KV_GAUSS_512 = range(8)
+KV_CHAIN = 8  # profiles only: a chain of steps in one launch
 KERNEL_VARIANTS = {"auto": KV_AUTO, "staged256": KV_STAGED_256, "staged512": KV_STAGED_512,
                    "direct256": KV_DIRECT_256, "direct512": KV_DIRECT_512, "fma": KV_FMA,
                    "gauss256": KV_GAUSS_256, "gauss512": KV_GAUSS_512}
@@ -205,7 +207,7 @@ class Plan:
         buf = C.create_string_buffer(int(n))
         L.jf_plan_describe(self.ptr, buf, n)
         keys = ["comp", "step", "level", "kS", "kN", "L", "rA", "rC", "tiles", "in_prec", "out_prec", "compute",
-                "nvar", "flops", "bytes", "rowsA", "rowsC", "sA", "nC"]
+                "nvar", "flops", "bytes", "rowsA", "rowsC", "sA", "nC", "chain"]
 
         def conv(k, v):
             if k in ("in_prec", "out_prec", "compute"):

@@ -25,7 +25,7 @@ import json
 import os
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-STEP_PREFIXES = ("k_absorb",)
+STEP_PREFIXES = ("k_absorb", "k_chain")
 
 
 def kernels_sha() -> str:

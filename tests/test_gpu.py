@@ -348,6 +348,52 @@ def test_autotuned_full_size_workload():
     assert 0.5 * total["kernel_ms"] <= sum(r["ms"] for r in prof) <= 2.0 * total["kernel_ms"]
 
 
+# --- chains: runs of in-place complex64 steps applied to one LDS tile per HBM pass ----------
+
+def _chain_instances():
+    # the same family and seeds as the host tests of the chain grouping (every plan holds chains)
+    for seed in (17, 20, 26, 35, 37, 38):
+        yield gen.random_circuit(6 + seed % 5, 60 + 5 * seed, 1 + seed % 3, 0.01, 0.3, 900 + seed)
+
+
+def test_chains_against_oracle_and_unchained_runs():
+    for i, inst in enumerate(_chain_instances()):
+        say("chains", i, "n", inst["n"])
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        p = jf.plan(inst, 1, "c64")
+        q = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_CHAIN)
+        ws = jf.workspace(max(p.info()["workspace_bytes"], q.info()["workspace_bytes"]))
+        a = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        prof = jf.jf_profile_steps(p, ws)
+        chains = [r for r in prof if r["variant"] == jf.KV_CHAIN]
+        assert chains and all(r["steps"] >= 2 for r in chains)
+        assert sum(r["steps"] for r in prof) == len(jf.jf_profile_steps(q, ws))
+        b = jf.jf_fidelity_alg1(q, ws, want_terms=True)
+        assert abs(a["fj"] - ref["fj"]) <= TOL["c64"] and abs(b["fj"] - ref["fj"]) <= TOL["c64"]
+        assert np.max(np.abs(a["terms"] - _terms(ref))) <= 1e-6
+        assert np.max(np.abs(a["terms"] - b["terms"])) <= 1e-6
+        jf.jf_autotune(p, ws, reps=2)  # chains kept or split by measurement: same bar
+        c = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        assert abs(c["fj"] - ref["fj"]) <= TOL["c64"]
+
+
+def test_chain_at_full_size_is_bitwise_the_gauss_steps():
+    # the n=16 workload chains its two 2^26-element in-place steps (32 x 32 blocks); run one launch
+    # each, the fixed rule gives both the Gauss-form kernel, whose products the chain repeats in
+    # the same order: the results agree bit for bit
+    inst = gen.config2()
+    p = jf.plan(inst, 1, "c64")
+    q = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_CHAIN)
+    ws = jf.workspace(max(p.info()["workspace_bytes"], q.info()["workspace_bytes"]))
+    a = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+    prof = jf.jf_profile_steps(p, ws)
+    chains = [r for r in prof if r["variant"] == jf.KV_CHAIN]
+    assert [r["steps"] for r in chains] == [2]
+    assert chains[0]["bytes"] == 2 * 8 * 2.0**26
+    b = jf.jf_fidelity_alg1(q, ws, want_terms=True)
+    assert a["fj"] == b["fj"] and np.array_equal(a["terms"], b["terms"])
+
+
 def test_every_feasible_batch_member_c64_against_c128():
     """All members of the 512-circuit workload that fit a 2^28 cap (443; the others need
     2^30..2^40 -- the bench runs those at larger caps): complex64 within 1e-6 of complex128.  The deep members (150-240 FP32 steps) are where a

@@ -198,3 +198,48 @@ def test_estimated_time_grows_with_the_work():
     assert 0 < small < large
     # complex128 moves twice the bytes of complex64 on the same order
     assert jf.plan(gen.config2(), 1, "c128").stats()["est_seconds"] > large
+
+
+# --- chains of in-place complex64 steps (one LDS tile per HBM pass) ------------------------
+
+def _chain_instances():
+    # seeds of this family whose complex64 plans hold chains (found by planning, checked below)
+    for seed in (17, 20, 26, 35, 37, 38):
+        yield gen.random_circuit(6 + seed % 5, 60 + 5 * seed, 1 + seed % 3, 0.01, 0.3, 900 + seed)
+
+
+def test_chains_group_consecutive_in_place_steps():
+    d = jf.plan(gen.config2(), 1, "c64").describe()
+    chained = [x for x in d if x["chain"] >= 0]
+    assert len(chained) >= 2  # the two 2^26 in-place steps of the n=16 workload
+    for inst in _chain_instances():
+        d = jf.plan(inst, 1, "c64").describe()
+        groups = {}
+        for x in d:
+            if x["chain"] >= 0:
+                groups.setdefault((x["comp"], x["chain"]), []).append(x)
+        assert groups
+        for steps in groups.values():
+            assert len(steps) >= 2
+            idx = [x["step"] for x in steps]
+            assert idx == list(range(idx[0], idx[0] + len(idx)))             # consecutive
+            assert len({x["level"] for x in steps}) == 1                     # one level
+            union = set()
+            for x in steps:
+                assert x["compute"] == "f32" and x["kS"] == x["kN"] <= 5       # single-term FP32
+                assert x["sA"] == x["nC"] and x["rowsA"] == x["rowsC"] and x["rA"] == x["rC"]
+                union |= set(x["sA"])
+            assert len(union) <= 9
+    # complex128 and 3xBF16 plans and JF_FLAG_NO_CHAIN have none
+    for dt, flags in (("c128", 0), ("bf16x3", 0), ("c64", jf.JF_FLAG_NO_CHAIN)):
+        assert all(x["chain"] == -1 for x in jf.plan(gen.config2(), 1, dt, flags=flags).describe())
+
+
+def test_emulated_chains_match_oracle_and_unchained_program():
+    for inst in _chain_instances():
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+        chained = jf.plan(inst, 1, "c64").emulate()   # the emulation follows the chain kernel's tile addressing
+        plain = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_CHAIN).emulate()
+        assert np.max(np.abs(chained - want)) < 1e-12
+        assert np.max(np.abs(chained - plain)) < 1e-13
