@@ -672,10 +672,13 @@ __device__ __forceinline__ void chain_step(float2* tile, const float2* __restric
 // are issued, every step of the chain runs on the LDS tile (a barrier after each), and the tile
 // goes back to HBM.  Element l of the tile belongs to thread l % NT throughout the loads, the LDS
 // fill and the stores, so the store phase and the next fill need no barrier between them.
+// Occupancy 3 (three 256-thread workgroups per CU when the operators leave room in LDS): with
+// the register budget that gives, the n=16 workload's 2^26-element chain takes 300 us against
+// 337 us at the compiler's default of 2 and 406 us with 512-thread workgroups (measured on MI355X).
 template <int NT>
-__global__ __launch_bounds__(NT) void k_chain(const ChainDesc* __restrict__ d, const float2* A, float2* C,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_chain(const ChainDesc* __restrict__ d, const float2* A, float2* C,
                                               ChainOps ops) {
-  static_assert(NT == 256, "element l of a tile is loaded by thread l % 256 (gDig digit 2 = l >> 8)");
+  static_assert(NT % 256 == 0 && NT <= 1024, "digits 0 and 1 of a thread's elements are its own");
   constexpr int EPT = (1 << CHAIN_T) / NT;
   __shared__ float2 tile[1 << CHAIN_T];
   __shared__ ChainStepDesc sd[CHAIN_STEPS];
@@ -718,7 +721,7 @@ __global__ __launch_bounds__(NT) void k_chain(const ChainDesc* __restrict__ d, c
     const long long b = base(t) + own;
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
-      if (tid + NT * k < E) pre[k] = ld_stream(&A[b + gd[32 + k]]);
+      if (tid + NT * k < E) pre[k] = ld_stream(&A[b + gd[32 + ((tid + NT * k) >> 8)]]);
   };
   long long t = blockIdx.x;
   if (t < nTiles) fetch(t);
@@ -741,7 +744,7 @@ __global__ __launch_bounds__(NT) void k_chain(const ChainDesc* __restrict__ d, c
     const long long b = base(t) + own;
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
-      if (tid + NT * k < E) st_stream(&C[b + gd[32 + k]], tile[tid + NT * k]);
+      if (tid + NT * k < E) st_stream(&C[b + gd[32 + ((tid + NT * k) >> 8)]], tile[tid + NT * k]);
   }
 }
 

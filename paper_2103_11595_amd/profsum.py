@@ -41,7 +41,8 @@ def bench_line(log: str) -> dict:
 
 
 def short(name: str) -> str:
-    return name.replace("void ", "").split("(jf::StepDesc")[0].split("(HIP_vector_type")[0].replace("jf::", "")
+    return (name.replace("void ", "").split("(jf::StepDesc")[0].split("(HIP_vector_type")[0].split("(ChainDesc")[0]
+            .split("(jf::ChainDesc")[0].replace("jf::", ""))
 
 
 def is_step(name: str) -> bool:
@@ -131,7 +132,7 @@ def traffic(args):
             f"| HBM fetch (scaled FETCH_SIZE) | {res['fetch']['bytes'] / 1e9:.3f} GB | {res['fetch']['bytes'] / n / 1e6:.1f} MB |",
             f"| HBM write (scaled WRITE_SIZE) | {res['write']['bytes'] / 1e9:.3f} GB | {res['write']['bytes'] / n / 1e6:.1f} MB |",
             f"| HBM traffic | {tr / 1e9:.3f} GB | {tr / n / 1e6:.1f} MB |",
-            f"| algorithmic bytes (planner) | {alg / 1e9:.3f} GB | {alg / n / 1e6:.1f} MB |", "",
+            f"| algorithmic bytes (every launch reads its input and writes its output once; a chain counts one pass) | {alg / 1e9:.3f} GB | {alg / n / 1e6:.1f} MB |", "",
             f"Traffic / algorithmic = **{tr / alg:.4f}**."]
     open(args.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
