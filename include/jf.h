@@ -291,8 +291,9 @@ jf_status jf_autotune(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream
 
 /*
  * jf_set_kernel_variant -- force one kernel (jf_kernel_variant) on every step it can run; the
- * other steps keep the AUTO rule, and chains are split into their steps.  JF_KV_AUTO restores
- * the rule and the chains everywhere (and so undoes jf_autotune).  For testing each kernel against
+ * other steps keep the AUTO rule.  Chains stay chains under JF_KV_GAUSS_256 / 512 (they compute
+ * the Gauss form) and are split into their steps under the other kernels.  JF_KV_AUTO restores the
+ * rule and the chains everywhere (and so undoes jf_autotune).  For testing each kernel against
  * the oracle.  Host only.  Errors: JF_E_ARG (JF_KV_CHAIN is not a per-step kernel).
  */
 jf_status jf_set_kernel_variant(jf_plan* plan, int variant);

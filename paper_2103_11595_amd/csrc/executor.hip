@@ -833,8 +833,10 @@ extern "C" jf_status jf_set_kernel_variant(jf_plan* p, int variant) {
       StepDesc* hd = reinterpret_cast<StepDesc*>(&S.host_image[S.lay.step_desc[c][s]]);
       hd->variant = variant_applies(*hd, variant) ? variant : KV_AUTO;
     }
-  // a forced kernel runs every step on its own; AUTO brings the chains back
-  for (auto& v : S.chain_off) std::fill(v.begin(), v.end(), char(variant != KV_AUTO));
+  // a forced kernel runs every step on its own, except the Gauss-form kernels, whose products the
+  // chains repeat; AUTO brings the chains back
+  const bool keep = variant == KV_AUTO || variant == KV_GAUSS_256 || variant == KV_GAUSS_512;
+  for (auto& v : S.chain_off) std::fill(v.begin(), v.end(), char(!keep));
   S.variant_gen = g_variant_gen.fetch_add(1);
   return JF_OK;
 }

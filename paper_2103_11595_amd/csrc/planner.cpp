@@ -34,6 +34,7 @@ struct LocalNet {
   std::vector<std::vector<int>> legs;  // local leg ids per tensor
   std::vector<std::vector<int>> leg_tensors;  // tensors per local leg (1 or 2)
   std::vector<char> open;               // local leg is an open (Kraus-index) leg
+  std::vector<int> glob;                // network (global) id of every local leg
   int nl = 0;
 };
 
@@ -51,6 +52,7 @@ LocalNet make_local(const Network& net, const std::vector<int>& comp) {
         id = L.nl++;
         lid[g] = id;
         L.leg_tensors.emplace_back();
+        L.glob.push_back(g);
       } else {
         id = it->second;
       }
@@ -146,12 +148,17 @@ struct CostModel {
   double bw = 5.2e12;        // effective bytes/s
   double flops = 28e12;      // effective flop/s (FP64 MFMA)
   double launch = 4e-6;      // seconds per step
+  // complex64 chains (k_chain), algorithmic flop/s: measured 65-115 TFLOP/s on MI355X (2^22 to 2^26
+  // elements); 80 picks the faster n=16 plan (1.01 ms per pass against 1.07 ms with 115)
+  double chain_flops = 80e12;
   double step(int rA, int rC, int kS, int kN, int ein, int eout) const {
     int f = rA - kS;
     double by = std::ldexp(double(ein), rA) + std::ldexp(double(eout), rC);
     double fl = 8.0 * std::ldexp(1.0, f + kS + kN);
     return std::max(by / bw, fl / flops) + launch;
   }
+  // one launch that reads and writes a complex64 intermediate of 2^rA elements once
+  double chain(int rA, double fl) const { return std::max(std::ldexp(16.0, rA) / bw, fl / chain_flops) + launch; }
 };
 
 }  // namespace
@@ -203,53 +210,78 @@ bool chain_tile(const std::set<int>& U, int rA, int ksmax, Chain& ch) {
   return int(ch.hi.size()) <= MAXHI;
 }
 
-// Group the steps of every level into chains: greedily extend a run of chainable steps while the
-// union of their contracted positions still has a tile, the operators fit the LDS budget and the
-// run has at most CHAIN_MAX_STEPS steps; runs of two or more become chains.
-void build_chains(ComponentProgram& cp) {
-  for (auto& lv : cp.levels) {
-    int i = lv.first;
-    while (i < lv.last) {
-      const Step& s0 = cp.steps[i];
-      if (!chainable(s0)) {
-        ++i;
-        continue;
-      }
-      std::set<int> U;
-      for (int b : step_s_positions(s0)) U.insert(b);
-      int ops = 1 << (2 * s0.kS), ksmax = s0.kS;
-      Chain best;
-      bool have = chain_tile(U, s0.rA, ksmax, best);
-      int j = i + 1;
-      while (have && j < lv.last && j - i < CHAIN_MAX_STEPS) {
-        const Step& sj = cp.steps[j];
-        if (!chainable(sj) || sj.rA != s0.rA) break;
-        std::set<int> U2 = U;
-        for (int b : step_s_positions(sj)) U2.insert(b);
-        const int ops2 = ops + (1 << (2 * sj.kS)), ks2 = std::max(ksmax, sj.kS);
-        Chain c2;
-        if (ops2 > CHAIN_MAX_OPS || !chain_tile(U2, s0.rA, ks2, c2)) break;
-        U = U2;
-        ops = ops2;
-        ksmax = ks2;
-        best = c2;
-        ++j;
-      }
-      if (have && j - i >= 2) {
-        best.first = i;
-        best.last = j;
-        best.bytes = 2.0 * std::ldexp(8.0, s0.rA);
-        for (int q = i; q < j; ++q) {
-          best.flops += cp.steps[q].flops;
-          cp.steps[q].chain = int(cp.chains.size());
-        }
-        cp.chains.push_back(best);
-        i = j;
-      } else {
-        ++i;
-      }
+// What chain grouping needs to know of a step.
+struct ChainCand {
+  bool ok = false;         // chainable (in place, single-term FP32, K = Nn <= 32)
+  int kS = 0, rA = 0;
+  std::vector<int> spos;   // bit positions of its contracted legs
+};
+
+// Group steps [first, last) of one level into chains: greedily extend a run of chainable steps
+// while the union of their contracted positions still has a tile, the operators fit the LDS
+// budget and the run has at most CHAIN_MAX_STEPS steps; emit(i, j, tile) for every run [i, j) of
+// two or more.  The lowering and the planner's cost estimate both group with this function.
+template <class Emit>
+void group_chains(const std::vector<ChainCand>& c, int first, int last, Emit&& emit) {
+  int i = first;
+  while (i < last) {
+    if (!c[i].ok) {
+      ++i;
+      continue;
+    }
+    std::set<int> U(c[i].spos.begin(), c[i].spos.end());
+    int ops = 1 << (2 * c[i].kS), ksmax = c[i].kS;
+    Chain best;
+    const bool have = chain_tile(U, c[i].rA, ksmax, best);
+    int j = i + 1;
+    while (have && j < last && j - i < CHAIN_MAX_STEPS) {
+      if (!c[j].ok || c[j].rA != c[i].rA) break;
+      std::set<int> U2 = U;
+      U2.insert(c[j].spos.begin(), c[j].spos.end());
+      const int ops2 = ops + (1 << (2 * c[j].kS)), ks2 = std::max(ksmax, c[j].kS);
+      Chain c2;
+      if (ops2 > CHAIN_MAX_OPS || !chain_tile(U2, c[i].rA, ks2, c2)) break;
+      U = U2;
+      ops = ops2;
+      ksmax = ks2;
+      best = c2;
+      ++j;
+    }
+    if (have && j - i >= 2) {
+      emit(i, j, best);
+      i = j;
+    } else {
+      ++i;
     }
   }
+}
+
+// Chains of one level of a lowered component (steps [first, last)); returns the change of the
+// level's cost-model time per leaf (the chain's launch in place of its steps' launches).
+double build_level_chains(ComponentProgram& cp, int first, int last, const CostModel& cm) {
+  std::vector<ChainCand> c(cp.steps.size());
+  for (int q = first; q < last; ++q) {
+    const Step& st = cp.steps[q];
+    c[q].ok = chainable(st);
+    c[q].kS = st.kS;
+    c[q].rA = st.rA;
+    if (c[q].ok) c[q].spos = step_s_positions(st);
+  }
+  double dt = 0;
+  group_chains(c, first, last, [&](int i, int j, Chain ch) {
+    ch.first = i;
+    ch.last = j;
+    ch.bytes = std::ldexp(16.0, cp.steps[i].rA);
+    for (int q = i; q < j; ++q) {
+      const Step& st = cp.steps[q];
+      ch.flops += st.flops;
+      dt -= std::max(st.bytes / cm.bw, st.flops / cm.flops) + cm.launch;
+      cp.steps[q].chain = int(cp.chains.size());
+    }
+    dt += cm.chain(cp.steps[i].rA, ch.flops);
+    cp.chains.push_back(ch);
+  });
+  return dt;
 }
 
 }  // namespace
@@ -438,6 +470,11 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       int in_e = low ? 8 : 16;
       int k = 0, lvstart = 0;
       std::vector<int> blk, trial;
+      // bit positions of the intermediate's legs, laid out as the lowering lays them out, and the
+      // steps of the current level as chain candidates with their cost-model times
+      std::vector<int> Tl, posT(L.nl, -1), Sv, Nv, nTl;
+      std::vector<ChainCand> seg;
+      std::vector<double> segt;
       while (k < N) {
         // a sliced slot starts a level: its Kraus operator is fixed, its Kraus legs are gone
         const Tensor* t0 = L.ts[p.order[k]];
@@ -452,6 +489,8 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           if (opt.alg == 1 && tj->site >= 0 && sl[tj->site]) { kend = j; break; }
         }
         (void)lvstart;
+        seg.clear();
+        segt.clear();
         while (k < kend) {
           const bool head = level_head && k == lvstart;
           blk = head ? legs_novar[p.order[k]] : L.legs[p.order[k]];
@@ -495,7 +534,44 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           const int rC = rA - kS + kN;
           const double by = std::ldexp(double(in_e), rA) + std::ldexp(double(out_e), rC);
           const double fl = 8.0 * std::ldexp(1.0, rA + kN);
-          est += mult * (std::max(by / cm.bw, fl / cm.flops) + cm.launch);
+          const double t_step = std::max(by / cm.bw, fl / cm.flops) + cm.launch;
+          est += mult * t_step;
+          // chain candidate and the new layout (as the lowering places legs)
+          Sv.clear();
+          Nv.clear();
+          for (int l : blk) (inT[l] ? Sv : Nv).push_back(l);
+          std::sort(Sv.begin(), Sv.end(), [&](int a, int b) { return posT[a] < posT[b]; });
+          std::sort(Nv.begin(), Nv.end(), [&](int a, int b) { return L.glob[a] < L.glob[b]; });
+          ChainCand cc;
+          if (opt.dtype == JF_C64 && k < sw && !final_step && kS == kN && kS >= 1 && kS <= 5) {
+            bool noise = false;
+            for (int q = k; q < e; ++q) noise = noise || L.ts[p.order[q]]->site >= 0;
+            if (!noise) {
+              cc.ok = true;
+              for (int l : Sv) cc.spos.push_back(posT[l]);
+            }
+          }
+          cc.kS = kS;
+          cc.rA = rA;
+          seg.push_back(std::move(cc));
+          segt.push_back(t_step);
+          if (!final_step) {
+            if (kS == kN) {
+              for (int i = 0; i < kS; ++i) {
+                posT[Nv[i]] = posT[Sv[i]];
+                Tl[posT[Sv[i]]] = Nv[i];
+                posT[Sv[i]] = -1;
+              }
+            } else {
+              nTl.clear();
+              for (int l : Tl)
+                if (!inB[l]) nTl.push_back(l);
+              for (int l : Sv) posT[l] = -1;
+              for (int l : Nv) nTl.push_back(l);
+              Tl.swap(nTl);
+              for (int i = 0; i < (int)Tl.size(); ++i) posT[Tl[i]] = i;
+            }
+          }
           for (int l : blk) {
             inT[l] ^= 1;
             inB[l] = 0;
@@ -504,6 +580,14 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           in_e = out_e;
           k = e;
         }
+        group_chains(seg, 0, int(seg.size()), [&](int i, int j, const Chain&) {
+          double fl = 0;
+          for (int q = i; q < j; ++q) {
+            fl += 8.0 * std::ldexp(1.0, seg[q].rA + seg[q].kS);
+            est -= mult * segt[q];
+          }
+          est += mult * cm.chain(seg[i].rA, fl);
+        });
       }
       return est;
     };
@@ -897,12 +981,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         k = e;
       }
       Lv.last = int(cp.steps.size());
+      if (!(opt.flags & JF_FLAG_NO_CHAIN)) P.est_seconds += mult * build_level_chains(cp, Lv.first, Lv.last, cm);
       Lv.max_log2 = level_maxw[lv];
       Lv.buf_bytes = std::max<size_t>(level_bytes[lv], 256);
       cp.levels.push_back(Lv);
     }
     cp.leaves = mult;
-    if (!(opt.flags & JF_FLAG_NO_CHAIN)) build_chains(cp);
     cp.lds_resident = cp.levels.size() == 1 && cp.levels[0].nvar == 1;
     for (auto& st : cp.steps)
       if (st.rA > 11 || (!st.final_step && st.rC > 11)) cp.lds_resident = false;
