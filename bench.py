@@ -218,7 +218,7 @@ def run_batch(args, torch, gen, jf, stream):
     rest = large[done - len(small):]
     # parity of the completed members (not timed): complex64 against complex128 where the
     # complex128 plan's workspace fits
-    worst, checked, unchecked = 0.0, 0, 0
+    worst, checked, unchecked, worst_member = 0.0, 0, 0, None
     if args.dtype != "c128":
         res_b = dict(zip([id(x[2]) for x in small], out_small))
         for est, info, p, inst in small + large[:done - len(small)]:
@@ -232,7 +232,12 @@ def run_batch(args, torch, gen, jf, stream):
                 torch.cuda.empty_cache()
                 ws = jf.workspace(need)
             f64 = res_b[id(p)]["fj"] if id(p) in res_b else jf.jf_fidelity_alg1(p, ws, stream)["fj"]
-            worst = max(worst, abs(f64 - jf.jf_fidelity_alg1(q, ws, stream)["fj"]))
+            dfj = abs(f64 - jf.jf_fidelity_alg1(q, ws, stream)["fj"])
+            if dfj > worst:
+                worst = dfj
+                worst_member = {"name": inst.get("name", ""), "n": inst["n"], "gates": len(inst["gates"]),
+                                "sites": len(inst.get("noise", [])), "max_log2": info["max_log2_intermediate"],
+                                "fj": f64}
             checked += 1
             if checked % 50 == 0:
                 progress(f"parity checked: {checked}, worst {worst:.2e}")
@@ -255,7 +260,8 @@ def run_batch(args, torch, gen, jf, stream):
                              "hbm_gbs": bytes_done / large_s / 1e9 if large_s > 0 else None},
            "remaining_feasible": len(rest), "remaining_terms": sum(x[1]["kraus_terms"] for x in rest),
            "projected_seconds_for_remaining": sum(x[0] for x in rest),
-           "parity": {"max_abs_dfj_vs_c128": worst, "checked": checked, "unchecked_c128_too_large": unchecked},
+           "parity": {"max_abs_dfj_vs_c128": worst, "checked": checked, "unchecked_c128_too_large": unchecked,
+                      "worst_member": worst_member},
            "planning_seconds": plan_s, "replanned": replanned, "replanning_seconds": replan_s,
            "infeasible_examples": infeasible[:5]}
     print(json.dumps(out))

@@ -380,6 +380,39 @@ def test_chains_against_oracle_and_unchained_runs():
         assert abs(c["fj"] - ref["fj"]) <= TOL["c64"]
 
 
+def test_chains_in_graphs_batches_and_decisions():
+    """Chained plans through every way of running a plan: hipGraph replays and one batch equal the
+    eager runs bit for bit, and the early Definition 1 decision brackets F_J."""
+    import torch
+    insts = list(_chain_instances())[:3]
+    plans = [jf.plan(inst, 1, "c64") for inst in insts]
+    for p in plans:
+        assert any(x["chain"] >= 0 for x in p.describe())
+    eager = []
+    for i, p in enumerate(plans):
+        say("chained eager", i)
+        ws = jf.workspace(p.info()["workspace_bytes"])
+        eager.append(jf.jf_fidelity_alg1(p, ws, want_terms=True))
+    say("chained batch")
+    got = jf.jf_fidelity_batch(plans)
+    for r, e in zip(got, eager):
+        assert r["fj"] == e["fj"]
+    side = torch.cuda.Stream()
+    for i, inst in enumerate(insts):
+        say("chained graph", i)
+        g = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_GRAPH)
+        ws = jf.workspace(g.info()["workspace_bytes"])
+        for k in range(3):
+            r = jf.jf_fidelity_alg1(g, ws, side if k % 2 else None, want_terms=True)
+            assert r["fj"] == eager[i]["fj"] and np.array_equal(r["terms"], eager[i]["terms"]), (i, k)
+            torch.cuda.synchronize()
+        ref = dense.fidelity_alg1(inst)["fj"]
+        for eps in (1 - ref + 0.01, 1 - ref - 0.01):
+            d = jf.jf_decide_equivalence(plans[i], eps)
+            assert d["fj_lower"] - d["margin"] <= ref <= d["fj_upper"] + d["margin"]
+            assert d["decision"] == (1 if ref > 1 - eps else 0)
+
+
 def test_chain_at_full_size_is_bitwise_the_gauss_steps():
     # the n=16 workload's plan chains its 2^26-element in-place steps (32 x 32 blocks) and others;
     # with the Gauss-form kernel forced on every step that takes it, running the chains and running
