@@ -313,9 +313,24 @@ DevState& state_of(jf_plan* p) {
   } while (0)
 
 struct Prof {
-  std::vector<hipEvent_t> ev;  // pairs around every contraction-step launch
+  std::vector<hipEvent_t> ev;  // pairs around every contraction-step launch (owned)
   std::vector<jf_step_profile> rec;  // one per launch, ms filled in after the run
   double bytes = 0, flops = 0;
+  Prof() = default;
+  Prof(const Prof&) = delete;
+  Prof& operator=(const Prof&) = delete;
+  ~Prof() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+};
+
+// Two timing events, destroyed on every way out of the scope that made them.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+  }
 };
 
 // Autotuning state of one run: which steps have been timed already.
@@ -342,9 +357,10 @@ jf_status tune_step(StepDesc* hd, const StepDesc* dd, const void* A, void* C, co
       return JF_OK;
     }
   }
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   int best = KV_AUTO;
   float best_ms = FLT_MAX;
   for (int v = KV_AUTO + 1; v < KV_COUNT; ++v) {
@@ -362,8 +378,6 @@ jf_status tune_step(StepDesc* hd, const StepDesc* dd, const void* A, void* C, co
       best = v;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   hd->variant = best;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune_cache[key] = best;
@@ -377,7 +391,7 @@ std::map<std::vector<long long>, int> g_chain_cache;
 // Time a chain against its steps run one launch each (every step with its tuned kernel, in place
 // on the chain's output after the first) and keep the faster.  Like tune_step, this clobbers the
 // data.
-jf_status tune_chain(jf_plan* p, DevState& S, size_t c, int q, const ChainDesc* dd, const ChainDesc& hd,
+jf_status tune_chain(DevState& S, size_t c, int q, const ChainDesc* dd, const ChainDesc& hd,
                      const void* A, void* C, const ChainOps& ops, const std::vector<const StepDesc*>& sdd,
                      const std::vector<const StepDesc*>& shd, hipStream_t stream, int reps) {
   std::vector<long long> key = {hd.T, hd.nTiles, A == C ? 1 : 0};
@@ -400,9 +414,10 @@ jf_status tune_chain(jf_plan* p, DevState& S, size_t c, int q, const ChainDesc* 
     }
     return hipSuccess;
   };
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   float ms[2] = {0, 0};
   for (int mode = 0; mode < 2; ++mode) {
     JF_HIP(mode == 0 ? launch_chain(dd, hd, A, C, ops, stream) : run_steps());  // warm-up
@@ -412,8 +427,6 @@ jf_status tune_chain(jf_plan* p, DevState& S, size_t c, int q, const ChainDesc* 
     JF_HIP(hipEventSynchronize(e1));
     JF_HIP(hipEventElapsedTime(&ms[mode], e0, e1));
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   S.chain_off[c][q] = ms[0] <= ms[1] ? 0 : 1;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_chain_cache[key] = S.chain_off[c][q];
@@ -460,20 +473,20 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
           if (ts != JF_OK) return ts;
           tune->done[c][q] = 1;
         }
-        jf_status ts = tune_chain(p, S, c, st.chain, dd, hd, cur, dst, ops, sdd, shd, stream, tune->reps);
+        jf_status ts = tune_chain(S, c, st.chain, dd, hd, cur, dst, ops, sdd, shd, stream, tune->reps);
         if (ts != JF_OK) return ts;
       }
       if (!S.chain_off[c][st.chain]) {
         if (prof) {
-          hipEvent_t a, b;
+          hipEvent_t a = nullptr, b = nullptr;
           JF_HIP(hipEventCreate(&a));
+          prof->ev.push_back(a);
           JF_HIP(hipEventCreate(&b));
+          prof->ev.push_back(b);
           set_launch_events(a, b);
           const hipError_t le = launch_chain(dd, hd, cur, dst, ops, stream);
           set_launch_events(nullptr, nullptr);
           JF_HIP(le);
-          prof->ev.push_back(a);
-          prof->ev.push_back(b);
           prof->bytes += ch.bytes;
           prof->flops += ch.flops;
           jf_step_profile r = {};
@@ -513,15 +526,15 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
       tune->done[c][si] = 1;
     }
     if (prof) {
-      hipEvent_t a, b;
+      hipEvent_t a = nullptr, b = nullptr;
       JF_HIP(hipEventCreate(&a));
+      prof->ev.push_back(a);
       JF_HIP(hipEventCreate(&b));
+      prof->ev.push_back(b);
       set_launch_events(a, b);
       const hipError_t le = launch_step(dd, *hd, cur, dst, B, stream);
       set_launch_events(nullptr, nullptr);
       JF_HIP(le);
-      prof->ev.push_back(a);
-      prof->ev.push_back(b);
       prof->bytes += st.bytes;
       prof->flops += st.flops;
       jf_step_profile r = {};
@@ -746,9 +759,10 @@ extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void*
   st = upload(p, ws, stream);
   if (st != JF_OK) return st;
   Prof prof;
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   JF_HIP(hipEventRecord(e0, stream));
   st = enqueue_program(p, static_cast<unsigned char*>(ws), stream, &prof);
   if (st != JF_OK) return st;
@@ -762,11 +776,8 @@ extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void*
     r.kernel_ms += ms;
     r.max_launch_ms = std::max(r.max_launch_ms, double(ms));
   }
-  for (auto ev : prof.ev) hipEventDestroy(ev);
   float tot = 0;
   JF_HIP(hipEventElapsedTime(&tot, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   r.total_ms = tot;
   r.bytes = prof.bytes;
   r.flops = prof.flops;
@@ -796,7 +807,6 @@ extern "C" jf_status jf_profile_steps(jf_plan* p, void* ws, size_t ws_bytes, voi
     prof.rec[i].ms = ms;
     if (i < cap) out[i] = prof.rec[i];
   }
-  for (auto ev : prof.ev) hipEventDestroy(ev);
   *n_launches = n;
   return JF_OK;
 }
@@ -867,9 +877,10 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
   jf_decision d = {};
   d.margin = margin;
   d.leaves_total = P.work_items;
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   JF_HIP(hipEventRecord(e0, stream));
   auto decide = [&](double lo, double hi) {
     if (lo - margin > thr) return 1;
@@ -981,8 +992,6 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
   JF_HIP(hipEventSynchronize(e1));
   float ms = 0;
   JF_HIP(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   d.seconds = ms * 1e-3;
   *out = d;
   return JF_OK;
@@ -1063,10 +1072,11 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     JF_HIP(hipMemcpyAsync(steps_dev, lsteps.data(), lsteps.size() * sizeof(LdsStep), hipMemcpyHostToDevice, stream));
     JF_HIP(hipStreamSynchronize(stream));
   }
-  hipEvent_t e0, e1;
-  JF_HIP(hipEventCreate(&e0));
-  JF_HIP(hipEventCreate(&e1));
-  DevState& S0 = state_of(plans[0 < n ? 0 : 0]);
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
+  DevState& S0 = state_of(plans[0]);
   const bool use_graph = n > 0 && stream != nullptr;
   std::vector<const jf_plan*> key(plans, plans + n);
   std::vector<unsigned> gens(n);
@@ -1117,8 +1127,6 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   float ms = 0;
   JF_HIP(hipEventElapsedTime(&ms, e0, e1));
   for (int i = 0; i < n; ++i) out[i].seconds = ms * 1e-3;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   return JF_OK;
 }
 

@@ -413,6 +413,18 @@ def test_chains_in_graphs_batches_and_decisions():
             assert d["decision"] == (1 if ref > 1 - eps else 0)
 
 
+def test_alg2_chains_against_oracle():
+    for seed in (8, 16, 23):
+        inst = gen.random_circuit(4 + seed % 3, 40 + 6 * seed, 2 + seed % 3, 0.01, 0.3, 2100 + seed)
+        p = jf.plan(inst, 2, "c64")
+        assert any(x["chain"] >= 0 for x in p.describe())
+        say("alg2 chains", seed)
+        ws = jf.workspace(p.info()["workspace_bytes"])
+        got = jf.jf_fidelity_alg2(p, ws)
+        assert any(r["variant"] == jf.KV_CHAIN for r in jf.jf_profile_steps(p, ws))
+        assert abs(got["fj"] - dense.fidelity_alg2(inst)["fj"]) <= TOL["c64"]
+
+
 def test_chain_at_full_size_is_bitwise_the_gauss_steps():
     # the n=16 workload's plan chains its 2^26-element in-place steps (32 x 32 blocks) and others;
     # with the Gauss-form kernel forced on every step that takes it, running the chains and running

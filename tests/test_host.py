@@ -243,3 +243,18 @@ def test_emulated_chains_match_oracle_and_unchained_program():
         plain = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_CHAIN).emulate()
         assert np.max(np.abs(chained - want)) < 1e-12
         assert np.max(np.abs(chained - plain)) < 1e-13
+
+
+def _alg2_chain_instances():
+    # Algorithm II complex64 plans of this family hold chains (checked below)
+    for seed in (8, 16, 23):
+        yield gen.random_circuit(4 + seed % 3, 40 + 6 * seed, 2 + seed % 3, 0.01, 0.3, 2100 + seed)
+
+
+def test_emulated_alg2_chains_match_oracle():
+    for inst in _alg2_chain_instances():
+        p = jf.plan(inst, 2, "c64")
+        assert sum(x["chain"] >= 0 for x in p.describe()) >= 2
+        want = dense.fidelity_alg2(inst)["fj"]
+        got = p.emulate()[0]
+        assert abs(got.real - want) < 1e-12 and abs(got.imag) < 1e-12
