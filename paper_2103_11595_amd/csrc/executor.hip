@@ -60,6 +60,7 @@ struct DevState {
   // per component, per chain: 1 = run its steps one launch each (the autotuner found the chain
   // slower, or a kernel variant was forced on every step)
   std::vector<std::vector<char>> chain_off;
+  bool validated = false;                   // the program passed validate_program (plans are immutable)
   hipEvent_t ev_order = nullptr, ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -620,10 +621,13 @@ jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
 
 jf_status check_ws(jf_plan* p, void* ws, size_t ws_bytes) {
   DevState& S = state_of(p);
-  std::string why;
-  if (!validate_program(p->prog, why)) {
-    set_error("plan failed validation: " + why);
-    return JF_E_ARG;
+  if (!S.validated) {
+    std::string why;
+    if (!validate_program(p->prog, why)) {
+      set_error("plan failed validation: " + why);
+      return JF_E_ARG;
+    }
+    S.validated = true;
   }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) {
     set_error("workspace must be a 256-byte aligned device pointer");
