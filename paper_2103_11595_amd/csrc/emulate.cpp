@@ -58,6 +58,7 @@ bool validate_program(const Program& P, std::string& why) {
       std::vector<char> seen(rA > 0 ? rA : 0, 0);
       for (int b : ch.P) ok = ok && b >= 0 && b < rA && !seen[b] && (seen[b] = 1);
       for (int b : ch.hi) ok = ok && b >= 0 && b < rA && !seen[b] && (seen[b] = 1);
+      for (int b = 0; b < 4 && b < rA; ++b) ok = ok && std::count(ch.P.begin(), ch.P.end(), b) == 1;  // whole lines
       int ops = 0, lvl = -1;
       for (int s = ch.first; ok && s < ch.last; ++s) {
         const Step& st = cp.steps[s];

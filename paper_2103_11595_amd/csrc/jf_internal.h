@@ -116,7 +116,7 @@ struct Step {
 // intermediate crosses HBM once for the whole chain.
 constexpr int CHAIN_MAX_STEPS = 8;   // steps per chain
 constexpr int CHAIN_MAX_T = 12;      // log2 elements of a tile (32 KB of complex64)
-constexpr int CHAIN_MAX_U = 9;       // contracted positions of a chain
+constexpr int CHAIN_MAX_U = 10;      // contracted positions of a chain
 constexpr int CHAIN_MAX_OPS = 4096;  // sum of K^2 over the chain's steps (operators in LDS)
 struct Chain {
   int first = 0, last = 0;       // steps of the component

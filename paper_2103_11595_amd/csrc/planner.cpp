@@ -205,6 +205,10 @@ bool chain_tile(const std::set<int>& U, int rA, int ksmax, Chain& ch) {
       ch.hi.push_back(b);
     }
   }
+  // the tile holds whole 128-byte lines (16 complex64 elements: bits 0..3), so no line is
+  // fetched or written by two tiles
+  for (int q = 0; q < 4 && q < rA; ++q)
+    if (std::find(ch.P.begin(), ch.P.end(), q) == ch.P.end()) return false;
   ch.T = T;
   ch.nTiles = 1LL << ch.hi.size();
   return int(ch.hi.size()) <= MAXHI;

@@ -229,7 +229,7 @@ def test_chains_group_consecutive_in_place_steps():
                 assert x["compute"] == "f32" and x["kS"] == x["kN"] <= 5       # single-term FP32
                 assert x["sA"] == x["nC"] and x["rowsA"] == x["rowsC"] and x["rA"] == x["rC"]
                 union |= set(x["sA"])
-            assert len(union) <= 9
+            assert len(union) <= 10
     # complex128 and 3xBF16 plans and JF_FLAG_NO_CHAIN have none
     for dt, flags in (("c128", 0), ("bf16x3", 0), ("c64", jf.JF_FLAG_NO_CHAIN)):
         assert all(x["chain"] == -1 for x in jf.plan(gen.config2(), 1, dt, flags=flags).describe())
