@@ -425,6 +425,24 @@ def test_alg2_chains_against_oracle():
         assert abs(got["fj"] - dense.fidelity_alg2(inst)["fj"]) <= TOL["c64"]
 
 
+def test_chains_of_single_gate_steps_against_oracle():
+    # one step per tensor and no cancellation: chains of 2 x 2 and 4 x 4 operators (the lane groups
+    # past K of the kernel's k-steps supply zeros, the rows past K are not stored)
+    inst = gen.random_circuit(8, 60, 2, 0.01, 0.3, 3003)
+    flags = jf.JF_FLAG_NO_FUSE | jf.JF_FLAG_NO_CANCEL
+    p = jf.plan(inst, 1, "c64", flags=flags)
+    q = jf.plan(inst, 1, "c64", flags=flags | jf.JF_FLAG_NO_CHAIN)
+    ws = jf.workspace(max(p.info()["workspace_bytes"], q.info()["workspace_bytes"]))
+    a = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+    chains = [r for r in jf.jf_profile_steps(p, ws) if r["variant"] == jf.KV_CHAIN]
+    assert chains and min(r["kS"] for r in chains) <= 2
+    b = jf.jf_fidelity_alg1(q, ws, want_terms=True)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    assert abs(a["fj"] - ref["fj"]) <= TOL["c64"]
+    assert np.max(np.abs(a["terms"] - _terms(ref))) <= 1e-6
+    assert np.max(np.abs(a["terms"] - b["terms"])) <= 1e-6
+
+
 def test_chain_at_full_size_is_bitwise_the_gauss_steps():
     # the n=16 workload's plan chains its 2^26-element in-place steps (32 x 32 blocks) and others;
     # with the Gauss-form kernel forced on every step that takes it, running the chains and running

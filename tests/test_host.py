@@ -258,3 +258,14 @@ def test_emulated_alg2_chains_match_oracle():
         want = dense.fidelity_alg2(inst)["fj"]
         got = p.emulate()[0]
         assert abs(got.real - want) < 1e-12 and abs(got.imag) < 1e-12
+
+
+def test_emulated_chains_of_single_gate_steps():
+    # one step per tensor and no cancellation: chains of 2 x 2 and 4 x 4 operators
+    inst = gen.random_circuit(8, 60, 2, 0.01, 0.3, 3003)
+    p = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_FUSE | jf.JF_FLAG_NO_CANCEL)
+    ks = {x["kS"] for x in p.describe() if x["chain"] >= 0}
+    assert {1, 2} <= ks
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    assert np.max(np.abs(p.emulate() - want)) < 1e-12
