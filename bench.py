@@ -49,6 +49,21 @@ def cpu_baseline(budget_s: float = 25.0) -> dict:
                       f"(same generator; n=16 infeasible densely), {dt:.1f} s"}
 
 
+def cpu_plan_executor(plan, fj_gpu: float) -> dict:
+    """The same lowered program executed on the host (the library's FP64 step emulation, one
+    thread): one full pass over all Kraus terms of the workload itself.  Not the oracle -- it runs
+    the planner's path -- and reported beside the oracle baseline only."""
+    import numpy as np
+    t0 = time.perf_counter()
+    terms = plan.emulate()
+    dt = time.perf_counter() - t0
+    fj = float(np.sum(np.abs(terms) ** 2))
+    return {"value": len(terms) / dt, "unit": "Kraus-term contractions/s", "cores": 1,
+            "kind": "host execution of the same lowered program (FP64 step emulation), not the oracle",
+            "sample": f"one full pass of the workload's complex128 plan, {len(terms)} Kraus terms, {dt:.1f} s",
+            "abs_dfj_vs_gpu_c128": abs(fj - fj_gpu)}
+
+
 def traffic_record(kernel_sha: str, launches: int, algorithmic_bytes: float):
     """HBM bytes per launch from the committed counter record, if it was taken with the same
     kernels on the same program (same launches and algorithmic bytes); else None."""
@@ -423,6 +438,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        if "c128" in res:
+            out["cpu_plan_executor"] = cpu_plan_executor(res["c128"]["plan"], res["c128"]["r"]["fj"])
     print(json.dumps(out))
 
 
