@@ -189,7 +189,13 @@ namespace {
 bool chain_tile(const std::set<int>& U, int rA, int ksmax, Chain& ch) {
   const int u = int(U.size());
   if (u > CHAIN_MAX_U || rA < u) return false;
-  const int rows = std::min(CHAIN_MAX_T - u, rA - u);
+  int rows = std::min(CHAIN_MAX_T - u, rA - u);
+  // a smaller tile for a smaller intermediate, so that there are 2^10 tiles or more (several per
+  // resident workgroup) where the tile can shrink: it keeps 16 rows per step (T - kS >= 4) and
+  // bits 0-3
+  int low_free = 0;
+  for (int q = 0; q < 4 && q < rA; ++q) low_free += U.count(q) ? 0 : 1;
+  while (u + rows > rA - 10 && rows - 1 >= low_free && u + rows - 1 - ksmax >= 4) --rows;
   const int T = u + rows;
   if (T - ksmax < 4) return false;
   ch.P.clear();
