@@ -147,7 +147,11 @@ long long scatter(long long x, const std::vector<int>& pos) {
 struct CostModel {
   double bw = 5.2e12;        // effective bytes/s
   double flops = 28e12;      // effective flop/s (FP64 MFMA)
-  double launch = 4e-6;      // seconds per step
+  // seconds per launch: a step kernel's dispatch and set-up in a running program (an empty kernel
+  // alone reads 3.8 us with dispatch events); 7 fits the latency-bound plans (the 36-qubit chain:
+  // 0.168 ms estimated, 0.170 measured) and gives the 25-qubit chain 65 launches for 70 at 4 us
+  // (0.62 against 0.66 ms); the n=16 plan changes little (0.995 against 1.014 ms)
+  double launch = 7e-6;
   // complex64 chains (k_chain), algorithmic flop/s: measured 65-115 TFLOP/s on MI355X (2^22 to 2^26
   // elements); 80 picks the faster n=16 plan (1.01 ms per pass against 1.07 ms with 115)
   double chain_flops = 80e12;
