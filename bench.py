@@ -8,6 +8,8 @@ One step = one full pass of the hot path over the workload: every contraction st
 for all 256 Kraus tuples, the FP64 closing contractions, the Kahan-compensated sum and the
 readback of F_J.  Planning, the one-time upload of the step program and the kernel autotuner
 (which times every kernel that can run each step and keeps the fastest) happen before timing.
+The plans are made with JF_FLAG_GRAPH and run on a non-default stream: each pass replays the step
+program as one captured hipGraph (3% faster than launching it step by step from the host).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -320,6 +322,7 @@ def main():
     if args.config != "cfg2":
         return run_single(args, torch, gen, jf, stream)
     inst = gen.config2()
+    stream = torch.cuda.Stream()  # default priority; the passes replay a hipGraph captured on it
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 2**20
@@ -331,7 +334,7 @@ def main():
     forms = [args.dtype] if args.only else [args.dtype] + [d for d in ("c128", "c64", "bf16x3") if d != args.dtype]
     res = {}
     for dt in forms:
-        p = jf.plan(inst, 1, dt)
+        p = jf.plan(inst, 1, dt, flags=jf.JF_FLAG_GRAPH)
         info = p.info()
         ws = jf.workspace(info["workspace_bytes"])
         main = dt == args.dtype
@@ -415,7 +418,8 @@ def main():
         "data": "synthetic (seeded generator, no datasets)",
         "config": {"workload": "alg1 batched: n=16 qubits, 400 random gates (70% H/S/T/RZ, 30% CX), "
                                "4 depolarising sites p~U[1e-3,1e-2], 256 Kraus-index miter networks",
-                   "alg": 1, "seed": 2, "kraus_terms": terms},
+                   "alg": 1, "seed": 2, "kraus_terms": terms,
+                   "launch": "hipGraph replay of the step program on a non-default stream"},
         "contraction_tflops": main_form["info"]["path_flops"] / main_form["sec"] / 1e12,
         "forms": {dt: {"kraus_terms_per_s": terms / v["sec"], "ms_per_step": v["sec"] * 1e3,
                        "tflops": v["info"]["path_flops"] / v["sec"] / 1e12, "fj": v["r"]["fj"],
