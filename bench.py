@@ -111,8 +111,12 @@ def run_single(args, torch, gen, jf, stream):
     for site in inst["noise"]:
         covered *= 4 if site["channel"] == "depolarizing" else 2
     res = {}
+    graph = args.graph if args.graph >= 0 else int(args.config != "cfg1")
+    flags = jf.JF_FLAG_GRAPH if graph else 0
+    if graph:
+        stream = torch.cuda.Stream()  # default priority; the passes replay a hipGraph captured on it
     for dt in (args.dtype,) + tuple(d for d in ("c128", "c64", "bf16x3") if d != args.dtype):
-        p = jf.plan(inst, alg, dt)
+        p = jf.plan(inst, alg, dt, flags=flags)
         info = p.info()
         ws = jf.workspace(info["workspace_bytes"])
         run = (lambda: jf.jf_fidelity_alg1(p, ws, stream)) if alg == 1 else (lambda: jf.jf_fidelity_alg2(p, ws, stream))
@@ -128,7 +132,8 @@ def run_single(args, torch, gen, jf, stream):
            "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": m["sec"] * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
            "data": "synthetic (seeded generator, no datasets)",
-           "config": {"workload": desc, "alg": alg, "kraus_terms_covered": covered},
+           "config": {"workload": desc, "alg": alg, "kraus_terms_covered": covered,
+                      "launch": "hipGraph replay on a non-default stream" if graph else "eager launches"},
            "kraus_terms_covered_per_s": covered / m["sec"],
            "forms": {dt: {"per_s": (v["info"]["kraus_terms"] if alg == 1 else 1) / v["sec"], "ms_per_step": v["sec"] * 1e3,
                           "fj": v["r"]["fj"], "one_minus_fj": v["r"]["one_minus_fj"],
@@ -300,6 +305,11 @@ def main():
     ap.add_argument("--batch-cap", type=int, default=32, help="cfg4: log2 size cap of the members' intermediates")
     ap.add_argument("--replan-s", type=float, default=60.0,
                     help="cfg4: host time for re-planning the costliest members at a higher search effort")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="--config cfg1/3/5: replay each pass as one hipGraph on a non-default stream (1) or "
+                         "launch every step from the host on the current stream (0); default: 1 for the "
+                         "many-step Alg II chains (cfg3 0.61 against 0.63 ms, cfg5 0.157 against 0.165 ms), "
+                         "0 for the one-launch n=5 workload (36 us eager, 64 us as a graph)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB with torch (a plain copy kernel of known size, "
                          "the reference for hardware byte counters)")
