@@ -414,7 +414,7 @@ def test_chains_in_graphs_batches_and_decisions():
 
 
 def test_alg2_chains_against_oracle():
-    for seed in (8, 16, 23):
+    for seed in (16, 22, 28):
         inst = gen.random_circuit(4 + seed % 3, 40 + 6 * seed, 2 + seed % 3, 0.01, 0.3, 2100 + seed)
         p = jf.plan(inst, 2, "c64")
         assert any(x["chain"] >= 0 for x in p.describe())

@@ -247,7 +247,7 @@ def test_emulated_chains_match_oracle_and_unchained_program():
 
 def _alg2_chain_instances():
     # Algorithm II complex64 plans of this family hold chains (checked below)
-    for seed in (8, 16, 23):
+    for seed in (16, 22, 28):
         yield gen.random_circuit(4 + seed % 3, 40 + 6 * seed, 2 + seed % 3, 0.01, 0.3, 2100 + seed)
 
 
