@@ -167,6 +167,7 @@ typedef struct {
   double empty_loops;
   int alg;             /* 1 or 2: the algorithm of the plan */
   double est_seconds;  /* planner's cost-model estimate of one run's device time */
+  int n_swaps_rewired; /* SWAP gates (after the cancellation) replaced by crossed wires */
 } jf_plan_stats;
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 

@@ -103,6 +103,7 @@ extern "C" jf_status jf_plan_stats_get(const jf_plan* p, jf_plan_stats* s) {
   r.empty_loops = p->prog.empty_loops;
   r.alg = p->prog.opt.alg;
   r.est_seconds = p->prog.est_seconds;
+  r.n_swaps_rewired = p->prog.n_swaps_rewired;
   *s = r;
   return JF_OK;
 }

@@ -75,6 +75,7 @@ struct Network {
 
 Network build_network(const jf_circuit& c, int alg);
 void cancel_inverse_pairs(Network& net);
+int rewire_swaps(Network& net);  // returns the number of SWAP tensors removed
 void trace_self_loops(Network& net);
 std::vector<std::vector<int>> components(const Network& net);
 int count_empty_loops(const Network& net);
@@ -192,7 +193,7 @@ struct Program {
   std::vector<int> site_comp;      // component holding each site (-1: none)
   std::vector<std::vector<double>> site_norm2;  // squared operator norm of every Kraus operator
   long long kraus_terms = 1;
-  int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0;
+  int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0, n_swaps_rewired = 0;
   double planner_seconds = 0;
   double flops = 0, bytes = 0;
   double est_seconds = 0;          // cost-model estimate of the device time of one run

@@ -236,6 +236,53 @@ void cancel_inverse_pairs(Network& net) {
   net.T = std::move(kept);
 }
 
+// SWAP gates carry no arithmetic (Section IV-C lists the exact simplifications): each one left
+// after the cancellation is removed and its wires are joined crosswise, the out leg of qubit j
+// becoming the in leg of the other qubit (its entry is 1 exactly where out_0 = in_1 and
+// out_1 = in_0, for U, U^dagger and their conjugates alike).  Joins are taken with union-find,
+// so runs of SWAPs collapse; a wire closed on itself by SWAPs alone ends as an empty loop.
+int rewire_swaps(Network& net) {
+  auto is_swap = [](const Tensor& t) {
+    if (t.kind != T_GATE || !t.src || t.src->nq != 2 || t.ins.size() != 2 || t.outs.size() != 2) return false;
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        const bool one = c == ((r & 1) << 1 | (r >> 1));
+        if (t.src->m[r * 4 + c] != cd(one ? 1.0 : 0.0, 0.0)) return false;
+      }
+    return true;
+  };
+  std::vector<int> parent(net.leg_alive.size());
+  std::iota(parent.begin(), parent.end(), 0);
+  std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
+  auto join = [&](int a, int b) {
+    a = find(a);
+    b = find(b);
+    if (a == b) return;
+    if (a < b) std::swap(a, b);
+    parent[a] = b;  // the smaller id stays
+    net.leg_alive[a] = 0;
+  };
+  std::vector<Tensor> kept;
+  int removed = 0;
+  for (auto& t : net.T) {
+    if (is_swap(t)) {
+      join(t.outs[0], t.ins[1]);
+      join(t.outs[1], t.ins[0]);
+      ++removed;
+    } else {
+      kept.push_back(std::move(t));
+    }
+  }
+  for (auto& t : kept) {
+    for (auto& l : t.legs) l = find(l);
+    for (auto& l : t.ins) l = find(l);
+    for (auto& l : t.outs) l = find(l);
+    for (auto& l : t.var_legs) l = find(l);
+  }
+  net.T = std::move(kept);
+  return removed;
+}
+
 // Empty loops: a wire whose every tensor was cancelled leaves one live leg that no tensor
 // references; it is a closed loop worth tr(I_2) = 2.
 int count_empty_loops(const Network& net) {

@@ -345,7 +345,10 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   P.n_qubits = c.n;
   Network net = build_network(c, opt.alg);
   P.n_before_cancel = net.n_before_cancel;
-  if (!(opt.flags & JF_FLAG_NO_CANCEL)) cancel_inverse_pairs(net);
+  if (!(opt.flags & JF_FLAG_NO_CANCEL)) {
+    cancel_inverse_pairs(net);
+    P.n_swaps_rewired = rewire_swaps(net);
+  }
   P.n_after_cancel = int(net.T.size());
   P.empty_loops = count_empty_loops(net);
   trace_self_loops(net);

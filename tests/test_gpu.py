@@ -443,6 +443,29 @@ def test_chains_of_single_gate_steps_against_oracle():
     assert np.max(np.abs(a["terms"] - b["terms"])) <= 1e-6
 
 
+def test_rewired_swaps_against_oracle():
+    import random
+    for seed in (1, 4, 5):
+        inst = gen.random_circuit(4 + seed % 3, 40 + 10 * seed, 1 + seed % 3, 0.01, 0.3, 4000 + seed)
+        r = random.Random(seed)
+        gates = [list(g) for g in inst["gates"]]
+        noise = [dict(x) for x in inst["noise"]]
+        for _ in range(6 + seed):
+            a, b = r.sample(range(inst["n"]), 2)
+            pos = r.randrange(len(gates) + 1)
+            gates.insert(pos, ["swap", [a, b], []])
+            for x in noise:
+                if x["after"] >= pos:
+                    x["after"] += 1
+        inst = dict(inst, gates=gates, noise=noise)
+        assert jf.plan(inst, 1, "c128").stats()["n_swaps_rewired"] > 0
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        got = run1(inst, "c128")
+        assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12
+        assert abs(run1(inst, "c64")["fj"] - ref["fj"]) <= TOL["c64"]
+        assert abs(run2(inst, "c128")["fj"] - ref["fj"]) <= 1e-12
+
+
 def test_chain_at_full_size_is_bitwise_the_gauss_steps():
     # the n=16 workload's plan chains its 2^26-element in-place steps (32 x 32 blocks) and others;
     # with the Gauss-form kernel forced on every step that takes it, running the chains and running

@@ -269,3 +269,57 @@ def test_emulated_chains_of_single_gate_steps():
     ref = dense.fidelity_alg1(inst, want_terms=True)
     want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
     assert np.max(np.abs(p.emulate() - want)) < 1e-12
+
+
+# --- SWAP gates become crossed wires -------------------------------------------------------
+
+def _with_swaps(inst, k, seed):
+    import random
+    r = random.Random(seed)
+    gates = [list(g) for g in inst["gates"]]
+    noise = [dict(x) for x in inst.get("noise", [])]
+    for _ in range(k):
+        a, b = r.sample(range(inst["n"]), 2)
+        pos = r.randrange(len(gates) + 1)
+        gates.insert(pos, ["swap", [a, b], []])
+        for x in noise:
+            if x["after"] >= pos:
+                x["after"] += 1
+    return dict(inst, gates=gates, noise=noise)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_swaps_rewired_exactly(seed):
+    inst = _with_swaps(gen.random_circuit(4 + seed % 3, 40 + 10 * seed, 1 + seed % 3, 0.01, 0.3, 4000 + seed),
+                       6 + seed, seed)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    p = jf.plan(inst, 1, "c128")
+    q = jf.plan(inst, 1, "c128", flags=jf.JF_FLAG_NO_CANCEL)   # no simplification: every SWAP a tensor
+    assert q.stats()["n_swaps_rewired"] == 0
+    if seed in (1, 4, 5):   # these keep SWAPs inside the noise light cone
+        assert p.stats()["n_swaps_rewired"] > 0
+    assert np.max(np.abs(p.emulate() - want)) < 1e-12
+    assert np.max(np.abs(q.emulate() - want)) < 1e-12
+    p2 = jf.plan(inst, 2, "c128")
+    assert abs(p2.emulate()[0].real - ref["fj"]) < 1e-12   # Algorithm II against the same F_J
+
+
+def test_swap_network_closes_into_loops():
+    # SWAPs alone, no noise: every wire closes on itself through crossed wires, F_J = 1
+    inst = {"n": 3, "gates": [["swap", [0, 1], []], ["swap", [1, 2], []], ["h", [0], []]], "noise": []}
+    r = jf.plan(inst, 1, "c128")
+    assert abs(r.emulate()[0] - 1.0) < 1e-15
+    # a SWAP between two noise sites survives the cancellation and is rewired: the channel on
+    # qubit 0 before it and the one on qubit 1 after it hit the same logical qubit, a depolarising
+    # chain with F_J = (1 + 3 (1 - 4 p_a / 3)(1 - 4 p_b / 3)) / 4
+    pa, pb = 0.1, 0.05
+    inst = {"n": 3, "gates": [["swap", [0, 1], []], ["h", [2], []]],
+            "noise": [{"after": -1, "qubit": 0, "channel": "depolarizing", "p": pa},
+                      {"after": 0, "qubit": 1, "channel": "depolarizing", "p": pb}]}
+    p = jf.plan(inst, 1, "c128")
+    assert p.stats()["n_swaps_rewired"] == 2   # the SWAP of E and the one of U^dagger
+    lam = (1 - 4 * pa / 3) * (1 - 4 * pb / 3)
+    assert abs(float(np.sum(np.abs(p.emulate()) ** 2)) - (1 + 3 * lam) / 4) < 1e-14
+    assert abs(dense.fidelity_alg1(inst)["fj"] - (1 + 3 * lam) / 4) < 1e-14
+    assert abs(jf.plan(inst, 2, "c128").emulate()[0].real - (1 + 3 * lam) / 4) < 1e-14
