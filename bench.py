@@ -160,6 +160,48 @@ def run_single(args, torch, gen, jf, stream):
     print(json.dumps(out))
 
 
+def run_crossover(args, torch, gen, jf, stream):
+    """Algorithm I against Algorithm II as the number of noise sites grows (the synthetic analogue of
+    the paper's comparison of the two algorithms over the noise count): one 10-qubit, 200-gate
+    circuit family of the workload generator, m = 1..14 depolarising sites (p = 1e-3), both
+    algorithms in complex128, each timed on the GPU after autotuning; the automatic choice
+    (alg = 0, the smaller cost-model time) is checked against the measured times."""
+    rows = []
+    for m in (1, 2, 4, 6, 8, 10, 12, 14):
+        inst = gen.random_circuit(10, 200, m, 1e-3, 1e-3, 700 + m)
+        row = {"sites": m, "kraus_terms": 4 ** m}
+        for alg in (1, 2):
+            try:
+                p = jf.plan(inst, alg, "c128", flags=jf.JF_FLAG_EFFORT(8))
+            except jf.JfError as e:
+                row[f"alg{alg}"] = {"infeasible": str(e)[:80]}
+                continue
+            ws = jf.workspace(p.info()["workspace_bytes"])
+            run = (lambda: jf.jf_fidelity_alg1(p, ws, stream)) if alg == 1 else (lambda: jf.jf_fidelity_alg2(p, ws, stream))
+            run()
+            jf.jf_autotune(p, ws, stream)
+            r, sec = _timed(torch, run, 5)
+            row[f"alg{alg}"] = {"ms": sec * 1e3, "est_ms": p.stats()["est_seconds"] * 1e3, "fj": r["fj"],
+                                "max_log2_intermediate": p.info()["max_log2_intermediate"],
+                                "work_items": p.info()["work_items"]}
+            del ws
+        auto = jf.plan(inst, 0, "c128", flags=jf.JF_FLAG_EFFORT(8)).alg
+        row["auto"] = auto
+        if "ms" in row.get("alg1", {}) and "ms" in row.get("alg2", {}):
+            row["faster"] = 1 if row["alg1"]["ms"] <= row["alg2"]["ms"] else 2
+            row["abs_dfj_alg1_alg2"] = abs(row["alg1"]["fj"] - row["alg2"]["fj"])
+        progress(f"crossover m={m}: {row}")
+        rows.append(row)
+    agree = [r["auto"] == r["faster"] for r in rows if "faster" in r]
+    out = {"metric": "Algorithm I vs Algorithm II time over the noise count (complex128)", "value": sum(agree) / max(1, len(agree)),
+           "unit": "fraction of sizes where the automatic choice is the faster algorithm", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic (seeded generator, no datasets)",
+           "config": {"workload": "n=10, 200 random gates (70% H/S/T/RZ, 30% CX), m depolarising sites p=1e-3",
+                      "planner_effort": 8},
+           "rows": rows}
+    print(json.dumps(out))
+
+
 def run_batch(args, torch, gen, jf, stream):
     """The 512-circuit batch under the budget rule: plan every member (reduced search effort, size
     cap 2^32), spend more search on the costliest ones within --replan-s of host time (keeping the
@@ -298,7 +340,7 @@ def main():
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"], help="form reported as value")
     ap.add_argument("--only", action="store_true", help="run only the reported form (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true", help="time the fixed kernel rule only")
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"],
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "crossover"],
                     help="workload: cfg2 (default) the n=16 Alg I workload; cfg1 n=5 Alg I; cfg3 n=25 chain Alg II; "
                          "cfg4 the 512-circuit batch (budget rule); cfg5 n=36 chain Alg II")
     ap.add_argument("--budget-s", type=float, default=60.0, help="cfg4: GPU time budget for the cost-sorted work list")
@@ -329,6 +371,8 @@ def main():
     stream = torch.cuda.current_stream()
     if args.config == "cfg4":
         return run_batch(args, torch, gen, jf, stream)
+    if args.config == "crossover":
+        return run_crossover(args, torch, gen, jf, stream)
     if args.config != "cfg2":
         return run_single(args, torch, gen, jf, stream)
     inst = gen.config2()

@@ -31,6 +31,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct DevLayout {
   size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
+  size_t sumsq_off = 0;  // scratch of the two-pass sum of |t|^2 (2 SUMSQ_BLOCKS doubles)
   size_t lds_items_off = 0, lds_steps_off = 0;
   std::vector<int> lds_comps;                             // components run by the persistent kernel
   int lds_steps = 0;
@@ -183,6 +184,8 @@ void build_layout(const Program& P, DevState& S) {
   off += align256(size_t(outn) * 16);
   L.sums_off = off;
   off += align256(P.comps.size() * 4 * sizeof(double));
+  L.sumsq_off = off;
+  off += align256(2 * SUMSQ_BLOCKS * sizeof(double));
   L.total = off;
 
   // host image of descriptors, pools and constants
@@ -600,7 +603,8 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
     jf_status st = enqueue_component(p, ws, stream, c, prof, tune);
     if (st != JF_OK) return st;
     JF_HIP(launch_sumsq(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
-                        reinterpret_cast<double*>(ws + L.sums_off) + 4 * c, stream));
+                        reinterpret_cast<double*>(ws + L.sums_off) + 4 * c,
+                        reinterpret_cast<double*>(ws + L.sumsq_off), stream));
   }
   return JF_OK;
 }
@@ -919,7 +923,8 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
       st = enqueue_component(p, w, stream, c, nullptr, nullptr);
       if (st != JF_OK) return st;
       JF_HIP(launch_sumsq(w + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
-                          reinterpret_cast<double*>(w + L.sums_off) + 4 * c, stream));
+                          reinterpret_cast<double*>(w + L.sums_off) + 4 * c,
+                          reinterpret_cast<double*>(w + L.sumsq_off), stream));
     }
     std::vector<double> sums(4 * P.comps.size());
     JF_HIP(hipMemcpyAsync(sums.data(), w + L.sums_off, sums.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -965,7 +970,7 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
                            nullptr, nullptr);
         if (st != JF_OK) return st;
       }
-      JF_HIP(launch_sumsq(out_last, cp.out_len, sums_last, stream));
+      JF_HIP(launch_sumsq(out_last, cp.out_len, sums_last, reinterpret_cast<double*>(w + L.sumsq_off), stream));
       double part[2];
       JF_HIP(hipMemcpyAsync(part, sums_last, sizeof(part), hipMemcpyDeviceToHost, stream));
       JF_HIP(hipStreamSynchronize(stream));

@@ -120,8 +120,10 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
 
-// sums[0..1] = double-double sum_i |x_i|^2 (Kahan/TwoSum, fixed reduction tree);
-// sums[2..3] = x_0 (re, im)
-hipError_t launch_sumsq(const void* x, long long n, double* sums, hipStream_t stream);
+// sums[0..1] = double-double sum_i |x_i|^2 (TwoSum, fixed partition and reduction trees);
+// sums[2..3] = x_0 (re, im).  scratch: 2 SUMSQ_BLOCKS doubles of device memory for the partial
+// sums of the first pass (used and released within the stream order of the call).
+constexpr int SUMSQ_BLOCKS = 1024;
+hipError_t launch_sumsq(const void* x, long long n, double* sums, double* scratch, hipStream_t stream);
 
 }  // namespace jf

@@ -14,7 +14,8 @@
 //   k_absorb_bf16x3_mfma BF16 matrix cores, three products per real product
 //   k_chain              several in-place FP32 steps applied to one LDS tile per HBM pass
 //   k_persistent         whole small components in one workgroup's LDS
-//   k_sumsq, k_zero      the FP64 double-double sum of |t|^2 and a graph-safe fill
+//   k_sumsq_part/_final  the FP64 double-double sum of |t|^2 (two fixed-tree passes)
+//   k_zero               a graph-safe fill
 // launch_step picks the kernel of a step (its variant, or the fixed rule).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -868,18 +869,12 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
   e = (a - (s - bb)) + (b - bb);
 }
 
-// double-double sum of |x_i|^2 with a fixed tree (deterministic)
-__global__ __launch_bounds__(256) void k_sumsq(const double2* x, long long n, double* out) {
-  __shared__ double sh[256], sl[256];
-  double hi = 0.0, lo = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) {
-    const double2 v = x[i];
-    const double p = fma(v.x, v.x, v.y * v.y);
-    double s, e;
-    two_sum(hi, p, s, e);
-    hi = s;
-    lo += e;
-  }
+// Double-double sum of |x_i|^2 with a fixed partition and fixed trees (deterministic): block b of
+// k_sumsq_part sums the chunk [b c, (b + 1) c) (thread t takes elements t, t + 256, ... of it, then a
+// tree over the block) into part[2b], part[2b + 1]; k_sumsq_final adds the G partials the same way
+// and writes out[0..1] = the sum, out[2..3] = x_0.  With one block the result is that of a single
+// block over all of x.
+__device__ __forceinline__ void dd_tree256(double* sh, double* sl, double hi, double lo) {
   sh[threadIdx.x] = hi;
   sl[threadIdx.x] = lo;
   __syncthreads();
@@ -894,6 +889,40 @@ __global__ __launch_bounds__(256) void k_sumsq(const double2* x, long long n, do
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_part(const double2* x, long long n, long long chunk, double* part) {
+  __shared__ double sh[256], sl[256];
+  const long long b0 = (long long)blockIdx.x * chunk;
+  const long long b1 = b0 + chunk < n ? b0 + chunk : n;
+  double hi = 0.0, lo = 0.0;
+  for (long long i = b0 + threadIdx.x; i < b1; i += 256) {
+    const double2 v = ld_stream(&x[i]);
+    const double p = fma(v.x, v.x, v.y * v.y);
+    double s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo += e;
+  }
+  dd_tree256(sh, sl, hi, lo);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0];
+    part[2 * blockIdx.x + 1] = sl[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_final(const double* part, int G, const double2* x, long long n,
+                                                     double* out) {
+  __shared__ double sh[256], sl[256];
+  double hi = 0.0, lo = 0.0;
+  for (int g = threadIdx.x; g < G; g += 256) {
+    double s, e;
+    two_sum(hi, part[2 * g], s, e);
+    e += lo + part[2 * g + 1];
+    hi = s + e;
+    lo = e - (hi - s);
+  }
+  dd_tree256(sh, sl, hi, lo);
   if (threadIdx.x == 0) {
     out[0] = sh[0];
     out[1] = sl[0];
@@ -1295,8 +1324,15 @@ hipError_t launch_zero(void* out, long long n, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const void* x, long long n, double* sums, hipStream_t stream) {
-  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, stream, (const double2*)x, n, sums);
+hipError_t launch_sumsq(const void* x, long long n, double* sums, double* scratch, hipStream_t stream) {
+  // at least 16K elements per block, at most SUMSQ_BLOCKS blocks
+  long long G = (n + 16383) / 16384;
+  if (G < 1) G = 1;
+  if (G > SUMSQ_BLOCKS) G = SUMSQ_BLOCKS;
+  const long long chunk = n > 0 ? (n + G - 1) / G : 0;
+  hipLaunchKernelGGL(k_sumsq_part, dim3(unsigned(G)), dim3(256), 0, stream, (const double2*)x, n, chunk, scratch);
+  hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(256), 0, stream, (const double*)scratch, int(G),
+                     (const double2*)x, n, sums);
   return hipGetLastError();
 }
 
