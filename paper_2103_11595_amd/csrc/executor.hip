@@ -204,6 +204,17 @@ void build_layout(const Program& P, DevState& S) {
         d.hiC[i] = st.hiC[i];
       }
       d.nHi = int(st.hiA.size());
+      for (int q = 0; q < DMAXHI / 4 * 16; ++q) {
+        const int c = q >> 4, m = q & 15;
+        long long a = 0, o = 0;
+        for (int b = 0; b < 4; ++b)
+          if (((m >> b) & 1) && 4 * c + b < d.nHi) {
+            a |= 1LL << st.hiA[4 * c + b];
+            o |= 1LL << st.hiC[4 * c + b];
+          }
+        d.digA[q] = a;
+        d.digC[q] = o;
+      }
       d.kS = st.kS;
       d.kN = st.kN;
       d.L = st.L;

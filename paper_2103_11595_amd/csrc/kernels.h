@@ -26,6 +26,9 @@ struct StepDesc {
   int mode;       // arithmetic of the step (see KernelMode)
   int variant;    // kernel used for it (see KernelVariant); read on the host only
   int pad[2];
+  // tile bases by 4-bit digits of the tile index: digit c with value m sets the address bits
+  // digA[16 c + m] (digC for C); the host fills them, the MFMA kernels copy them into LDS
+  long long digA[DMAXHI / 4 * 16], digC[DMAXHI / 4 * 16];
 };
 
 // Kernels that can run a step.  KV_AUTO applies the fixed rule of launch_step; the others are

@@ -129,22 +129,16 @@ __device__ __forceinline__ void load_tables(const StepDesc* __restrict__ d, Tabl
 // Tile base addresses of the MFMA kernels by table look-up: the tile index t is cut into 4-bit
 // digits and ch[c][m] holds the address bits that digit c with value m sets (bit b of the digit
 // sets bit hi[4 c + b]).  base(t) is then the OR of DMAXHI / 4 independent LDS reads (rows past
-// the tile bits are zero), where a loop over the bits of t would chain nHi dependent ones.
+// the tile bits are zero), where a loop over the bits of t would chain nHi dependent ones.  The
+// host computes the tables (StepDesc::digA, digC); a workgroup copies them into LDS.
 constexpr int NDIG = DMAXHI / 4;
 struct TileBases {
   long long chA[NDIG][16], chC[NDIG][16];
 };
-__device__ __forceinline__ void load_tile_bases(const StepDesc* __restrict__ d, TileBases& tbb, int nHi) {
+__device__ __forceinline__ void load_tile_bases(const StepDesc* __restrict__ d, TileBases& tbb, int) {
   for (int i = threadIdx.x; i < NDIG * 16; i += blockDim.x) {
-    const int c = i >> 4, m = i & 15;
-    long long a = 0, o = 0;
-    for (int b = 0; b < 4; ++b)
-      if (((m >> b) & 1) && 4 * c + b < nHi) {
-        a |= 1LL << d->hiA[4 * c + b];
-        o |= 1LL << d->hiC[4 * c + b];
-      }
-    tbb.chA[c][m] = a;
-    tbb.chC[c][m] = o;
+    tbb.chA[i >> 4][i & 15] = d->digA[i];
+    tbb.chC[i >> 4][i & 15] = d->digC[i];
   }
 }
 __device__ __forceinline__ long long tile_base(const long long (*ch)[16], long long t) {
