@@ -138,7 +138,10 @@ void gather_terms(const Program& p, const std::vector<std::vector<cd>>& comp_out
     for (size_t c = 0; c < p.comps.size(); ++c) {
       long long o = 0;
       for (int i = 0; i < m; ++i)
-        if (p.site_comp[i] == int(c)) o |= (long long)j[i] << p.comps[c].out_site_shift[i];
+        if (p.site_comp[i] == int(c)) {
+          const std::vector<int>& ob = p.comps[c].out_bit[i];
+          for (size_t b = 0; b < ob.size(); ++b) o |= (long long)((j[i] >> b) & 1) << ob[b];
+        }
       t *= comp_out[c][o];
     }
     tt[2 * idx] = t.real();

@@ -150,7 +150,10 @@ struct ComponentProgram {
   std::vector<Step> steps;
   std::vector<Level> levels;
   int n_open_bits = 0;           // bits of this component's output (padded variant index)
-  std::vector<int> out_site_shift; // per network site: bit offset in the component output (-1: absent)
+  // per network site: output bit of each Kraus-index bit (empty: not in this component).  Sliced
+  // sites hold the top bits, one contiguous run each; the open sites' bits follow the final
+  // step's own layout, so its writes are as contiguous as its reads.
+  std::vector<std::vector<int>> out_bit;
   long long out_len = 1;         // complex entries of the component output
   long long leaves = 1;          // DFS leaves
   double flops = 0, bytes = 0;

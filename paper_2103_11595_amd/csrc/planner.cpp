@@ -16,6 +16,7 @@
 // of Section IV-C in the form of a prefix stack.
 #include <algorithm>
 #include <iterator>
+#include <stdexcept>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -386,7 +387,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // ---- site bookkeeping: open legs of this component, output bit offsets
     ComponentProgram cp;
     cp.n_tensors = N;
-    cp.out_site_shift.assign(c.sites.size(), -1);
+    cp.out_bit.assign(c.sites.size(), std::vector<int>());
     std::vector<int> comp_sites;
     for (int i = 0; i < N; ++i)
       if (L.ts[i]->kind == T_SLOT || (L.ts[i]->site >= 0 && opt.alg == 1 && !L.ts[i]->var_legs.empty()))
@@ -396,16 +397,16 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     for (int i = 0; i < N; ++i)
       if (opt.alg == 1 && L.ts[i]->site >= 0) comp_sites.push_back(L.ts[i]->site);
     std::sort(comp_sites.begin(), comp_sites.end());
+    comp_sites.erase(std::unique(comp_sites.begin(), comp_sites.end()), comp_sites.end());
     {
-      int shift = 0;
-      for (int k = int(comp_sites.size()) - 1; k >= 0; --k) {  // last site in time = lowest bits
-        int si = comp_sites[k];
-        cp.out_site_shift[si] = shift;
-        shift += int(net.site_var_legs[si].size());
+      int nbits = 0;
+      for (int si : comp_sites) {
+        nbits += int(net.site_var_legs[si].size());
+        cp.out_bit[si].assign(net.site_var_legs[si].size(), -1);
         P.site_comp[si] = int(P.comps.size());
       }
-      cp.n_open_bits = shift;
-      cp.out_len = 1LL << shift;
+      cp.n_open_bits = nbits;
+      cp.out_len = 1LL << nbits;
     }
     // global leg id -> (site, bit)
     std::map<int, std::pair<int, int>> open_of;
@@ -793,6 +794,20 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
     }
     level_start.push_back(N);
+    // output bits: the sliced sites take the top ones (last level lowest, one run per site, so a
+    // variant's offset is v << run start); the open sites' bits are placed by the final step
+    {
+      int free_bits = cp.n_open_bits;
+      for (int si : level_site)
+        if (si >= 0) free_bits -= int(net.site_var_legs[si].size());
+      int shift = free_bits;
+      for (int lv = int(level_site.size()) - 1; lv >= 0; --lv) {
+        const int si = level_site[lv];
+        if (si < 0) continue;
+        for (size_t b = 0; b < cp.out_bit[si].size(); ++b) cp.out_bit[si][b] = shift + int(b);
+        shift += int(cp.out_bit[si].size());
+      }
+    }
 
     auto restrict_variant = [&](const Tensor& t, int v) {
       // fix the Kraus-index legs of a slot tensor to operator v
@@ -830,7 +845,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       Lv.first = int(cp.steps.size());
       Lv.site = level_site[lv];
       Lv.nvar = Lv.site >= 0 ? net.site_nk[Lv.site] : 1;
-      Lv.out_stride = Lv.site >= 0 ? (1LL << cp.out_site_shift[Lv.site]) : 0;
+      Lv.out_stride = (Lv.site >= 0 && !cp.out_bit[Lv.site].empty()) ? (1LL << cp.out_bit[Lv.site][0]) : 0;
       mult *= Lv.nvar;
       int k = level_start[lv];
       const int kend = level_start[lv + 1];
@@ -903,9 +918,16 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         const bool final_step = (e == N);
         std::map<int, int> posC;
         if (final_step) {
-          // every remaining leg is an open Kraus-index leg: write at its output bit
-          for (int l : F) posC[l] = cp.out_site_shift[open_of[l].first] + open_of[l].second;
-          for (int l : NN) posC[l] = cp.out_site_shift[open_of.at(l).first] + open_of.at(l).second;
+          // every remaining leg is an open Kraus-index leg of an unsliced site: the output keeps
+          // the kept legs in their order (tile rows lowest) with the new legs above them, and the
+          // Kraus bit each position carries is recorded for reading the output back
+          for (int i = 0; i < (int)F.size(); ++i) posC[F[i]] = i;
+          for (int i = 0; i < st.kN; ++i) posC[NN[i]] = int(F.size()) + i;
+          for (auto& kv : posC) {
+            const auto& sb = open_of.at(kv.first);
+            if (cp.out_bit[sb.first][sb.second] != -1) throw std::logic_error("output bit placed twice");
+            cp.out_bit[sb.first][sb.second] = kv.second;
+          }
         } else if (st.kS == st.kN) {
           for (int l : F) posC[l] = posA[l];
           for (int i = 0; i < st.kN; ++i) posC[NN[i]] = posA[S[i]];
@@ -1004,6 +1026,9 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       cp.levels.push_back(Lv);
     }
     cp.leaves = mult;
+    for (int si : comp_sites)
+      for (int ob : cp.out_bit[si])
+        if (ob < 0 || ob >= cp.n_open_bits) throw std::logic_error("Kraus bit without an output position");
     cp.lds_resident = cp.levels.size() == 1 && cp.levels[0].nvar == 1;
     for (auto& st : cp.steps)
       if (st.rA > 11 || (!st.final_step && st.rC > 11)) cp.lds_resident = false;

@@ -81,6 +81,27 @@ def test_cap_forces_slicing_not_failure():
         assert np.max(np.abs(tight.emulate() - want)) < 1e-12
 
 
+@pytest.mark.parametrize("cut", [0, 2])
+def test_final_step_writes_in_its_own_layout(cut):
+    # The open Kraus bits of a component take the output positions its final step keeps (tile rows
+    # lowest), sliced sites the bits above: the per-tuple values still read back in tuple order.
+    inst = gen.random_circuit(4, 40, 6, 0.01, 0.3, 901)
+    c = jf.jf_load_circuit(inst)
+    free = jf.jf_plan_contraction(c, 1, "c128")
+    p = free if cut == 0 else jf.jf_plan_contraction(c, 1, "c128",
+                                                     max_log2=int(free.info()["max_log2_intermediate"]) - cut)
+    assert (p.stats()["n_sliced_sites"] > 0) == (cut > 0)
+    last = {}
+    for r in p.describe():
+        last[r["comp"]] = r
+    for r in last.values():
+        assert r["rowsC"] == list(range(r["L"]))
+        assert r["nC"] == list(range(r["rC"] - r["kN"], r["rC"]))
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    assert np.max(np.abs(p.emulate() - want)) < 1e-12
+
+
 def test_is_equivalent_is_strict():
     r = {"fj": 0.9, "one_minus_fj": 0.1, "imag_residual": 0.0, "kraus_terms": 1, "work_items": 1,
          "max_log2_intermediate": 0.0, "path_flops": 0.0, "path_bytes": 0.0, "seconds": 0.0}
