@@ -41,7 +41,8 @@ typedef enum {
   JF_E_NOT_UNITARY = -2,  /* a gate matrix violates ||G^dagger G - I||_max <= tol */
   JF_E_NOT_TP = -3,       /* a Kraus set violates ||sum K^dagger K - I||_max <= tol (Section II-B) */
   JF_E_QUBIT = -4,        /* qubit index out of range, or a two-qubit gate on one qubit */
-  JF_E_TOO_LARGE = -5,    /* no contraction order fits the intermediate-size cap */
+  JF_E_TOO_LARGE = -5,    /* no contraction order fits the intermediate-size cap, or Algorithm I's
+                             per-Kraus-tuple output of a component exceeds 2^34 values */
   JF_E_OOM = -6,          /* workspace smaller than required */
   JF_E_HIP = -7,          /* a HIP runtime call failed (message in jf_last_error) */
   JF_E_UNSUPPORTED = -8   /* valid request this build does not provide */
@@ -149,6 +150,9 @@ jf_status jf_load_circuit(int n_qubits, const jf_gate* ideal, int n_ideal,
  * steps into small-operator blocks and lower the order to a device step program.
  * alg = 0 plans both algorithms and keeps the one whose step program has the smaller estimated
  * device time (jf_plan_stats.alg tells which; call jf_fidelity_alg1 or _alg2 accordingly).
+ * Algorithm I holds one FP64 complex value per Kraus tuple of each connected component, sliced
+ * or not, so a component with more than 34 Kraus-index bits (256 GiB of values) is
+ * JF_E_TOO_LARGE for alg = 1 (alg = 0 then keeps Algorithm II).
  * Host only (no GPU needed).  Errors: JF_E_ARG, JF_E_TOO_LARGE, JF_E_UNSUPPORTED.
  */
 jf_status jf_plan_contraction(const jf_circuit* circuit, int alg, jf_dtype dtype,

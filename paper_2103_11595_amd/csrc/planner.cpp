@@ -27,6 +27,7 @@
 #include "jf_internal.h"
 
 namespace jf {
+static constexpr int kMaxOutLog2 = 34;
 
 namespace {
 
@@ -404,6 +405,13 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         nbits += int(net.site_var_legs[si].size());
         cp.out_bit[si].assign(net.site_var_legs[si].size(), -1);
         P.site_comp[si] = int(P.comps.size());
+      }
+      // Algorithm I keeps one FP64 complex value per Kraus tuple of the component, whole whatever
+      // the slicing: past 2^34 of them (256 GiB) no single device holds the output
+      if (nbits > kMaxOutLog2) {
+        set_error("Algorithm I output of 2^" + std::to_string(nbits) + " Kraus-tuple values exceeds 2^" +
+                  std::to_string(kMaxOutLog2) + " (Algorithm II does not grow with the tuples)");
+        throw jf_status(JF_E_TOO_LARGE);
       }
       cp.n_open_bits = nbits;
       cp.out_len = 1LL << nbits;

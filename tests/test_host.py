@@ -171,6 +171,16 @@ def test_plans_of_the_workloads_fit_one_gpu():
         assert info["workspace_bytes"] < 64 * 2**30
 
 
+def test_alg1_output_is_bounded_by_the_cap():
+    # 30 sites of 1.5 Kraus bits each: 2^45 per-tuple values cannot be held; Algorithm II can
+    inst = gen.config3()
+    c = jf.jf_load_circuit(inst)
+    st = _status(lambda: jf.jf_plan_contraction(c, 1, "c64"))
+    assert st == -5
+    assert "Kraus-tuple values" in jf.lib().jf_last_error().decode()
+    assert jf.jf_plan_contraction(c, 0, "c64").stats()["alg"] == 2
+
+
 def test_auto_algorithm_keeps_the_cheaper_plan():
     for seed, (n, g, m) in enumerate([(4, 40, 3), (5, 60, 2), (3, 30, 5)]):
         inst = gen.random_circuit(n, g, m, 1e-3, 0.1, 60 + seed)
