@@ -19,7 +19,10 @@
  *   - Device memory: the caller passes a device workspace of at least the size reported by
  *     jf_plan_info (jf_batch_workspace for a batch), 256-byte aligned, and a hipStream_t (as
  *     void*; NULL = the null stream).  Fidelity calls enqueue on that stream, synchronise it
- *     and write results to caller host memory.
+ *     and write results to caller host memory.  A workspace keeps the plan's device tables
+ *     between calls, and a later call with the same plan and address does not upload them again:
+ *     before memory that served as a workspace is freed or written for anything else, call
+ *     jf_workspace_release on it.
  *   - Qubit 0 is the most significant bit of a basis index; a two-qubit matrix acts on
  *     (q0, q1) with q0 the more significant; CX/CZ/CS have their control on q0.
  *   - Matrices are row-major with interleaved (re, im) doubles.
@@ -193,8 +196,8 @@ long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
  * Plans made with JF_FLAG_GRAPH capture the step program into a hipGraph on the first call for a
  * (workspace, stream, kernel choice) and replay it in later calls; with the NULL stream such a
  * plan uses a stream of its own, ordered after the work already on the NULL stream.  (On MI355X
- * replay measured no faster than eager launches for these programs, whose cost per step is on
- * the GPU side, and the NULL-stream hand-off adds ~40 us.)  The call synchronises before returning.
+ * replay gains a few percent on a non-default stream, since the cost per step is on the GPU side,
+ * and the NULL-stream hand-off adds ~40 us.)  The call synchronises before returning.
  * Errors: JF_E_ARG (not an Alg I plan), JF_E_OOM (workspace too small), JF_E_HIP.
  */
 jf_status jf_fidelity_alg1(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
@@ -333,6 +336,16 @@ typedef struct {
 } jf_decision;
 jf_status jf_decide_equivalence(jf_plan* plan, double eps, void* dev_ws, size_t ws_bytes, void* stream,
                                 jf_decision* out);
+
+/*
+ * jf_workspace_release -- the caller is done with [dev_ws, dev_ws + ws_bytes) as a workspace (it
+ * will free it or use it for something else).  The library forgets which plan tables it holds,
+ * so every plan uploads its tables again the next time it is given memory in that range.  Host
+ * only: touches no device memory, and needs no synchronisation beyond the caller's own (the
+ * fidelity calls have synchronised their streams when they return).  ws_bytes = 0 releases the
+ * one address.  Errors: JF_E_ARG (NULL dev_ws).
+ */
+jf_status jf_workspace_release(const void* dev_ws, size_t ws_bytes);
 
 void jf_free_circuit(jf_circuit* circuit);
 void jf_free_plan(jf_plan* plan);

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <cfloat>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -1046,6 +1047,24 @@ extern "C" jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* by
   }
   tot += align256(items * sizeof(LdsItem)) + align256(steps * sizeof(LdsStep));
   *bytes = tot;
+  return JF_OK;
+}
+
+extern "C" jf_status jf_workspace_release(const void* dev_ws, size_t ws_bytes) {
+  if (!dev_ws) {
+    set_error("jf_workspace_release: NULL workspace");
+    return JF_E_ARG;
+  }
+  // forget every upload that lies in [dev_ws, dev_ws + ws_bytes): the plans whose tables were
+  // there upload them again on their next call (batch members sit at offsets inside the range)
+  const auto lo = reinterpret_cast<uintptr_t>(dev_ws);
+  const auto hi = lo + (ws_bytes ? ws_bytes : 1);
+  std::lock_guard<std::mutex> g(g_upload_mu);
+  for (auto it = g_last_upload.begin(); it != g_last_upload.end();) {
+    const auto a = reinterpret_cast<uintptr_t>(it->first);
+    if (a >= lo && a < hi) it = g_last_upload.erase(it);
+    else ++it;
+  }
   return JF_OK;
 }
 

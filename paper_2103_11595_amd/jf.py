@@ -10,8 +10,10 @@ jf_fidelity_alg2, jf_fidelity_batch, jf_is_equivalent, plus Python conveniences
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjf.so")
@@ -108,7 +110,7 @@ EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_st
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
            "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant",
-           "jf_decide_equivalence"]
+           "jf_decide_equivalence", "jf_workspace_release"]
 
 _lib = None
 
@@ -149,6 +151,7 @@ def lib():
     L.jf_autotune.argtypes = [vp, vp, sz, vp, C.c_int]
     L.jf_set_kernel_variant.argtypes = [vp, C.c_int]
     L.jf_decide_equivalence.argtypes = [vp, C.c_double, vp, sz, vp, C.POINTER(jf_decision)]
+    L.jf_workspace_release.argtypes = [vp, sz]
     for name in EXPORTS:
         if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
@@ -307,10 +310,39 @@ def _torch_cuda():
     return torch
 
 
+def _release_range(ptr: int, nbytes: int) -> None:
+    if _lib is not None:
+        _lib.jf_workspace_release(C.c_void_p(ptr), nbytes)
+
+
 def workspace(nbytes: int, device=None):
-    """Device workspace as a torch uint8 tensor (the caching allocator aligns to >= 512 bytes)."""
+    """Device workspace as a torch uint8 tensor (the caching allocator aligns to >= 512 bytes).
+    When the tensor is collected, the library is told to forget the plan tables it held, so that
+    its memory can serve again as anything, including another workspace at the same address."""
     torch = _torch_cuda()
-    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    weakref.finalize(t, _release_range, t.data_ptr(), t.numel()).atexit = False
+    return t
+
+
+def jf_workspace_release(ws) -> None:
+    """Tell the library that a workspace tensor is about to be freed or reused for other data: the
+    plans whose device tables it held upload them again on their next call."""
+    _check(lib().jf_workspace_release(C.c_void_p(ws.data_ptr()), ws.numel()))
+
+
+@contextlib.contextmanager
+def _ws(ws, nbytes_fn):
+    """The caller's workspace, or a temporary one that is released to the library before torch's
+    caching allocator can hand its memory to anything else."""
+    if ws is not None:
+        yield ws
+        return
+    tmp = workspace(nbytes_fn())
+    try:
+        yield tmp
+    finally:
+        jf_workspace_release(tmp)
 
 
 def _stream_ptr(stream):
@@ -322,26 +354,24 @@ def _stream_ptr(stream):
 def jf_fidelity_alg1(plan: Plan, ws=None, stream=None, want_terms: bool = False) -> dict:
     import numpy as np
     info = plan.info()
-    if ws is None:
-        ws = workspace(info["workspace_bytes"])
-    r = jf_result()
-    terms = (C.c_double * (2 * info["kraus_terms"]))() if want_terms else None
-    _check(lib().jf_fidelity_alg1(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
-                                  C.byref(r), terms))
-    d = r.as_dict()
-    if want_terms:
-        a = np.frombuffer(terms, dtype=np.float64).copy()
-        d["terms"] = a[0::2] + 1j * a[1::2]
-    return d
+    with _ws(ws, lambda: info["workspace_bytes"]) as ws:
+        r = jf_result()
+        terms = (C.c_double * (2 * info["kraus_terms"]))() if want_terms else None
+        _check(lib().jf_fidelity_alg1(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                      C.byref(r), terms))
+        d = r.as_dict()
+        if want_terms:
+            a = np.frombuffer(terms, dtype=np.float64).copy()
+            d["terms"] = a[0::2] + 1j * a[1::2]
+        return d
 
 
 def jf_fidelity_alg2(plan: Plan, ws=None, stream=None) -> dict:
     info = plan.info()
-    if ws is None:
-        ws = workspace(info["workspace_bytes"])
-    r = jf_result()
-    _check(lib().jf_fidelity_alg2(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
-    return r.as_dict()
+    with _ws(ws, lambda: info["workspace_bytes"]) as ws:
+        r = jf_result()
+        _check(lib().jf_fidelity_alg2(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
+        return r.as_dict()
 
 
 def jf_batch_workspace(plans) -> int:
@@ -353,39 +383,35 @@ def jf_batch_workspace(plans) -> int:
 
 def jf_fidelity_batch(plans, ws=None, stream=None) -> list:
     arr = (C.c_void_p * len(plans))(*[p.ptr for p in plans])
-    if ws is None:
-        ws = workspace(jf_batch_workspace(plans))
-    res = (jf_result * len(plans))()
-    _check(lib().jf_fidelity_batch(arr, len(plans), C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), res))
-    return [r.as_dict() for r in res]
+    with _ws(ws, lambda: jf_batch_workspace(plans)) as ws:
+        res = (jf_result * len(plans))()
+        _check(lib().jf_fidelity_batch(arr, len(plans), C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), res))
+        return [r.as_dict() for r in res]
 
 
 def jf_profile_run(plan: Plan, ws=None, stream=None) -> dict:
-    if ws is None:
-        ws = workspace(plan.info()["workspace_bytes"])
-    r = jf_profile()
-    _check(lib().jf_profile_run(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
-    return r.as_dict()
+    with _ws(ws, lambda: plan.info()["workspace_bytes"]) as ws:
+        r = jf_profile()
+        _check(lib().jf_profile_run(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
+        return r.as_dict()
 
 
 def jf_profile_steps(plan: Plan, ws=None, stream=None) -> list:
     """Per-launch durations (ms) with flops, bytes, shape, arithmetic and kernel of each step."""
-    if ws is None:
-        ws = workspace(plan.info()["workspace_bytes"])
-    n = C.c_int(0)
-    _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), None, 0,
-                                  C.byref(n)))
-    buf = (jf_step_profile * max(1, n.value))()
-    _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), buf,
-                                  n.value, C.byref(n)))
-    return [buf[i].as_dict() for i in range(n.value)]
+    with _ws(ws, lambda: plan.info()["workspace_bytes"]) as ws:
+        n = C.c_int(0)
+        _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), None, 0,
+                                      C.byref(n)))
+        buf = (jf_step_profile * max(1, n.value))()
+        _check(lib().jf_profile_steps(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), buf,
+                                      n.value, C.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
 
 
 def jf_autotune(plan: Plan, ws=None, stream=None, reps: int = 3) -> None:
     """Time every kernel that can run each step and keep the fastest (the workspace is clobbered)."""
-    if ws is None:
-        ws = workspace(plan.info()["workspace_bytes"])
-    _check(lib().jf_autotune(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), int(reps)))
+    with _ws(ws, lambda: plan.info()["workspace_bytes"]) as ws:
+        _check(lib().jf_autotune(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), int(reps)))
 
 
 def jf_set_kernel_variant(plan: Plan, variant) -> None:
@@ -396,12 +422,11 @@ def jf_set_kernel_variant(plan: Plan, variant) -> None:
 
 def jf_decide_equivalence(plan: Plan, eps: float, ws=None, stream=None) -> dict:
     """Definition 1 with early stopping and a two-sided bound (decision 1 / 0 / -1)."""
-    if ws is None:
-        ws = workspace(plan.info()["workspace_bytes"])
-    r = jf_decision()
-    _check(lib().jf_decide_equivalence(plan.ptr, float(eps), C.c_void_p(ws.data_ptr()), ws.numel(),
-                                       _stream_ptr(stream), C.byref(r)))
-    return r.as_dict()
+    with _ws(ws, lambda: plan.info()["workspace_bytes"]) as ws:
+        r = jf_decision()
+        _check(lib().jf_decide_equivalence(plan.ptr, float(eps), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                           _stream_ptr(stream), C.byref(r)))
+        return r.as_dict()
 
 
 def jf_is_equivalent(result: dict, eps: float) -> bool:

@@ -217,6 +217,30 @@ def test_replays_are_bitwise_identical():
     assert len(set(vals)) == 1
 
 
+def test_released_workspace_is_uploaded_again():
+    # A workspace keeps the plan's device tables between calls; once its memory has held other
+    # data, jf_workspace_release makes the next call upload them again.  One component larger
+    # than the LDS kernel's limit, so every table the kernels read lives in the workspace.
+    import torch
+    inst = gen.random_circuit(10, 200, 3, 1e-3, 1e-2, 21)
+    p = jf.plan(inst, 1, "c64")
+    assert p.stats()["n_components"] == 1 and p.info()["max_log2_intermediate"] > 11
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    say("workspace release: n=10, 200 gates, 3 sites, c64")
+    want = jf.jf_fidelity_alg1(p, ws)["fj"]
+    ws.zero_()
+    torch.cuda.synchronize()
+    jf.jf_workspace_release(ws)
+    assert jf.jf_fidelity_alg1(p, ws)["fj"] == want
+    del ws
+    # the binding's temporary workspaces are released before torch hands their memory on
+    for _ in range(2):
+        assert jf.jf_fidelity_alg1(p)["fj"] == want
+        junk = torch.zeros(p.info()["workspace_bytes"], dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        del junk
+
+
 def test_batch_matches_individual_runs():
     insts = [gen.config1(s) for s in (1, 2, 3)] + [gen.random_circuit(9, 150, 2, 1e-3, 1e-2, 11)]
     plans = [jf.plan(i, 1, "c128") for i in insts] + [jf.plan(gen.config1(4), 2, "c128")]

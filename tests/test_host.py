@@ -102,6 +102,13 @@ def test_final_step_writes_in_its_own_layout(cut):
     assert np.max(np.abs(p.emulate() - want)) < 1e-12
 
 
+def test_workspace_release_is_host_only():
+    import ctypes as C
+    L = jf.lib()
+    assert L.jf_workspace_release(None, 0) == -1
+    assert L.jf_workspace_release(C.c_void_p(1 << 20), 4096) == 0   # never dereferenced
+
+
 def test_is_equivalent_is_strict():
     r = {"fj": 0.9, "one_minus_fj": 0.1, "imag_residual": 0.0, "kraus_terms": 1, "work_items": 1,
          "max_log2_intermediate": 0.0, "path_flops": 0.0, "path_bytes": 0.0, "seconds": 0.0}
