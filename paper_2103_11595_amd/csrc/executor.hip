@@ -50,7 +50,7 @@ struct DevState {
   hipGraphExec_t graph = nullptr;
   const void* graph_ws = nullptr;
   hipStream_t graph_stream = nullptr;
-  std::vector<const jf_plan*> graph_plans;  // the batch the cached graph was captured for
+  std::vector<unsigned long long> graph_plans;  // uids of the batch the cached graph was captured for
   std::vector<unsigned> graph_gens;         // and the kernel-choice generation of each plan
   unsigned variant_gen = 0;                 // bumped whenever a step's kernel choice changes
   // single-plan runs: the step program captured once per (workspace, stream, kernel choice)
@@ -1117,7 +1117,8 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   hipEvent_t e0 = ev.a, e1 = ev.b;
   DevState& S0 = state_of(plans[0]);
   const bool use_graph = n > 0 && stream != nullptr;
-  std::vector<const jf_plan*> key(plans, plans + n);
+  std::vector<unsigned long long> key(n);
+  for (int i = 0; i < n; ++i) key[i] = plans[i]->uid;
   std::vector<unsigned> gens(n);
   for (int i = 0; i < n; ++i) gens[i] = state_of(plans[i]).variant_gen;
   if (use_graph && (S0.graph == nullptr || S0.graph_ws != ws || S0.graph_stream != stream || S0.graph_plans != key ||

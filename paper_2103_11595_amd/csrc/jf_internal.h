@@ -6,6 +6,7 @@
 // and lowering to device "absorb" steps -> execution (GPU) or emulation (host, validation only).
 #pragma once
 
+#include <atomic>
 #include <complex>
 #include <cstdint>
 #include <memory>
@@ -227,4 +228,11 @@ struct jf_plan {
   jf::Program prog;
   // device state (lazily created by the executor)
   void* dev = nullptr;
+  // process-unique identity: a plan allocated where a freed one lived must not match caches
+  // keyed by the freed plan (the batch graph)
+  const unsigned long long uid = next_uid();
+  static unsigned long long next_uid() {
+    static std::atomic<unsigned long long> n{0};
+    return ++n;
+  }
 };

@@ -257,6 +257,26 @@ def test_batch_matches_individual_runs():
             assert a["fj"] == b["fj"], rep
 
 
+def test_batch_graph_follows_its_members():
+    # the cached batch graph is keyed by plan identity, not address: replacing a member with a new
+    # plan (which may be allocated where the freed one lived) captures a new graph
+    import gc
+    import torch
+    a = jf.plan(gen.config1(1), 1, "c128")
+    s = torch.cuda.Stream()
+    for seed in (2, 3, 4):
+        b = jf.plan(gen.random_circuit(6, 60 + 10 * seed, 2, 1e-3, 1e-2, seed), 1, "c128")
+        want = [jf.jf_fidelity_alg1(a)["fj"], jf.jf_fidelity_alg1(b)["fj"]]
+        ws = jf.workspace(jf.jf_batch_workspace([a, b]))
+        say("batch graph member", seed)
+        with torch.cuda.stream(s):
+            got = [r["fj"] for r in jf.jf_fidelity_batch([a, b], ws, s)]
+        torch.cuda.synchronize()
+        assert got == want
+        del b, ws
+        gc.collect()
+
+
 def test_workspace_too_small_is_reported():
     p = jf.plan(gen.config1(), 1)
     ws = jf.workspace(256)
