@@ -713,11 +713,14 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
       hipGraphExecDestroy(S.run_graph);
       S.run_graph = nullptr;
     }
-    hipGraph_t g;
+    hipGraph_t g = nullptr;
     JF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     st = enqueue_program(p, w, s);
     const hipError_t ce = hipStreamEndCapture(s, &g);
-    if (st != JF_OK) return st;
+    if (st != JF_OK) {
+      if (ce == hipSuccess && g) hipGraphDestroy(g);
+      return st;
+    }
     if (ce != hipSuccess) {
       set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
       return JF_E_HIP;
@@ -1127,7 +1130,7 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
       hipGraphExecDestroy(S0.graph);
       S0.graph = nullptr;
     }
-    hipGraph_t g;
+    hipGraph_t g = nullptr;
     JF_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     if (!items.empty() &&
         launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
@@ -1135,7 +1138,10 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
       st = JF_E_HIP;
     for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream, nullptr, true);
     hipError_t ce = hipStreamEndCapture(stream, &g);
-    if (st != JF_OK) return st;
+    if (st != JF_OK) {
+      if (ce == hipSuccess && g) hipGraphDestroy(g);
+      return st;
+    }
     if (ce != hipSuccess) {
       set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
       return JF_E_HIP;
