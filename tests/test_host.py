@@ -209,6 +209,15 @@ def test_plans_are_reproducible():
     assert {k: v for k, v in sa.items() if k != "planner_seconds"} == {k: v for k, v in sb.items() if k != "planner_seconds"}
 
 
+def test_step_tiles_cover_whole_cache_lines_on_the_n16_plan():
+    # bits 0-3 (16 complex64 = one 128-byte line) inside every tile: no line is fetched by two tiles
+    for d in jf.plan(gen.config2(), 1, "c64", flags=jf.JF_FLAG_GRAPH).describe():
+        if d["rA"] >= 4:
+            assert {0, 1, 2, 3} <= set(d["rowsA"] + d["sA"]), d["step"]
+        if d["rC"] >= 4:
+            assert {0, 1, 2, 3} <= set(d["rowsC"] + d["nC"]), d["step"]
+
+
 @pytest.mark.parametrize("effort", [1, 4, 9])
 def test_reduced_search_effort_still_exact(effort):
     inst = gen.random_circuit(5, 70, 3, 1e-3, 0.1, 40 + effort)
