@@ -64,6 +64,9 @@ struct DevState {
   std::vector<std::vector<char>> chain_off;
   bool validated = false;                   // the program passed validate_program (plans are immutable)
   hipEvent_t ev_order = nullptr, ev0 = nullptr, ev1 = nullptr;
+  // pinned host landing area of the component sums (4 doubles each): a pageable destination
+  // costs the runtime a staging copy on every call, which small programs feel
+  double* pinned_sums = nullptr;
 };
 
 std::atomic<unsigned> g_variant_gen{1};
@@ -660,9 +663,11 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
   const Program& P = p->prog;
   DevState& S = state_of(p);
   std::vector<double> sums(P.comps.size() * 4 + 1);
-  if (!P.comps.empty())
-    JF_HIP(hipMemcpyAsync(sums.data(), ws + S.lay.sums_off, P.comps.size() * 4 * sizeof(double), hipMemcpyDeviceToHost,
-                          stream));
+  const size_t sums_bytes = P.comps.size() * 4 * sizeof(double);
+  if (!P.comps.empty()) {
+    if (!S.pinned_sums) JF_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.pinned_sums), sums_bytes, hipHostMallocDefault));
+    JF_HIP(hipMemcpyAsync(S.pinned_sums, ws + S.lay.sums_off, sums_bytes, hipMemcpyDeviceToHost, stream));
+  }
   std::vector<std::vector<cd>> co;
   if (terms) {
     for (auto& cp : P.comps) {
@@ -673,6 +678,7 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
     }
   }
   JF_HIP(hipStreamSynchronize(stream));
+  if (!P.comps.empty()) std::memcpy(sums.data(), S.pinned_sums, sums_bytes);
   std::vector<CompSum> cs(P.comps.size());
   for (size_t c = 0; c < P.comps.size(); ++c) {
     cs[c].hi = sums[4 * c];
@@ -1188,6 +1194,7 @@ extern "C" void jf_free_plan(jf_plan* p) {
     }
     for (hipEvent_t e : {s->ev0, s->ev1, s->ev_order})
       if (e) hipEventDestroy(e);
+    if (s->pinned_sums) hipHostFree(s->pinned_sums);
     {
       std::lock_guard<std::mutex> g(g_upload_mu);
       for (auto it = g_last_upload.begin(); it != g_last_upload.end();)

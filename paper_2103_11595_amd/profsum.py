@@ -2,6 +2,7 @@
 files only, runs nothing on the GPU).
 
     python -m paper_2103_11595_amd.profsum trace  --dir D --log L --out profiles/X.md --command "..."
+    python -m paper_2103_11595_amd.profsum passes --dir D --log L --out profiles/W.md --command "..."
     python -m paper_2103_11595_amd.profsum traffic --fetch D1 --write D2 --log L --copy-mib M \
         --out profiles/Y.md --json profiles/Z.json --command "..."
 
@@ -9,6 +10,12 @@ files only, runs nothing on the GPU).
 the last clean program runs (the passes after the autotuner, identified from the end of the
 trace: every program run has the same number of step launches, taken from bench.py's JSON line),
 and their average duration next to the live HIP-event average bench.py printed.
+
+``passes`` reads a ``--kernel-trace`` run of any bench.py workload whose passes repeat one fixed
+launch sequence of the library's kernels (graph replays, eager runs of one plan): the period is
+found from the end of the trace (the shortest sequence of kernel names that the last three
+repetitions share), and the last ``--passes`` periods are summarised per kernel, with the device
+time and the span of a pass.
 
 ``traffic`` reads two ``--pmc`` runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of bench.py with
 ``--copy-calibration-mib M``: the copy of M MiB (one ``__amd_rocclr_copyBuffer`` dispatch that reads
@@ -95,6 +102,48 @@ def trace(args):
     print("\n".join(out))
 
 
+def period(names, max_p=5000):
+    for p in range(1, min(max_p, len(names) // 3) + 1):
+        if names[-p:] == names[-2 * p:-p] == names[-3 * p:-2 * p]:
+            return p
+    raise SystemExit("no repeating launch sequence at the end of the trace")
+
+
+def passes(args):
+    b = bench_line(args.log)
+    # the library's kernels only: the runtime's copy kernels (result read-back) come and go
+    rows = [r for r in csv.DictReader(open(os.path.join(args.dir, "bench_kernel_trace.csv")))
+            if "jf::" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    p = period([r["Kernel_Name"] for r in rows])
+    if len(rows) < p * args.passes:
+        raise SystemExit(f"trace holds {len(rows)} launches, fewer than {args.passes} x {p}")
+    sel = rows[-p * args.passes:]
+    by = {}
+    for r in sel:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        k = short(r["Kernel_Name"]).split("(")[0]
+        c, t = by.get(k, (0, 0.0))
+        by[k] = (c + 1, t + d)
+    total = sum(t for _, t in by.values())
+    spans = [(int(sel[(i + 1) * p - 1]["End_Timestamp"]) - int(sel[i * p]["Start_Timestamp"])) / 1e3
+             for i in range(args.passes)]
+    out = [f"# {args.title}", "", "Command (from the repository root, on one MI355X):", "", "    " + args.command, "",
+           f"kernels.hip sha256[:16] = {kernels_sha()}", "",
+           f"Last {args.passes} passes of the trace, {p} launches each (the period of the launch sequence at the "
+           "end of the trace; earlier launches belong to the autotuner and the first runs).", "",
+           "| kernel | launches | avg (us) | total (ms) | % |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k}` | {c} | {t / c:.1f} | {t / 1e3:.3f} | {100 * t / total:.2f} |")
+    out += ["", f"Per pass: {p} launches, {total / args.passes:.1f} us of kernel time, "
+            f"{sum(spans) / len(spans):.1f} us from the first launch's start to the last one's end "
+            f"(min {min(spans):.1f}, max {max(spans):.1f}).",
+            f"bench.py in the profiled run: value {b['value']:.1f} {b['unit']} ({b['ms_per_step']:.3f} ms per pass, "
+            "host synchronisation and the result copy included)."]
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def counters(path, name):
     rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
@@ -150,6 +199,13 @@ def main():
     t.add_argument("--command", required=True)
     t.add_argument("--live-log", default=None, help="log of a bench.py run without the profiler")
     t.add_argument("--live-command", default="python3 bench.py")
+    q = sub.add_parser("passes")
+    q.add_argument("--dir", required=True)
+    q.add_argument("--log", required=True)
+    q.add_argument("--passes", type=int, default=20)
+    q.add_argument("--out", required=True)
+    q.add_argument("--title", default="Kernels of one pass")
+    q.add_argument("--command", required=True)
     f = sub.add_parser("traffic")
     f.add_argument("--fetch", required=True)
     f.add_argument("--write", required=True)
@@ -160,7 +216,7 @@ def main():
     f.add_argument("--title", default="HBM traffic of the contraction-step kernels")
     f.add_argument("--command", required=True)
     a = ap.parse_args()
-    trace(a) if a.cmd == "trace" else traffic(a)
+    {"trace": trace, "passes": passes, "traffic": traffic}[a.cmd](a)
 
 
 if __name__ == "__main__":
