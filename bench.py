@@ -203,6 +203,53 @@ def run_crossover(args, torch, gen, jf, stream):
     print(json.dumps(out))
 
 
+# Table 1 of the paper: circuit, qubits, gates, noise sites, then its measured seconds for Qiskit's
+# process_fidelity, Algorithm II and Algorithm I (None: time-out or memory-out).  A laptop CPU (Intel
+# i7-1065G7, 8 GB) with the TDD contraction engine; the circuits themselves are not reproduced here.
+PAPER_TABLE1 = [
+    ("rb", 2, 7, 6, 0.03, 0.10, 24.34), ("qft2", 2, 7, 2, 0.05, 0.05, 0.14),
+    ("grover", 3, 96, 4, 0.15, 3.56, 23.58), ("qft3", 3, 18, 7, 0.16, 0.53, 230.82),
+    ("qv_n3d5", 3, 50, 2, 0.21, 0.91, 1.55), ("bv4", 4, 11, 7, 0.24, 0.17, 210.48),
+    ("7x1mod15", 5, 14, 3, 4.29, 0.18, 1.39), ("bv5", 5, 14, 6, 5.13, 0.26, 64.01),
+    ("qft5", 5, 55, 3, 31.90, 2.44, 4.07), ("qv_n5d5", 5, 100, 3, 20.12, 10.82, 33.82),
+    ("bv6", 6, 17, 14, 258.15, 0.48, None), ("qv_n6d5", 6, 150, 1, 1158.10, 18.54, 8.94),
+    ("qft7", 7, 112, 6, None, 33.72, 391.74), ("qv_n7d5", 7, 150, 2, None, 72.17, 151.04),
+    ("bv9", 9, 26, 6, None, 0.52, 117.18), ("qv_n9d5", 9, 200, 3, None, 82.98, 361.29),
+    ("qft9", 9, 189, 2, None, 131.41, 27.32), ("qft10", 10, 235, 2, None, 595.30, 194.08),
+    ("bv13", 13, 38, 4, None, 0.81, 11.48), ("bv14", 14, 41, 4, None, 0.86, 14.31),
+    ("bv16", 16, 47, 9, None, 1.61, None),
+]
+
+
+def run_paper_shapes(args, torch, gen, jf, stream):
+    """Context for the paper's Table 1: for each row, a seeded random circuit of the row's shape
+    (qubits, gates, depolarising sites with p = 1e-3; the gate mix of the workload generator, not
+    the row's circuit), planned with the automatic choice of algorithm in complex128 and timed per
+    synchronous call on the GPU (no autotuning), beside the host planner time and the paper's own
+    seconds on its hardware.  Different circuits and machines: context, not a comparison."""
+    rows = []
+    for i, (name, n, g, k, t_q, t_2, t_1) in enumerate(PAPER_TABLE1):
+        inst = gen.random_circuit(n, g, k, 1e-3, None, 900 + i)
+        t0 = time.perf_counter()
+        p = jf.plan(inst, 0, "c128")
+        plan_s = time.perf_counter() - t0
+        ws = jf.workspace(p.info()["workspace_bytes"])
+        run = (lambda: jf.jf_fidelity_alg1(p, ws, stream)) if p.alg == 1 else (lambda: jf.jf_fidelity_alg2(p, ws, stream))
+        r, sec = _timed(torch, run, 5)
+        row = {"shape_of": name, "n": n, "gates": g, "sites": k, "alg": p.alg, "fj": r["fj"],
+               "gpu_s": sec, "plan_s": plan_s, "paper_qiskit_s": t_q, "paper_alg2_s": t_2, "paper_alg1_s": t_1}
+        progress(f"paper shape {name}: {row}")
+        rows.append(row)
+        del ws
+    out = {"metric": "seconds per circuit on random circuits of the paper's Table 1 shapes (context)",
+           "value": sum(r["gpu_s"] for r in rows), "unit": "s (GPU, all rows)", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "c128", "data": "synthetic (seeded generator, no datasets)",
+           "config": {"workload": "one random circuit per Table 1 row shape (70% H/S/T/RZ, 30% CX; depolarising p=1e-3)",
+                      "paper_hardware": "Intel i7-1065G7 laptop CPU, 8 GB, TDD engine (the paper's own circuits)"},
+           "plan_s_total": sum(r["plan_s"] for r in rows), "rows": rows}
+    print(json.dumps(out))
+
+
 def run_batch(args, torch, gen, jf, stream):
     """The 512-circuit batch under the budget rule: plan every member (reduced search effort, size
     cap 2^32), spend more search on the costliest ones within --replan-s of host time (keeping the
@@ -341,9 +388,10 @@ def main():
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128", "bf16x3"], help="form reported as value")
     ap.add_argument("--only", action="store_true", help="run only the reported form (profiling runs)")
     ap.add_argument("--no-autotune", action="store_true", help="time the fixed kernel rule only")
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "crossover"],
+    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "crossover", "paper-shapes"],
                     help="workload: cfg2 (default) the n=16 Alg I workload; cfg1 n=5 Alg I; cfg3 n=25 chain Alg II; "
-                         "cfg4 the 512-circuit batch (budget rule); cfg5 n=36 chain Alg II")
+                         "cfg4 the 512-circuit batch (budget rule); cfg5 n=36 chain Alg II; crossover Alg I vs II "
+                         "over the noise count; paper-shapes random circuits of the paper's Table 1 shapes (context)")
     ap.add_argument("--budget-s", type=float, default=60.0, help="cfg4: GPU time budget for the cost-sorted work list")
     ap.add_argument("--batch-cap", type=int, default=32, help="cfg4: log2 size cap of the members' intermediates")
     ap.add_argument("--replan-s", type=float, default=60.0,
@@ -374,6 +422,8 @@ def main():
         return run_batch(args, torch, gen, jf, stream)
     if args.config == "crossover":
         return run_crossover(args, torch, gen, jf, stream)
+    if args.config == "paper-shapes":
+        return run_paper_shapes(args, torch, gen, jf, stream)
     if args.config != "cfg2":
         return run_single(args, torch, gen, jf, stream)
     inst = gen.config2()
