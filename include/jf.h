@@ -124,7 +124,8 @@ typedef struct jf_plan jf_plan;
                                   bit; chains are the default) */
 /* Search effort of the planner: JF_FLAG_EFFORT(e), e = 1..15, runs 2^(e+5) randomised greedy
  * restarts per component.  The default (e = 0 in the flags) sizes the search to the network:
- * min(2^17, max(2^12, 8e7 / tensors)) restarts, i.e. 2^17 up to ~600 tensors and 2^16 at ~1200.
+ * min(2^17, max(2^12, 8e7 / tensors)) restarts, i.e. 2^17 up to ~600 tensors and 2^16 at ~1200,
+ * and to the stakes: 512 when the first greedy paths already estimate under 200 us of device time.
  * More restarts find cheaper contraction orders; the plan is reproducible for a given effort. */
 #define JF_FLAG_EFFORT(e) (((unsigned)(e) & 15u) << 8)
 

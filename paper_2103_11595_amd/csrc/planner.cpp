@@ -647,13 +647,18 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       if (base_width(p) <= opt.cap_log2) p.est = fused_estimate(p);
       consider(p);
     }
+    // The default search is also sized to the stakes: when the deterministic starts already give a
+    // program estimated under 200 us of device time, seconds of host search could save only
+    // microseconds, so it takes 512 restarts (an explicit effort is kept as given).
+    const int tries_total = (opt.restarts <= 0 && N > 24 && have && best_base <= opt.cap_log2 && best.est < 2e-4)
+                                ? std::min(restarts_total, 512)
+                                : restarts_total;
     {
       // Randomised restarts on a thread pool.  Each worker draws its starts and Boltzmann noise
       // from its own seeded generator and keeps its best path; the winner is chosen by the same
       // rule in worker order, so the plan does not depend on timing (the time cap only guards
       // pathological inputs).
       const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
-      const int tries_total = restarts_total;
       std::vector<Path> wbest(workers);
       std::vector<int> whave(workers, 0);
       auto work = [&](int w) {
@@ -696,7 +701,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
     // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
     // Part of a thorough search only (>= 2^12 restarts): its sweeps cost O(tensors^2).
-    if (have && best_base <= opt.cap_log2 && (restarts_total >= 4096 || N <= 24)) {
+    if (have && best_base <= opt.cap_log2 && (tries_total >= 4096 || N <= 24)) {
       auto recompute = [&](Path& p) {
         std::vector<char> inT(L.nl, 0);
         int width = 0;
