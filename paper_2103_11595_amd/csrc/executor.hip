@@ -659,14 +659,26 @@ jf_status check_ws(jf_plan* p, void* ws, size_t ws_bytes) {
   return JF_OK;
 }
 
+// The plan's pinned landing area: 4 doubles per component (every read-back of sums fits in it).
+jf_status pinned_sums(jf_plan* p, double** out) {
+  DevState& S = state_of(p);
+  if (!S.pinned_sums)
+    JF_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.pinned_sums),
+                         std::max<size_t>(p->prog.comps.size(), 1) * 4 * sizeof(double), hipHostMallocDefault));
+  *out = S.pinned_sums;
+  return JF_OK;
+}
+
 jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_result* out, double* terms) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
   std::vector<double> sums(P.comps.size() * 4 + 1);
   const size_t sums_bytes = P.comps.size() * 4 * sizeof(double);
   if (!P.comps.empty()) {
-    if (!S.pinned_sums) JF_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.pinned_sums), sums_bytes, hipHostMallocDefault));
-    JF_HIP(hipMemcpyAsync(S.pinned_sums, ws + S.lay.sums_off, sums_bytes, hipMemcpyDeviceToHost, stream));
+    double* pin = nullptr;
+    const jf_status ps = pinned_sums(p, &pin);
+    if (ps != JF_OK) return ps;
+    JF_HIP(hipMemcpyAsync(pin, ws + S.lay.sums_off, sums_bytes, hipMemcpyDeviceToHost, stream));
   }
   std::vector<std::vector<cd>> co;
   if (terms) {
@@ -947,9 +959,13 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
                           reinterpret_cast<double*>(w + L.sums_off) + 4 * c,
                           reinterpret_cast<double*>(w + L.sumsq_off), stream));
     }
+    double* pin = nullptr;
+    st = pinned_sums(p, &pin);
+    if (st != JF_OK) return st;
     std::vector<double> sums(4 * P.comps.size());
-    JF_HIP(hipMemcpyAsync(sums.data(), w + L.sums_off, sums.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    JF_HIP(hipMemcpyAsync(pin, w + L.sums_off, sums.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     JF_HIP(hipStreamSynchronize(stream));
+    std::memcpy(sums.data(), pin, sums.size() * sizeof(double));
     const double sc = std::exp2(P.log2_scale);
     double prod_other = sc * sc * std::norm(P.scalar);
     for (size_t c = 0; c < P.comps.size(); ++c)
@@ -993,8 +1009,9 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
       }
       JF_HIP(launch_sumsq(out_last, cp.out_len, sums_last, reinterpret_cast<double*>(w + L.sumsq_off), stream));
       double part[2];
-      JF_HIP(hipMemcpyAsync(part, sums_last, sizeof(part), hipMemcpyDeviceToHost, stream));
+      JF_HIP(hipMemcpyAsync(pin, sums_last, sizeof(part), hipMemcpyDeviceToHost, stream));
       JF_HIP(hipStreamSynchronize(stream));
+      std::memcpy(part, pin, sizeof(part));
       double m = mass_unsliced;
       for (int lv = 0; lv < nl; ++lv)
         if (cp.levels[lv].site >= 0) {
