@@ -206,6 +206,24 @@ def test_stability_with_idle_qubits_on_gpu():
     assert abs(a["fj"] - b["fj"]) <= 1e-12
 
 
+# --- circuits of the shapes of the paper's Table 1 (qubits, gates, noise sites) -------------
+
+# (row index in Table 1, qubits, gates, sites) for the rows with at most 5 qubits; the circuits are
+# the generator's random ones of those shapes, seeded as bench.py --config paper-shapes seeds them
+TABLE1_SMALL_SHAPES = [(0, 2, 7, 6), (1, 2, 7, 2), (2, 3, 96, 4), (3, 3, 18, 7), (4, 3, 50, 2),
+                       (5, 4, 11, 7), (6, 5, 14, 3), (7, 5, 14, 6), (8, 5, 55, 3), (9, 5, 100, 3)]
+
+
+@pytest.mark.parametrize("row,n,g,k", TABLE1_SMALL_SHAPES)
+def test_table1_shapes_automatic_choice_against_oracle(row, n, g, k):
+    inst = gen.random_circuit(n, g, k, 1e-3, None, 900 + row)
+    want = dense.fidelity_alg2(inst)["fj"]
+    say("table-1 shape", row, "n", n, "gates", g, "sites", k)
+    for dtype in ("c128", "c64"):
+        got = jf.fidelity(inst, 0, dtype)["fj"]
+        assert abs(got - want) <= TOL[dtype], (dtype, got, want)
+
+
 # --- determinism, batching, errors ---------------------------------------------------------
 
 def test_replays_are_bitwise_identical():
