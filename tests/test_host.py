@@ -102,6 +102,15 @@ def test_final_step_writes_in_its_own_layout(cut):
     assert np.max(np.abs(p.emulate() - want)) < 1e-12
 
 
+def test_profile_summary_finds_the_pass_period():
+    from paper_2103_11595_amd import profsum
+    one_pass = ["k_zero", "k_absorb_a", "k_chain", "k_absorb_a", "k_sumsq_part", "k_sumsq_final"]
+    assert profsum.period(["k_tune"] * 7 + one_pass * 5) == len(one_pass)
+    assert profsum.period(["k_tune"] * 3 + ["k_persistent"] * 4) == 1
+    with pytest.raises(SystemExit):
+        profsum.period(["a", "b", "c", "d", "e", "f", "g"])
+
+
 def test_workspace_release_is_host_only():
     import ctypes as C
     L = jf.lib()
