@@ -48,7 +48,7 @@ typedef enum {
                              per-Kraus-tuple output of a component exceeds 2^34 values */
   JF_E_OOM = -6,          /* workspace smaller than required */
   JF_E_HIP = -7,          /* a HIP runtime call failed (message in jf_last_error) */
-  JF_E_UNSUPPORTED = -8   /* valid request this build does not provide */
+  JF_E_UNSUPPORTED = -8   /* valid request this library does not provide */
 } jf_status;
 
 typedef enum {
