@@ -393,6 +393,19 @@ def test_autotune_parity_and_bitwise_replay():
         assert c["fj"] == before["fj"] and np.array_equal(c["terms"], before["terms"])
 
 
+def test_many_open_kraus_bits_alg1_matches_alg2():
+    # 14 depolarising sites left open: Algorithm I holds 2^28 per-tuple values, written in the final
+    # step's own layout; the sum of their squares must agree with the doubled network
+    inst = gen.random_circuit(10, 200, 14, 1e-3, 1e-3, 714)
+    p1 = jf.plan(inst, 1, "c128", flags=jf.JF_FLAG_EFFORT(8))
+    assert p1.stats()["n_open_bits"] == 28
+    say("open bits 28: alg1 vs alg2, n=10, 200 gates, 14 sites, c128")
+    f1 = jf.jf_fidelity_alg1(p1)["fj"]
+    f2 = jf.fidelity(inst, 2, "c128", flags=jf.JF_FLAG_EFFORT(8))["fj"]
+    assert abs(f1 - f2) <= TOL["c128"]
+    assert (1 - 1e-3) ** 14 <= f1 <= 1.0
+
+
 def test_autotuned_full_size_workload():
     inst = gen.config2()
     p128 = jf.plan(inst, 1, "c128")
