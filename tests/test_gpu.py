@@ -393,6 +393,25 @@ def test_autotune_parity_and_bitwise_replay():
         assert c["fj"] == before["fj"] and np.array_equal(c["terms"], before["terms"])
 
 
+def test_padded_kraus_sets_sliced_and_open_against_oracle():
+    # three-operator Kraus sets (padded variant index) at every site; with the cap lowered some sites
+    # are sliced, and the padded entries of the output must stay zero
+    inst = gen.random_circuit(3, 40, 4, 0.05, 0.2, 19)
+    three = [k.tolist() for k in dense.kraus_set("bit_phase_flip", 0.3)] + [[[0, 0], [0, 0]]]
+    inst["noise"] = [dict(site, kraus=three) for site in inst["noise"]]
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    c = jf.jf_load_circuit(inst)
+    free = jf.jf_plan_contraction(c, 1, "c128")
+    for cut in (0, 2):
+        say("padded kraus sets, cap cut", cut)
+        p = free if cut == 0 else jf.jf_plan_contraction(c, 1, "c128",
+                                                         max_log2=int(free.info()["max_log2_intermediate"]) - cut)
+        got = jf.jf_fidelity_alg1(p, want_terms=True)
+        assert np.max(np.abs(got["terms"] - want)) < 1e-12
+        assert abs(got["fj"] - ref["fj"]) <= TOL["c128"]
+
+
 def test_many_open_kraus_bits_alg1_matches_alg2():
     # 14 depolarising sites left open: Algorithm I holds 2^28 per-tuple values, written in the final
     # step's own layout; the sum of their squares must agree with the doubled network

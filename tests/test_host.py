@@ -179,6 +179,25 @@ def test_emulated_mixed_channels_and_explicit_kraus():
     assert abs(jf.plan(inst, 2).emulate()[0].real - ref["fj"]) < 1e-12
 
 
+def test_padded_kraus_sets_with_slicing_read_back_in_tuple_order():
+    # three-operator sets (a padded variant index) at every site, some sites sliced and some open:
+    # the output bits of both kinds map back to the tuple order the oracle uses
+    inst = gen.random_circuit(3, 40, 4, 0.05, 0.2, 19)
+    three = [k.tolist() for k in dense.kraus_set("bit_phase_flip", 0.3)] + [[[0, 0], [0, 0]]]
+    inst["noise"] = [dict(site, kraus=three) for site in inst["noise"]]
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    c = jf.jf_load_circuit(inst)
+    free = jf.jf_plan_contraction(c, 1, "c128")
+    sliced = 0
+    for cut in (0, 1, 2):
+        p = free if cut == 0 else jf.jf_plan_contraction(c, 1, "c128",
+                                                         max_log2=int(free.info()["max_log2_intermediate"]) - cut)
+        sliced = max(sliced, p.stats()["n_sliced_sites"])
+        assert np.max(np.abs(p.emulate() - want)) < 1e-12, cut
+    assert sliced > 0
+
+
 def test_plans_of_the_workloads_fit_one_gpu():
     for inst, alg, cap in [(gen.config1(), 1, 28), (gen.config2(), 1, 28), (gen.config3(), 2, 28), (gen.config5(), 2, 28)]:
         p = jf.plan(inst, alg, "c64")
