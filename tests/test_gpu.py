@@ -226,6 +226,27 @@ def test_table1_shapes_automatic_choice_against_oracle(row, n, g, k):
 
 # --- determinism, batching, errors ---------------------------------------------------------
 
+DEGENERATE = [
+    {"n": 1, "gates": [], "noise": [{"after": -1, "qubit": 0, "channel": "depolarizing", "p": 0.1}]},
+    {"n": 1, "gates": [["h", [0], []]], "noise": []},
+    {"n": 2, "gates": [], "noise": []},
+    {"n": 2, "gates": [["h", [0], []]], "noise": [{"after": 0, "qubit": 1, "channel": "amplitude_damping", "p": 0.2}]},
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+def test_degenerate_circuits_on_gpu(case):
+    # no gates, no noise, noise on an idle wire, one qubit: networks that cancel to a scalar or to a
+    # single small component, through every algorithm choice
+    inst = DEGENERATE[case]
+    want = dense.fidelity_alg1(inst)["fj"]
+    say("degenerate case", case)
+    for alg in (0, 1, 2):
+        for dtype in ("c128", "c64"):
+            got = jf.fidelity(inst, alg, dtype)["fj"]
+            assert abs(got - want) <= TOL[dtype], (alg, dtype, got, want)
+
+
 def test_replays_are_bitwise_identical():
     inst = gen.config2()
     p = jf.plan(inst, 1, "c64")
