@@ -247,6 +247,20 @@ def test_degenerate_circuits_on_gpu(case):
             assert abs(got - want) <= TOL[dtype], (alg, dtype, got, want)
 
 
+def test_62_qubits_layer_of_depolarising_channels_closed_form():
+    # the largest qubit count the loader takes; a layer of depolarising channels on distinct qubits
+    # gives F_J = prod(1 - p_i) whatever the circuit around it
+    inst = gen.random_circuit(62, 200, 0, 0.0, None, 62)
+    ps = [1e-3, 4e-3, 2e-2]
+    inst["noise"] = [{"after": 99, "qubit": q, "channel": "depolarizing", "p": p} for q, p in zip((0, 30, 61), ps)]
+    want = float(np.prod([1 - p for p in ps]))
+    say("62 qubits, 200 gates, a layer of 3 depolarising channels")
+    for alg in (1, 2):
+        for dtype in ("c128", "c64"):
+            got = jf.fidelity(inst, alg, dtype)["fj"]
+            assert abs(got - want) <= TOL[dtype], (alg, dtype, got, want)
+
+
 def test_replays_are_bitwise_identical():
     inst = gen.config2()
     p = jf.plan(inst, 1, "c64")
