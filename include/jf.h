@@ -98,9 +98,15 @@ typedef struct {
 
 typedef struct {
   double fj;              /* F_J */
-  double one_minus_fj;    /* 1 - F_J, compensated (1 - sum of |t_k|^2 summed in one Kahan pass) */
+  double one_minus_fj;    /* 1 - F_J.  Alg I: sum_k |t_k|^2 of each component is a double-double
+                             (TwoSum, fixed reduction trees), the product over components a
+                             double-double, and 1 - F_J = (1 - hi) - lo, where 1 - hi is exact for
+                             hi in [0.5, 2] (Sterbenz).  Alg II: 1 - Re T/d^2, exact (Sterbenz) when
+                             Re T/d^2 lies in [0.5, 2]; Re T itself is an FP64 sum. */
   double imag_residual;   /* Alg II: |Im T| / d^2 (mathematically 0); Alg I: 0 */
-  long long kraus_terms;  /* prod_i n_i, the number of Kraus tuples the result covers */
+  long long kraus_terms;  /* prod_i n_i, the number of Kraus tuples the result covers, saturated at
+                             2^63 - 1 (an Algorithm II network with 40 depolarising sites covers
+                             4^40) */
   long long work_items;   /* slices (DFS leaves) executed */
   double max_log2_intermediate; /* largest intermediate of the executed program, log2 elements */
   double path_flops;      /* real flops of the executed contraction program (complex MAC = 8) */

@@ -72,7 +72,24 @@ struct DevState {
 std::atomic<unsigned> g_variant_gen{1};
 
 std::mutex g_upload_mu;
-std::map<const void*, const void*> g_last_upload;  // workspace -> plan that last uploaded into it
+// Plans whose tables a workspace holds: start address -> (plan, bytes of the plan's whole region:
+// tables, buffers, outputs and sums).  A run writes its whole region, so an upload forgets every
+// entry whose region overlaps the new one (a batch member inside a larger plan's buffers, or a
+// larger plan over the members of an earlier batch); live entries never overlap.
+struct Upload {
+  const void* plan;
+  size_t bytes;
+};
+std::map<const void*, Upload> g_last_upload;
+
+// Forget every upload whose region meets [lo, hi) (caller holds g_upload_mu).
+void forget_uploads(uintptr_t lo, uintptr_t hi) {
+  for (auto it = g_last_upload.begin(); it != g_last_upload.end();) {
+    const auto a = reinterpret_cast<uintptr_t>(it->first);
+    if (a < hi && lo < a + std::max<size_t>(it->second.bytes, 1)) it = g_last_upload.erase(it);
+    else ++it;
+  }
+}
 
 int mode_of(const Step& st) {
   if (st.compute == C_F64) return st.in_prec == P_C64 ? KM_F32_TO_F64 : KM_F64;
@@ -627,14 +644,19 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
 jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
   DevState& S = state_of(p);
   std::lock_guard<std::mutex> g(g_upload_mu);
-  if (S.uploaded_to == ws && g_last_upload[ws] == p) return JF_OK;
+  if (S.uploaded_to == ws) {
+    auto it = g_last_upload.find(ws);
+    if (it != g_last_upload.end() && it->second.plan == p) return JF_OK;
+  }
   fill_lds_tables(p->prog, S.lay, static_cast<unsigned char*>(ws),
                   reinterpret_cast<LdsItem*>(&S.host_image[S.lay.lds_items_off]),
                   reinterpret_cast<LdsStep*>(&S.host_image[S.lay.lds_steps_off]), 0);
   JF_HIP(hipMemcpyAsync(ws, S.host_image.data(), S.host_image.size(), hipMemcpyHostToDevice, stream));
   JF_HIP(hipStreamSynchronize(stream));
   S.uploaded_to = ws;
-  g_last_upload[ws] = p;
+  const auto a = reinterpret_cast<uintptr_t>(ws);
+  forget_uploads(a, a + S.lay.total);
+  g_last_upload[ws] = Upload{p, S.lay.total};
   return JF_OK;
 }
 
@@ -1081,16 +1103,12 @@ extern "C" jf_status jf_workspace_release(const void* dev_ws, size_t ws_bytes) {
     set_error("jf_workspace_release: NULL workspace");
     return JF_E_ARG;
   }
-  // forget every upload that lies in [dev_ws, dev_ws + ws_bytes): the plans whose tables were
-  // there upload them again on their next call (batch members sit at offsets inside the range)
+  // forget every upload whose region meets [dev_ws, dev_ws + ws_bytes): the plans whose tables
+  // were there upload them again on their next call (batch members sit at offsets inside the range)
   const auto lo = reinterpret_cast<uintptr_t>(dev_ws);
   const auto hi = lo + (ws_bytes ? ws_bytes : 1);
   std::lock_guard<std::mutex> g(g_upload_mu);
-  for (auto it = g_last_upload.begin(); it != g_last_upload.end();) {
-    const auto a = reinterpret_cast<uintptr_t>(it->first);
-    if (a >= lo && a < hi) it = g_last_upload.erase(it);
-    else ++it;
-  }
+  forget_uploads(lo, hi);
   return JF_OK;
 }
 
@@ -1215,7 +1233,7 @@ extern "C" void jf_free_plan(jf_plan* p) {
     {
       std::lock_guard<std::mutex> g(g_upload_mu);
       for (auto it = g_last_upload.begin(); it != g_last_upload.end();)
-        if (it->second == p) it = g_last_upload.erase(it);
+        if (it->second.plan == p) it = g_last_upload.erase(it);
         else ++it;
     }
     delete s;

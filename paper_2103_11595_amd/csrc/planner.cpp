@@ -16,6 +16,7 @@
 // of Section IV-C in the form of a prefix stack.
 #include <algorithm>
 #include <iterator>
+#include <limits>
 #include <stdexcept>
 #include <chrono>
 #include <cmath>
@@ -369,7 +370,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     }
     P.site_norm2.push_back(v);
   }
-  for (int nk : net.site_nk) P.kraus_terms *= nk;
+  // prod_i n_i saturates at the largest long long (Algorithm II networks cover 4^40 tuples and more)
+  for (int nk : net.site_nk)
+    if (__builtin_mul_overflow(P.kraus_terms, (long long)nk, &P.kraus_terms)) {
+      P.kraus_terms = std::numeric_limits<long long>::max();
+      break;
+    }
 
   const bool low = opt.dtype != JF_C128;
   const int elem_lo = low ? 8 : 16;

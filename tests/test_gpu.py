@@ -330,6 +330,29 @@ def test_batch_graph_follows_its_members():
         gc.collect()
 
 
+def test_batch_then_larger_plan_on_one_workspace():
+    # a batch member's tables sit at an offset inside the workspace; a larger plan run alone on the
+    # same workspace writes over them, so the batch after it must upload its members again
+    import torch
+    a = jf.plan(gen.random_circuit(10, 200, 3, 1e-3, 1e-2, 21), 1, "c64")
+    b = jf.plan(gen.random_circuit(11, 250, 3, 1e-3, 1e-2, 25), 1, "c64")
+    big = jf.plan(gen.random_circuit(14, 360, 4, 1e-3, 1e-2, 29), 1, "c64")
+    for p in (a, b, big):
+        assert p.info()["max_log2_intermediate"] > 11   # step programs, tables in the workspace
+    assert big.info()["workspace_bytes"] > a.info()["workspace_bytes"] + 2 * b.info()["workspace_bytes"]
+    want = [jf.jf_fidelity_alg1(p)["fj"] for p in (a, b, big)]
+    ws = jf.workspace(max(jf.jf_batch_workspace([a, b]), big.info()["workspace_bytes"]))
+    s = torch.cuda.Stream()
+    for rep in range(2):
+        say("batch [a, b] then a larger plan on the same workspace, round", rep)
+        with torch.cuda.stream(s):
+            got = [r["fj"] for r in jf.jf_fidelity_batch([a, b], ws, s)]
+        torch.cuda.synchronize()
+        assert got == want[:2], rep
+        assert jf.jf_fidelity_alg1(big, ws, s)["fj"] == want[2]
+        torch.cuda.synchronize()
+
+
 def test_workspace_too_small_is_reported():
     p = jf.plan(gen.config1(), 1)
     ws = jf.workspace(256)

@@ -206,6 +206,16 @@ def test_plans_of_the_workloads_fit_one_gpu():
         assert info["workspace_bytes"] < 64 * 2**30
 
 
+def test_kraus_term_count_saturates():
+    # the 36-qubit chain's doubled network covers 4^40 Kraus tuples: the count saturates at
+    # 2^63 - 1 instead of overflowing; a 31-site count is exact
+    big = jf.plan(gen.config5(), 2, "c64").info()
+    assert big["kraus_terms"] == 2**63 - 1
+    inst = gen.config5()
+    inst["noise"] = inst["noise"][:31]
+    assert jf.plan(inst, 2, "c64").info()["kraus_terms"] == 4**31
+
+
 def test_alg1_output_is_bounded_by_the_cap():
     # 30 sites of 1.5 Kraus bits each: 2^45 per-tuple values cannot be held; Algorithm II can
     inst = gen.config3()

@@ -258,6 +258,95 @@ def test_clifford_kernel_enumeration_matches_dp():
         assert abs(a - b) < 1e-13 and abs(c - b) < 1e-13
 
 
+def _random_clifford_gates(rng, n, count):
+    gates = []
+    for _ in range(count):
+        if rng.random() < 0.6:
+            gates.append([["h", "s", "sdg"][int(rng.integers(3))], [int(rng.integers(n))], []])
+        else:
+            c, t = (int(v) for v in rng.choice(n, size=2, replace=False))
+            gates.append([["cx", "cz"][int(rng.integers(2))], [c, t], []])
+    return gates
+
+
+def test_clifford_checker_beyond_32_sites_two_sites_per_qubit():
+    """More than 32 sites: the codewords have 2m = 80 bits, so the checker's enumeration runs
+    through its second 64-bit word.  36 qubits, every site in one layer between two random
+    Clifford halves: 32 qubits carry one depolarising site, four carry two (kernel dimension 8).
+    The layer's trace factorises over qubits (closed form (iii)); a qubit with one channel
+    contributes 1 - p, one with two consecutive depolarising channels (1 + 3 lambda) / 4,
+    lambda = prod (1 - 4p/3) (closed form (iv))."""
+    rng = np.random.default_rng(36)
+    n = 36
+    first, second = _random_clifford_gates(rng, n, 150), _random_clifford_gates(rng, n, 150)
+    # site index -> qubit; the pairs straddle index 32 so kernel vectors use both words
+    pairs = {0: (1, 33), 1: (5, 36), 2: (30, 39), 3: (34, 37)}
+    qubit_of = {}
+    for q, (i, j) in pairs.items():
+        qubit_of[i] = qubit_of[j] = q
+    rest = iter(range(4, n))
+    for i in range(40):
+        if i not in qubit_of:
+            qubit_of[i] = next(rest)
+    ps = rng.uniform(1e-4, 1e-2, size=40)
+    noise = [{"after": len(first) - 1, "qubit": qubit_of[i], "channel": "depolarizing", "p": float(ps[i])}
+             for i in range(40)]
+    inst = {"n": n, "gates": first + second, "noise": noise}
+    want = 1.0
+    for i in range(40):
+        if qubit_of[i] >= 4:
+            want *= 1.0 - ps[i]
+    for q, (i, j) in pairs.items():
+        lam = (1 - 4 * ps[i] / 3) * (1 - 4 * ps[j] / 3)
+        want *= (1 + 3 * lam) / 4
+    got = clifford.fidelity(inst)
+    assert got["kernel_dim"] == 8
+    assert abs(got["fj"] - want) < 1e-13
+    # the same with the chunking moved (every codeword of the kernel in its own chunk)
+    assert abs(clifford.fidelity(inst, chunk_bits=1)["fj"] - want) < 1e-13
+
+
+def test_clifford_checker_beyond_32_sites_one_per_qubit():
+    """40 Pauli channels of the four kinds on 40 distinct qubits in one layer: F_J = prod (1 - p_i)
+    (closed forms (ii) and (iii)); kernel dimension 0, codewords of 80 bits."""
+    rng = np.random.default_rng(40)
+    n = 40
+    first, second = _random_clifford_gates(rng, n, 120), _random_clifford_gates(rng, n, 120)
+    chans = ["depolarizing", "bit_flip", "phase_flip", "bit_phase_flip"]
+    ps = rng.uniform(1e-4, 1e-2, size=n)
+    order = rng.permutation(n)
+    noise = [{"after": len(first) - 1, "qubit": int(order[i]), "channel": chans[i % 4], "p": float(ps[i])}
+             for i in range(n)]
+    got = clifford.fidelity({"n": n, "gates": first + second, "noise": noise})
+    assert got["kernel_dim"] == 0
+    assert abs(got["fj"] - float(np.prod(1.0 - ps))) < 1e-13
+
+
+def test_clifford_checker_beyond_32_sites_catches_a_dropped_high_word():
+    """The high-word path matters: with the second codeword word ignored (a plausible slip), the
+    two-sites-per-qubit case above no longer gives its closed form."""
+    import oracle.clifford as cl
+    rng = np.random.default_rng(36)
+    n = 36
+    first, second = _random_clifford_gates(rng, n, 150), _random_clifford_gates(rng, n, 150)
+    noise = [{"after": len(first) - 1, "qubit": i % n, "channel": "depolarizing", "p": 0.01} for i in range(40)]
+    inst = {"n": n, "gates": first + second, "noise": noise}
+    good = cl.fidelity(inst)["fj"]
+    want = (0.99 ** 32) * ((1 + 3 * (1 - 0.04 / 3) ** 2) / 4) ** 4
+    assert abs(good - want) < 1e-13
+    orig = cl._enumerate_kernel
+
+    def low_word_only(basis, sites, chunk_bits=20):
+        return orig([b & ((1 << 64) - 1) for b in basis], sites, chunk_bits)
+
+    cl._enumerate_kernel = low_word_only
+    try:
+        bad = cl.fidelity(inst)["fj"]
+    finally:
+        cl._enumerate_kernel = orig
+    assert abs(bad - want) > 1e-6
+
+
 # --- gate definitions (Section II-A and Example 1) ----------------------------------------
 
 def test_gate_definitions():
