@@ -227,6 +227,26 @@ jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* dev_ws, size_t w
                             void* stream, jf_result* out);
 
 /*
+ * jf_fidelity_noalloc -- for callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Runs an Algorithm I or II plan as
+ * jf_fidelity_alg1 / jf_fidelity_alg2 do (the same kernels, launched eagerly: no hipGraph, also
+ * for JF_FLAG_GRAPH plans) with the library's own static device scratch as the workspace:
+ * JF_NOALLOC_BYTES per GPU, a file-scope device array that each GPU the library runs on holds
+ * until the process ends.  The call makes no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating call; results are copied straight into the caller's host memory.
+ *   stream       hipStream_t as void* (NULL = the null stream); the call synchronises it
+ *   out          as jf_fidelity_alg1 / alg2, except out->seconds: host wall time of the call
+ *   term_traces  optional, Algorithm I plans only, as in jf_fidelity_alg1
+ * All calls on one GPU share its scratch and leave their contents in it (a plan's tables are
+ * copied in again whenever another plan used the scratch last; the call clears its own outputs),
+ * so calls that overlap in time on one GPU -- from several threads or streams -- race: the caller
+ * serialises them.  Errors: JF_E_ARG, JF_E_OOM (the plan's workspace, jf_plan_info, exceeds
+ * JF_NOALLOC_BYTES: run it through jf_fidelity_alg1 / alg2 with a caller workspace), JF_E_HIP.
+ */
+#define JF_NOALLOC_BYTES (128u << 20)
+jf_status jf_fidelity_noalloc(jf_plan* plan, void* stream, jf_result* out, double* term_traces);
+
+/*
  * jf_profile_run -- measurement aid: runs the plan's program once like jf_fidelity_alg1/alg2,
  * with a pair of HIP events attached to the dispatch of every contraction-step kernel
  * (hipExtLaunchKernelGGL: the events time the kernel itself, not the queue gaps around it), and

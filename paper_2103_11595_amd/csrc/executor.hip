@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
@@ -691,15 +692,21 @@ jf_status pinned_sums(jf_plan* p, double** out) {
   return JF_OK;
 }
 
-jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_result* out, double* terms) {
+// Copy the component sums (and, with terms, the per-tuple outputs) back and assemble F_J.  The sums
+// land in the plan's pinned area unless pinned is false (then straight into pageable host memory:
+// no host allocation by the library, as the no-allocation entry point needs).
+jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_result* out, double* terms,
+                       bool pinned = true) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
   std::vector<double> sums(P.comps.size() * 4 + 1);
   const size_t sums_bytes = P.comps.size() * 4 * sizeof(double);
   if (!P.comps.empty()) {
-    double* pin = nullptr;
-    const jf_status ps = pinned_sums(p, &pin);
-    if (ps != JF_OK) return ps;
+    double* pin = sums.data();
+    if (pinned) {
+      const jf_status ps = pinned_sums(p, &pin);
+      if (ps != JF_OK) return ps;
+    }
     JF_HIP(hipMemcpyAsync(pin, ws + S.lay.sums_off, sums_bytes, hipMemcpyDeviceToHost, stream));
   }
   std::vector<std::vector<cd>> co;
@@ -712,7 +719,7 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
     }
   }
   JF_HIP(hipStreamSynchronize(stream));
-  if (!P.comps.empty()) std::memcpy(sums.data(), S.pinned_sums, sums_bytes);
+  if (!P.comps.empty() && pinned) std::memcpy(sums.data(), S.pinned_sums, sums_bytes);
   std::vector<CompSum> cs(P.comps.size());
   for (size_t c = 0; c < P.comps.size(); ++c) {
     cs[c].hi = sums[4 * c];
@@ -809,6 +816,75 @@ extern "C" jf_status jf_fidelity_alg1(jf_plan* p, void* ws, size_t ws_bytes, voi
     return JF_E_ARG;
   }
   return run_one(p, ws, ws_bytes, static_cast<hipStream_t>(stream), out, terms);
+}
+
+// ------------------------------------------------------------- no-allocation entry point ---
+// Device scratch of jf_fidelity_noalloc: one copy per GPU, held until the process ends.  In host
+// code the name `scratch` is a host-side stand-in, never a device address: the device address
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[JF_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on its first use on that device).
+jf_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  JF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("jf_fidelity_noalloc: device index " + std::to_string(dev) + " beyond the supported " +
+              std::to_string(kMaxDevices));
+    return JF_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    JF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      set_error("jf_fidelity_noalloc: hipGetSymbolAddress returned no address for the scratch");
+      return JF_E_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return JF_OK;
+}
+}  // namespace
+
+extern "C" jf_status jf_fidelity_noalloc(jf_plan* p, void* stream_v, jf_result* out, double* terms) {
+  if (!p || !out || (p->prog.opt.alg != 1 && p->prog.opt.alg != 2)) {
+    set_error("jf_fidelity_noalloc: NULL argument or no algorithm in the plan");
+    return JF_E_ARG;
+  }
+  if (terms && p->prog.opt.alg != 1) {
+    set_error("jf_fidelity_noalloc: per-term traces exist for Algorithm I plans only");
+    return JF_E_ARG;
+  }
+  const size_t need = state_of(p).lay.total;
+  if (need > JF_NOALLOC_BYTES) {
+    set_error("jf_fidelity_noalloc: the plan needs a workspace of " + std::to_string(need) +
+              " bytes; the no-allocation scratch holds " + std::to_string((size_t)JF_NOALLOC_BYTES));
+    return JF_E_OOM;
+  }
+  void* ws = nullptr;
+  jf_status st = scratch_of_current_device(&ws);
+  if (st != JF_OK) return st;
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  st = check_ws(p, ws, JF_NOALLOC_BYTES);
+  if (st != JF_OK) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  st = upload(p, ws, stream);  // a copy of the plan's tables (every plan shares the scratch)
+  if (st != JF_OK) return st;
+  st = enqueue_program(p, static_cast<unsigned char*>(ws), stream);  // eager: no graph, no events
+  if (st != JF_OK) return st;
+  jf_result r;
+  st = read_results(p, static_cast<unsigned char*>(ws), stream, &r, terms, false);
+  if (st != JF_OK) return st;
+  r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = r;
+  return JF_OK;
 }
 
 extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void* stream_v, jf_profile* out) {

@@ -110,7 +110,7 @@ EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_st
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
            "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant",
-           "jf_decide_equivalence", "jf_workspace_release"]
+           "jf_decide_equivalence", "jf_workspace_release", "jf_fidelity_noalloc"]
 
 _lib = None
 
@@ -152,6 +152,7 @@ def lib():
     L.jf_set_kernel_variant.argtypes = [vp, C.c_int]
     L.jf_decide_equivalence.argtypes = [vp, C.c_double, vp, sz, vp, C.POINTER(jf_decision)]
     L.jf_workspace_release.argtypes = [vp, sz]
+    L.jf_fidelity_noalloc.argtypes = [vp, vp, C.POINTER(jf_result), C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
@@ -372,6 +373,23 @@ def jf_fidelity_alg2(plan: Plan, ws=None, stream=None) -> dict:
         r = jf_result()
         _check(lib().jf_fidelity_alg2(plan.ptr, C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), C.byref(r)))
         return r.as_dict()
+
+
+JF_NOALLOC_BYTES = 128 << 20  # the library's static per-GPU scratch (include/jf.h)
+
+
+def jf_fidelity_noalloc(plan: Plan, stream=None, want_terms: bool = False) -> dict:
+    """The no-allocation entry point: the plan runs on the library's static device scratch (no
+    workspace argument; plans whose workspace exceeds JF_NOALLOC_BYTES are rejected)."""
+    import numpy as np
+    r = jf_result()
+    terms = (C.c_double * (2 * plan.info()["kraus_terms"]))() if want_terms else None
+    _check(lib().jf_fidelity_noalloc(plan.ptr, _stream_ptr(stream), C.byref(r), terms))
+    d = r.as_dict()
+    if want_terms:
+        a = np.frombuffer(terms, dtype=np.float64).copy()
+        d["terms"] = a[0::2] + 1j * a[1::2]
+    return d
 
 
 def jf_batch_workspace(plans) -> int:
