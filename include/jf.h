@@ -54,7 +54,12 @@ typedef enum {
 typedef enum {
   JF_C128 = 0,       /* complex128 storage, FP64 arithmetic */
   JF_C64 = 1,        /* complex64 storage, FP32 MFMA with FP32 accumulation */
-  JF_C64_BF16X3 = 2  /* complex64 storage, each product as 3 BF16 MFMA products (hi*hi + hi*lo + lo*hi) */
+  JF_C64_BF16X6 = 2  /* complex64 storage, split precision: every FP32 operand of a contraction step
+                        is split exactly into three BF16 numbers (x = x0 + x1 + x2, "3 x BF16") and
+                        each real product is formed from the six piece products x0 y0, x0 y1,
+                        x1 y0, x0 y2, x1 y1, x2 y0 on the BF16 matrix cores with FP32 accumulation
+                        (the three dropped ones are below 2^-24 of the product); noise-carrying
+                        operators keep a fourth piece, the BF16 residual of the FP64 operator */
 } jf_dtype;
 /* In every dtype the closing (small) contractions, the traces t_k, sum_k |t_k|^2 (Kahan-
  * compensated) and 1 - F_J are evaluated in FP64 on the GPU. */
@@ -189,7 +194,7 @@ jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
  * "comp step level kS kN L rA rC tiles in_prec out_prec compute nvar flops bytes rowsA rowsC sA nC
  *  chain", rowsA .. nC being comma-separated bit positions (A for tile rows and summed legs, C for
  * tile rows and new legs; "-" when empty).  compute is f64, f32, f32x2 (FP32 with the operator kept
- * as an FP32 pair) or bf16x3.  chain is the index (within the component) of the chain the step
+ * as an FP32 pair), split or split4 (the split form; split4 with the fourth operator piece).  chain is the index (within the component) of the chain the step
  * belongs to, -1 if it runs as its own launch (see JF_FLAG_NO_CHAIN).
  * Writes at most len bytes (NUL-terminated) and returns the full length needed. Host only. */
 long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
@@ -266,7 +271,8 @@ jf_status jf_profile_run(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* str
 /*
  * jf_profile_steps -- the same run, reported per launch: out[i] for the i-th contraction-step
  * launch in program order (i < cap), *n_launches = number of launches.  mode is the step's
- * arithmetic (0 FP64, 1 FP32, 2 FP32 in / FP64 out, 3 3xBF16, 4 FP32 with a two-term operator);
+ * arithmetic (0 FP64, 1 FP32, 2 FP32 in / FP64 out, 3 split form, 4 FP32 with a two-term operator,
+ * 5 split form with a fourth operator piece);
  * variant the kernel that ran it (jf_kernel_variant, never AUTO); steps the number of program
  * steps the launch ran (1, or the length of a chain: variant JF_KV_CHAIN, kS = kN the largest
  * summed extent of its steps, L the log2 of its LDS tile, flops the chain's, bytes one read and
@@ -348,7 +354,7 @@ int jf_is_equivalent(const jf_result* result, double eps);
  * where the mass of a Kraus tuple is prod_i ||K_{k_i}||^2 (operator norms; w_k for Pauli
  * channels), an upper bound on its term.  It stops as soon as fj_lower - margin > 1 - eps
  * (decision 1: equivalent) or fj_upper + margin <= 1 - eps (decision 0: not equivalent), where
- * margin is the parity bar of the plan's form (1e-12 complex128, 1e-6 complex64, 3e-5 3xBF16).
+ * margin is the parity bar of the plan's form (1e-12 complex128, 1e-6 complex64 and split form).
  * Plans with one leaf (and Algorithm II plans) run once and decide from F_J; decision -1 means
  * F_J lies within the margin of 1 - eps.  Leaves run in depth-first order (Kraus operator 0 of
  * each sliced site first: the no-error operator for the built-in channels).  Synchronises the

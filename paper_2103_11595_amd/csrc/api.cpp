@@ -35,7 +35,7 @@ extern "C" jf_status jf_plan_contraction(const jf_circuit* c, int alg, jf_dtype 
     jf_free_plan(take1 ? p2 : p1);
     return JF_OK;
   }
-  if (!c || !out || (alg != 1 && alg != 2) || dtype < JF_C128 || dtype > JF_C64_BF16X3) {
+  if (!c || !out || (alg != 1 && alg != 2) || dtype < JF_C128 || dtype > JF_C64_BF16X6) {
     set_error("jf_plan_contraction: bad argument");
     return JF_E_ARG;
   }
@@ -143,7 +143,7 @@ extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len
   if (!p) return -1;
   std::string out;
   const char* pn[] = {"c128", "c64"};
-  const char* cn[] = {"f64", "f32", "bf16x3"};
+  const char* cn[] = {"f64", "f32", "split"};
   for (size_t c = 0; c < p->prog.comps.size(); ++c) {
     const ComponentProgram& cp = p->prog.comps[c];
     for (size_t lv = 0; lv < cp.levels.size(); ++lv)
@@ -152,7 +152,9 @@ extern "C" long long jf_plan_describe(const jf_plan* p, char* buf, long long len
         char line[256];
         snprintf(line, sizeof(line), "%zu %d %zu %d %d %d %d %d %lld %s %s %s %d %.6g %.6g", c, s, lv, st.kS, st.kN, st.L,
                  st.rA, st.rC, st.nTiles, pn[st.in_prec], pn[st.out_prec],
-                 (st.compute == C_F32 && st.two_term) ? "f32x2" : cn[st.compute], st.nvar, st.flops, st.bytes);
+                 (st.compute == C_F32 && st.two_term) ? "f32x2" : (st.compute == C_SPLIT && st.two_term) ? "split4"
+                                                                                            : cn[st.compute],
+                 st.nvar, st.flops, st.bytes);
         out += line;
         // bit positions (in A, resp. C) of the tile rows, the summed legs and the new legs
         auto bits = [](const std::vector<long long>& off, int n) {

@@ -64,14 +64,16 @@ bool validate_program(const Program& P, std::string& why) {
         const Step& st = cp.steps[s];
         ok = chainable(st) && st.chain == int(q) && st.rA == rA && ch.T - st.kS >= 4;
         for (int b : step_s_positions(st)) ok = ok && std::count(ch.P.begin(), ch.P.end(), b) == 1;
-        ops += 1 << (2 * st.kS);
+        ops += chain_step_ops(st.kS, st.compute == C_SPLIT);
         for (size_t l = 0; l < cp.levels.size(); ++l)
           if (s >= cp.levels[l].first && s < cp.levels[l].last) {
             if (lvl < 0) lvl = int(l);
             ok = ok && lvl == int(l);
           }
       }
-      if (!ok || ops > CHAIN_MAX_OPS) {
+      const bool split = ch.first < (int)cp.steps.size() && cp.steps[ch.first].compute == C_SPLIT;
+      for (int s = ch.first; ok && s < ch.last; ++s) ok = (cp.steps[s].compute == C_SPLIT) == split;
+      if (!ok || ops > (split ? CHAIN_MAX_OPS_SPLIT : CHAIN_MAX_OPS)) {
         why = "chain " + std::to_string(q) + " of component " + std::to_string(c) + " is malformed";
         return false;
       }

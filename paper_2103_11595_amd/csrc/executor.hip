@@ -95,7 +95,109 @@ void forget_uploads(uintptr_t lo, uintptr_t hi) {
 int mode_of(const Step& st) {
   if (st.compute == C_F64) return st.in_prec == P_C64 ? KM_F32_TO_F64 : KM_F64;
   if (st.compute == C_F32) return st.two_term ? KM_F32X2 : KM_F32;
-  return KM_BF16X3;
+  return st.two_term ? KM_SPLIT4 : KM_SPLIT;
+}
+
+// Nearest BF16 number (ties to even) of an FP32 value, as an FP32 value.
+float bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+// Exact three-way split of an FP32 value into BF16 numbers: x = p[0] + p[1] + p[2] (each remainder
+// is exact in FP32, and the last has at most 8 significant bits left).
+void split3(float x, float p[3]) {
+  p[0] = bf16_rne(x);
+  const float r1 = x - p[0];
+  p[1] = bf16_rne(r1);
+  p[2] = bf16_rne(r1 - p[1]);
+}
+
+void balanced_round(const std::vector<cd>& M, std::vector<float>& out);
+
+// Split-form operator block (kernels.h): P pieces of float4 entries, then the BF16 fragments of the
+// Gauss form (single-term blocks) and of the real embedding.  Offsets in 16-byte units.
+struct SplitLayout {
+  int P = 3;
+  long long gauss = -1, embed = -1, total = 0;
+};
+SplitLayout split_layout(const Step& st) {
+  SplitLayout l;
+  l.P = st.two_term ? 4 : 3;
+  const long long pieces = (long long)l.P << (st.kS + st.kN);
+  long long off = pieces;
+  if (!st.two_term) {
+    l.gauss = off;
+    off += 576LL * split_gauss_mb(st.kN) * split_gauss_kc(st.kS);
+  }
+  l.embed = off;
+  off += 64LL * l.P * split_embed_mb(st.kN) * split_embed_kc(st.kS);
+  l.total = off;
+  return l;
+}
+uint32_t bf16_bits(float x) {  // x is a BF16 number
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  return u >> 16;
+}
+uint32_t bf16_pair(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+
+// Fill one split-form block at dst from the FP64 block M (K x Nn, row-major [s][n]).
+void fill_split_block(const Step& st, const std::vector<cd>& M, unsigned char* dst) {
+  const SplitLayout l = split_layout(st);
+  const int K = 1 << st.kS, Nn = 1 << st.kN;
+  const size_t nb = M.size();
+  // pieces of the FP32 block (balanced rounding for single-term blocks, as the FP32 steps round),
+  // and for two-term blocks a fourth piece: the BF16 residual of the FP64 block
+  std::vector<float> bal;
+  if (!st.two_term) balanced_round(M, bal);
+  std::vector<float> pc(size_t(l.P) * nb * 4, 0.f);  // [q][i][Re, Im, Re + Im, 0]
+  for (size_t i = 0; i < nb; ++i) {
+    const double re64 = M[i].real(), im64 = M[i].imag();
+    const float re = st.two_term ? float(re64) : bal[2 * i], im = st.two_term ? float(im64) : bal[2 * i + 1];
+    float pr[3], pi[3], ps[3];
+    split3(re, pr);
+    split3(im, pi);
+    split3(re + im, ps);
+    for (int q = 0; q < 3; ++q) {
+      pc[(q * nb + i) * 4 + 0] = pr[q];
+      pc[(q * nb + i) * 4 + 1] = pi[q];
+      pc[(q * nb + i) * 4 + 2] = ps[q];
+    }
+    if (l.P == 4) {
+      pc[(3 * nb + i) * 4 + 0] = bf16_rne(float(re64 - double(re)));
+      pc[(3 * nb + i) * 4 + 1] = bf16_rne(float(im64 - double(im)));
+    }
+  }
+  std::memcpy(dst, pc.data(), pc.size() * 4);
+  auto piece = [&](int q, int s, int n, int x) {
+    return (s < K && n < Nn) ? pc[((size_t(q) * nb) + size_t(s) * Nn + n) * 4 + x] : 0.f;
+  };
+  uint32_t* w = reinterpret_cast<uint32_t*>(dst);
+  if (l.gauss >= 0) {
+    const int MB = split_gauss_mb(st.kN), KC = split_gauss_kc(st.kS);
+    for (int e = 0; e < 3 * MB * KC * 64 * 3; ++e) {
+      const int q = e % 3, rest = e / 3, lane = rest & 63, r2 = rest >> 6;
+      const int kc = r2 % KC, r3 = r2 / KC, mb = r3 % MB, x = r3 / MB;
+      const int n = 16 * mb + (lane & 15), s0 = 32 * kc + 8 * (lane >> 4);
+      for (int dd = 0; dd < 4; ++dd)
+        w[4 * (l.gauss + e) + dd] = bf16_pair(piece(q, s0 + 2 * dd, n, x), piece(q, s0 + 2 * dd + 1, n, x));
+    }
+  }
+  const int MB = split_embed_mb(st.kN), KC = split_embed_kc(st.kS);
+  for (int e = 0; e < MB * KC * 64 * l.P; ++e) {
+    const int q = e % l.P, rest = e / l.P, lane = rest & 63, r2 = rest >> 6;
+    const int kc = r2 % KC, mb = r2 / KC;
+    const int n = 8 * mb + ((lane & 15) >> 1), b = lane & 1, s0 = 16 * kc + 4 * (lane >> 4);
+    for (int dd = 0; dd < 4; ++dd) {
+      const float re = piece(q, s0 + dd, n, 0), im = piece(q, s0 + dd, n, 1);
+      w[4 * (l.embed + e) + dd] = b == 0 ? bf16_pair(re, -im) : bf16_pair(im, re);
+    }
+  }
 }
 
 // FP32 image of a complex FP64 operator block for single-term FP32 steps.  Every entry is one of
@@ -163,11 +265,11 @@ void build_layout(const Program& P, DevState& S) {
     for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
       const Step& st = P.comps[c].steps[s];
       // FP64 steps: double2 blocks; FP32 steps: hi and lo float2 blocks (b = hi + lo to ~48 bits);
-      // 3xBF16 steps: float2 blocks (split on the device)
-      size_t e = st.compute == C_F64 ? 16 : (st.compute == C_F32 && st.two_term) ? 16 : 8;
+      // split steps: pieces and fragments (split_layout)
+      const size_t e = st.compute == C_F64 ? 16 : st.two_term ? 16 : 8;
       for (auto& b : st.B) {
         L.step_b[c][s].push_back(off);
-        off += align256(b.size() * e);
+        off += align256(st.compute == C_SPLIT ? size_t(split_layout(st).total) * 16 : b.size() * e);
       }
     }
   }
@@ -242,6 +344,12 @@ void build_layout(const Program& P, DevState& S) {
       d.L = st.L;
       d.nTiles = st.nTiles;
       d.mode = mode_of(st);
+      d.frag_gauss = d.frag_embed = -1;
+      if (st.compute == C_SPLIT) {
+        const SplitLayout sl = split_layout(st);
+        d.frag_gauss = int(sl.gauss);
+        d.frag_embed = int(sl.embed);
+      }
       std::memcpy(&S.host_image[L.step_desc[c][s]], &d, sizeof(d));
       for (size_t v = 0; v < st.B.size(); ++v) {
         unsigned char* dst = &S.host_image[L.step_b[c][s][v]];
@@ -251,10 +359,12 @@ void build_layout(const Program& P, DevState& S) {
             std::memcpy(dst + 16 * i, &re, 8);
             std::memcpy(dst + 16 * i + 8, &im, 8);
           }
+        } else if (st.compute == C_SPLIT) {
+          fill_split_block(st, st.B[v], dst);
         } else {
           const size_t nb = st.B[v].size();
           std::vector<float> bal;
-          const bool single = !(st.compute == C_F32 && st.two_term);
+          const bool single = !st.two_term;
           if (single) balanced_round(st.B[v], bal);
           for (size_t i = 0; i < nb; ++i) {
             float re = float(st.B[v][i].real()), im = float(st.B[v][i].imag());
@@ -286,12 +396,14 @@ void build_layout(const Program& P, DevState& S) {
       d.nsteps = ch.last - ch.first;
       d.T = ch.T;
       d.nHi = int(ch.hi.size());
+      d.split = P.comps[c].steps[ch.first].compute == C_SPLIT ? 1 : 0;
       int boff = 0;
       for (int j = 0; j < d.nsteps; ++j) {
         const Step& st = P.comps[c].steps[ch.first + j];
         d.st[j].kS = st.kS;
         d.st[j].boff = boff;
-        boff += 1 << (2 * st.kS);
+        d.st[j].frag = d.split ? int(split_layout(st).gauss) : 0;
+        boff += chain_step_ops(st.kS, d.split != 0);
         for (size_t i = 0; i < tb.sOff[j].size(); ++i) d.st[j].sOff[i] = tb.sOff[j][i];
         for (int i = 0; i < 48; ++i) d.st[j].fDig[i] = tb.fDig[j][i];
       }
@@ -431,7 +543,7 @@ std::map<std::vector<long long>, int> g_chain_cache;
 jf_status tune_chain(DevState& S, size_t c, int q, const ChainDesc* dd, const ChainDesc& hd,
                      const void* A, void* C, const ChainOps& ops, const std::vector<const StepDesc*>& sdd,
                      const std::vector<const StepDesc*>& shd, hipStream_t stream, int reps) {
-  std::vector<long long> key = {hd.T, hd.nTiles, A == C ? 1 : 0};
+  std::vector<long long> key = {hd.T, hd.nTiles, A == C ? 1 : 0, hd.split};
   for (const StepDesc* h : shd) {
     key.push_back(h->kS);
     key.push_back(resolve_variant(*h));
@@ -497,7 +609,7 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
       std::vector<const StepDesc*> sdd, shd;
       for (int q = ch.first; q < ch.last; ++q) {
         const int var = (q == lev.first && lev.site >= 0) ? v : 0;
-        ops.B[q - ch.first] = reinterpret_cast<const float2*>(ws + L.step_b[c][q][var]);
+        ops.B[q - ch.first] = ws + L.step_b[c][q][var];
         sdd.push_back(reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][q]));
         shd.push_back(reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][q]]));
       }
@@ -532,7 +644,7 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
           for (const StepDesc* h : shd) r.kS = std::max(r.kS, h->kS);
           r.kN = r.kS;
           r.L = ch.T;
-          r.mode = KM_F32;
+          r.mode = hd.split ? KM_SPLIT : KM_F32;
           r.variant = KV_CHAIN;
           r.component = int(c);
           r.steps = ch.last - ch.first;
@@ -1011,7 +1123,7 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
   const DevLayout& L = state_of(p).lay;
   unsigned char* w = static_cast<unsigned char*>(ws);
   // arithmetic margin of the form (the parity bar of its results)
-  const double margin = P.opt.dtype == JF_C128 ? 1e-12 : P.opt.dtype == JF_C64 ? 1e-6 : 3e-5;
+  const double margin = P.opt.dtype == JF_C128 ? 1e-12 : 1e-6;
   const double thr = 1.0 - eps;
   jf_decision d = {};
   d.margin = margin;

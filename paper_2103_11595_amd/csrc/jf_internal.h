@@ -86,7 +86,9 @@ Tensor contract_pair(const Tensor& a, const Tensor& b);
 
 // ---------------------------------------------------------------- program ---
 enum Prec { P_C128 = 0, P_C64 = 1 };            // storage
-enum Compute { C_F64 = 0, C_F32 = 1, C_BF16X3 = 2 };
+// C_SPLIT: every real product from three-way BF16 splits of both operands (six piece products on
+// the BF16 matrix cores, FP32 accumulation)
+enum Compute { C_F64 = 0, C_F32 = 1, C_SPLIT = 2 };
 
 constexpr int MAXK = 64;     // max K (=2^kS) and Nn (=2^kN) of one device step
 constexpr int MAXR = 256;    // max rows per tile
@@ -119,7 +121,10 @@ struct Step {
 constexpr int CHAIN_MAX_STEPS = 8;   // steps per chain
 constexpr int CHAIN_MAX_T = 12;      // log2 elements of a tile (32 KB of complex64)
 constexpr int CHAIN_MAX_U = 10;      // contracted positions of a chain
-constexpr int CHAIN_MAX_OPS = 4096;  // sum of K^2 over the chain's steps (operators in LDS)
+constexpr int CHAIN_MAX_OPS = 4096;        // FP32 chains: sum of K^2 over the steps (operators in LDS)
+constexpr int CHAIN_MAX_OPS_SPLIT = 2304;  // split chains: 16-byte operator fragments in LDS (36 KB)
+// LDS entries the operator of a chain step takes, against the budget of its kind above
+inline int chain_step_ops(int kS, bool split) { return split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : 1 << (2 * kS); }
 struct Chain {
   int first = 0, last = 0;       // steps of the component
   int T = 0;                     // tile bits

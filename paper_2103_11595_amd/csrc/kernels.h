@@ -25,7 +25,9 @@ struct StepDesc {
   long long nTiles;
   int mode;       // arithmetic of the step (see KernelMode)
   int variant;    // kernel used for it (see KernelVariant); read on the host only
-  int pad[2];
+  // split-form steps: offsets (16-byte units, from the start of the operator block) of its BF16
+  // fragments in the two matrix-core layouts (Gauss form, real embedding); -1 where absent
+  int frag_gauss, frag_embed;
   // tile bases by 4-bit digits of the tile index: digit c with value m sets the address bits
   // digA[16 c + m] (digC for C); the host fills them, the MFMA kernels copy them into LDS
   long long digA[DMAXHI / 4 * 16], digC[DMAXHI / 4 * 16];
@@ -55,30 +57,52 @@ enum KernelMode {
   KM_F64 = 0,       // double2 -> double2, FP64
   KM_F32 = 1,       // float2 -> float2, FP32
   KM_F32_TO_F64 = 2,// float2 -> double2, FP64 (closing part of the low-precision modes)
-  KM_BF16X3 = 3,    // float2 -> float2, three BF16 products per real product, FP32 accumulate
+  KM_SPLIT = 3,     // float2 -> float2, split form: every real product from three-way BF16 splits
+                    // (six piece products, FP32 accumulation); operator in 3 pieces
   KM_F32X2 = 4,     // float2 -> float2, FP32, operator as an FP32 pair (hi + lo) -- noise-carrying blocks
+  KM_SPLIT4 = 5,    // the split form with a fourth operator piece (the FP64 residual) -- noise-carrying blocks
 };
+// Operator block of a split-form step: P pieces (3, or 4 for KM_SPLIT4) of K x Nn entries,
+// row-major [s][n], each entry float4 (Re, Im, Re + Im, 0) whose values are exact BF16 numbers;
+// after them the same pieces as BF16 matrix-core fragments in LDS order (StepDesc::frag_gauss,
+// frag_embed; see split_gauss_frags / split_embed_frags).
+//   Gauss form (P = 3): MB = max(1, Nn / 16), KC = max(1, K / 32); entry e of 3 MB KC 64 3:
+//     piece q = e % 3, lane = (e / 3) % 64, kc, mb, x (Re, Im, Re + Im) the next mixed-radix digits;
+//     dword d holds the BF16 pair of component x at s = 32 kc + 8 (lane / 16) + 2 d (+ 1), n = 16 mb +
+//     lane % 16 (zero outside K x Nn)
+//   real embedding: MB = max(1, Nn / 8), KC = max(1, K / 16); entry e of MB KC 64 P: piece q = e % P,
+//     lane, kc, mb as above; dword d holds k = 2 s (low half) and 2 s + 1 (high) of B_real column
+//     2 n + b for s = 16 kc + 4 (lane / 16) + d, n = 8 mb + (lane % 16) / 2, b = lane % 2
+//     (B_real[2s + a][2n + b] = [[Re, Im], [-Im, Re]][a][b] of B[s][n])
+__host__ __device__ inline int split_gauss_mb(int kN) { return kN <= 4 ? 1 : 1 << (kN - 4); }
+__host__ __device__ inline int split_gauss_kc(int kS) { return kS <= 5 ? 1 : 1 << (kS - 5); }
+__host__ __device__ inline int split_embed_mb(int kN) { return kN <= 3 ? 1 : 1 << (kN - 3); }
+__host__ __device__ inline int split_embed_kc(int kS) { return kS <= 4 ? 1 : 1 << (kS - 4); }
 
 // Launch one step.  A / C may alias (in-place steps): every tile reads exactly the elements it
 // writes and stages them in LDS before writing.  B: K x Nn row-major, in the compute type
-// (double2 for FP64 modes, float2 otherwise).
+// (double2 for FP64 modes, float2 for FP32 modes, the pieces above for the split modes).
 hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h_desc, const void* A, void* C, const void* B,
                        hipStream_t stream);
 
-// Chains: up to CHAIN_STEPS consecutive in-place FP32 steps of one level (each K = Nn <= 32, every
-// step keeping the intermediate's layout) applied to one LDS tile of 2^T <= 2^CHAIN_T elements per
-// HBM pass.  Tile-local index l (compressed over the tile's positions) sits in the tensor at
+// Chains: up to CHAIN_STEPS consecutive in-place FP32 or split-form steps of one level (each
+// K = Nn <= 32, every step keeping the intermediate's layout) applied to one LDS tile of
+// 2^T <= 2^CHAIN_T elements per HBM pass.  Tile-local index l (compressed over the tile's positions) sits in the tensor at
 //   tile base + gDig[l & 15] + gDig[16 + ((l >> 4) & 15)] + gDig[32 + (l >> 8)],
 // the tile base being the scatter of the tile index over hi[0 .. nHi).  Step j contracts its K
 // indices s at tile-local sOff[s] against the remaining tile bits f at
 //   fDig[f & 15] + fDig[16 + ((f >> 4) & 15)] + fDig[32 + (f >> 8)],
-// and writes n at the same places (sOff[n]).  Its operator (K x K, float2, row-major [s][n]) is
-// ops.B[j]; in LDS it sits at entry boff.
+// and writes n at the same places (sOff[n]).  Its operator (K x K, row-major [s][n]: float2, or
+// the split-form pieces) is ops.B[j]; in LDS it sits at entry boff (float2 entries for FP32 steps,
+// 16-byte BF16 fragments for split steps: 576 max(1, K / 16) of them per step).
 constexpr int CHAIN_STEPS = 8;
 constexpr int CHAIN_T = 12;
-constexpr int CHAIN_OPS = 4096;  // float2 entries of all operators of a chain
+constexpr int CHAIN_OPS = 4096;        // float2 entries of all operators of an FP32 chain
+constexpr int CHAIN_OPS_SPLIT = 2304;  // 16-byte fragments of all operators of a split chain (36 KB)
 struct ChainStepDesc {
   int kS, boff;
+  int frag;  // split chains: offset (16-byte units) of the Gauss-form fragments in the operator block
+  int pad;
   unsigned short sOff[32];
   unsigned short fDig[48];
 };
@@ -87,10 +111,12 @@ struct ChainDesc {
   int hi[DMAXHI];
   long long nTiles;
   int nsteps, T, nHi, ops;
+  int split;  // 1: split-form steps
+  int pad;
   ChainStepDesc st[CHAIN_STEPS];
 };
 struct ChainOps {
-  const float2* B[CHAIN_STEPS];
+  const void* B[CHAIN_STEPS];
 };
 // A and C may alias (in place): a tile is read whole before any of it is written.
 hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h_desc, const void* A, void* C, const ChainOps& ops,

@@ -7,12 +7,14 @@
 // positions (see StepDesc).  The work is cut into tiles of 2^L rows (the lowest free bits, so
 // 16 consecutive rows are one contiguous run) times all K contracted combinations; tiles are
 // disjoint, so a step whose output layout equals its input layout runs in place.  Kernels:
-//   k_absorb, k_absorb_f32x2, k_absorb_bf16x3   vector FMA on a tile staged in LDS
+//   k_absorb, k_absorb_f32x2, k_absorb_split    vector FMA on a tile staged in LDS
 //   k_absorb_mfma        matrix cores on the real embedding, tile staged in LDS
 //   k_absorb_mfma_rd     matrix cores on the real embedding, operands straight into registers
 //   k_absorb_mfma_gauss  matrix cores, three real products per complex one, register-direct
-//   k_absorb_bf16x3_mfma BF16 matrix cores, three products per real product
-//   k_chain              several in-place FP32 steps applied to one LDS tile per HBM pass
+//   k_absorb_split_gauss, k_absorb_split_embed  the split form (three-way BF16 splits, six
+//                        piece products) on BF16 matrix cores, register-direct
+//   k_chain, k_chain_split  several in-place FP32 / split-form steps applied to one LDS tile
+//                        per HBM pass
 //   k_persistent         whole small components in one workgroup's LDS
 //   k_sumsq_part/_final  the FP64 double-double sum of |t|^2 (two fixed-tree passes)
 //   k_zero               a graph-safe fill
@@ -80,32 +82,50 @@ template <> __device__ __forceinline__ float2 cconv<float2, float2>(float2 v) { 
 template <> __device__ __forceinline__ double2 cconv<double2, float2>(float2 v) { return make_double2(v.x, v.y); }
 template <> __device__ __forceinline__ float2 cconv<float2, double2>(double2 v) { return make_float2(float(v.x), float(v.y)); }
 
-// Round-to-nearest-even truncation of an FP32 value to BF16 (kept in an FP32 register):
-// add half an ulp of the 16-bit result (plus the tie-to-even bit) and clear the low half.
-__device__ __forceinline__ float bf16_round(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return __uint_as_float(u & 0xFFFF0000u);
-}
+// ------------------------------------------------------------------- three-way BF16 split ---
+// The split form computes every real product a * b of an FP32 step from BF16 pieces: each FP32
+// operand is written as three BF16 values, x = x0 + x1 + x2 exactly (x0 = bf16(x), x1 = bf16(x - x0),
+// x2 = x - x0 - x1, which has at most 8 significant bits left; both roundings to nearest even, so
+// the pieces carry no sign bias), and the product keeps the six piece products of order 2^-16 of
+// it or more,
+//   a0 b0 + (a0 b1 + a1 b0) + (a0 b2 + a1 b1 + a2 b0),
+// each exact in FP32 (8 x 8 bits) and accumulated in FP32, the five small ones (smallest first)
+// before a0 b0; the three dropped products are below 2^-24 of the product, the accumulation rounds
+// as FP32 accumulation does.  Operator pieces come from the host as FP32 values that
+// are exact BF16 numbers: P = 3 pieces of the FP32 block, or P = 4 for noise-carrying blocks, whose
+// fourth piece is the residual of the FP64 block (it pairs with a0 only).  Layout of an operator
+// block: P pieces of K x Nn entries (row-major [s][n]), each entry float4 (Re, Im, Re + Im, 0).
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
 
-// 3xBF16 complex multiply-accumulate: every real product a*b becomes
-// hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b) with hi = bf16(x), lo = bf16(x - hi) (FP32 accumulation).
-struct SplitC {
-  float rh, rl, ih, il;
-};
-__device__ __forceinline__ SplitC split(float2 v) {
-  SplitC s;
-  s.rh = bf16_round(v.x);
-  s.rl = bf16_round(v.x - s.rh);
-  s.ih = bf16_round(v.y);
-  s.il = bf16_round(v.y - s.ih);
-  return s;
+// Pieces of two FP32 values, each piece a packed BF16 pair (the first value in the low half).
+__device__ __forceinline__ void split3_pair(float x, float y, uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  const f32x2v v = {x, y};
+  const bf16x2v b0 = __builtin_convertvector(v, bf16x2v);
+  const f32x2v r1 = v - __builtin_convertvector(b0, f32x2v);
+  const bf16x2v b1 = __builtin_convertvector(r1, bf16x2v);
+  const f32x2v r2 = r1 - __builtin_convertvector(b1, f32x2v);
+  const bf16x2v b2 = __builtin_convertvector(r2, bf16x2v);  // exact: r2 has at most 8 significant bits
+  p0 = __builtin_bit_cast(uint32_t, b0);
+  p1 = __builtin_bit_cast(uint32_t, b1);
+  p2 = __builtin_bit_cast(uint32_t, b2);
 }
-__device__ __forceinline__ float mul3(float ah, float al, float bh, float bl, float acc) {
-  acc = fmaf(al, bh, acc);
-  acc = fmaf(ah, bl, acc);
-  return fmaf(ah, bh, acc);
+// Pieces of eight FP32 values (k = 0..7 of one matrix-core operand): three BF16 octets.
+__device__ __forceinline__ void split3_oct(const float (&v)[8], bf16x8& p0, bf16x8& p1, bf16x8& p2) {
+  uint4 w0, w1, w2;
+  split3_pair(v[0], v[1], w0.x, w1.x, w2.x);
+  split3_pair(v[2], v[3], w0.y, w1.y, w2.y);
+  split3_pair(v[4], v[5], w0.z, w1.z, w2.z);
+  split3_pair(v[6], v[7], w0.w, w1.w, w2.w);
+  p0 = __builtin_bit_cast(bf16x8, w0);
+  p1 = __builtin_bit_cast(bf16x8, w1);
+  p2 = __builtin_bit_cast(bf16x8, w2);
 }
+// BF16 bit pattern of an FP32 value that is exactly a BF16 number (an operator piece).
+__device__ __forceinline__ uint32_t bf16_of(float x) { return __float_as_uint(x) >> 16; }
+__device__ __forceinline__ uint32_t bf16_pack(float lo, float hi) { return bf16_of(lo) | (bf16_of(hi) << 16); }
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 w) { return __builtin_bit_cast(bf16x8, w); }
 
 // ----------------------------------------------------------------------- absorb step ---
 struct Tables {
@@ -222,18 +242,38 @@ __global__ __launch_bounds__(256) void k_absorb_f32x2(const StepDesc* __restrict
   }
 }
 
-// 3xBF16 path: A and B split on their way into LDS.
-__global__ __launch_bounds__(256) void k_absorb_bf16x3(const StepDesc* __restrict__ d, const float2* A, float2* C,
-                                                       const float2* __restrict__ B) {
+// Split form on the vector units (any shape): per real product the six (P = 4: seven) piece
+// products of the split form.
+// acc += the piece products of a * b, the small ones first (smallest first), a0 b0 last
+template <int P>
+__device__ __forceinline__ float mul6(const float (&a)[3], const float (&b)[4], float acc) {
+  if (P == 4) acc = fmaf(a[0], b[3], acc);
+  acc = fmaf(a[2], b[0], acc);
+  acc = fmaf(a[1], b[1], acc);
+  acc = fmaf(a[0], b[2], acc);
+  acc = fmaf(a[1], b[0], acc);
+  acc = fmaf(a[0], b[1], acc);
+  return fmaf(a[0], b[0], acc);
+}
+
+// LDS: the A tile in FP32 (K x R), split when it is used; the operator's P pieces as packed BF16
+// (Re in the low half, Im in the high half), [s][n][piece].
+template <int P>
+__global__ __launch_bounds__(256) void k_absorb_split(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                      const float4* __restrict__ B) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ Tables tb;
   const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
   const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
   const long long nTiles = d->nTiles;
   load_tables(d, tb, K, Nn, R, nHi);
-  SplitC* sB = reinterpret_cast<SplitC*>(smem);
-  SplitC* sA = sB + K * Nn;
-  for (int i = threadIdx.x; i < K * Nn; i += blockDim.x) sB[i] = split(B[i]);
+  uint32_t* sB = reinterpret_cast<uint32_t*>(smem);
+  float2* sA = reinterpret_cast<float2*>(sB + P * K * Nn);
+  for (int i = threadIdx.x; i < K * Nn; i += blockDim.x)
+    for (int q = 0; q < P; ++q) {
+      const float4 b = B[q * K * Nn + i];
+      sB[i * P + q] = bf16_pack(b.x, b.y);
+    }
   __syncthreads();
   for (long long t = blockIdx.x; t < nTiles; t += gridDim.x) {
     long long bA = 0, bC = 0;
@@ -244,18 +284,30 @@ __global__ __launch_bounds__(256) void k_absorb_bf16x3(const StepDesc* __restric
       }
     for (int i = threadIdx.x; i < K * R; i += blockDim.x) {
       const int s = i >> L, r = i & (R - 1);
-      sA[i] = split(A[bA + tb.offS[s] + tb.offRA[r]]);
+      sA[i] = A[bA + tb.offS[s] + tb.offRA[r]];
     }
     __syncthreads();
     for (int o = threadIdx.x; o < Nn * R; o += blockDim.x) {
       const int n = o >> L, r = o & (R - 1);
       float re = 0.f, im = 0.f;
       for (int s = 0; s < K; ++s) {
-        const SplitC a = sA[s * R + r], b = sB[s * Nn + n];
-        re = mul3(a.rh, a.rl, b.rh, b.rl, re);
-        re = mul3(-a.ih, -a.il, b.ih, b.il, re);
-        im = mul3(a.rh, a.rl, b.ih, b.il, im);
-        im = mul3(a.ih, a.il, b.rh, b.rl, im);
+        const float2 av = sA[s * R + r];
+        uint32_t p0, p1, p2;
+        split3_pair(av.x, av.y, p0, p1, p2);
+        const float ar[3] = {__uint_as_float(p0 << 16), __uint_as_float(p1 << 16), __uint_as_float(p2 << 16)};
+        const float ai[3] = {__uint_as_float(p0 & 0xFFFF0000u), __uint_as_float(p1 & 0xFFFF0000u),
+                             __uint_as_float(p2 & 0xFFFF0000u)};
+        const float nai[3] = {-ai[0], -ai[1], -ai[2]};
+        float br[4] = {0.f, 0.f, 0.f, 0.f}, bi[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < P; ++q) {
+          const uint32_t w = sB[(s * Nn + n) * P + q];
+          br[q] = __uint_as_float(w << 16);
+          bi[q] = __uint_as_float(w & 0xFFFF0000u);
+        }
+        re = mul6<P>(ar, br, re);   // Re C += Re A Re B - Im A Im B
+        re = mul6<P>(nai, bi, re);
+        im = mul6<P>(ar, bi, im);   // Im C += Re A Im B + Im A Re B
+        im = mul6<P>(ai, br, im);
       }
       C[bC + tb.offN[n] + tb.offRC[r]] = make_float2(re, im);
     }
@@ -662,17 +714,250 @@ __device__ __forceinline__ void chain_step(float2* tile, const float2* __restric
   }
 }
 
-// A chain of in-place FP32 steps, one HBM pass (see ChainDesc).  Each workgroup loops over tiles
-// with the grid stride: the tile's 2^T elements go from registers into LDS, the next tile's loads
-// are issued, every step of the chain runs on the LDS tile (a barrier after each), and the tile
-// goes back to HBM.  Element l of the tile belongs to thread l % NT throughout the loads, the LDS
-// fill and the stores, so the store phase and the next fill need no barrier between them.
-// Occupancy 3 (three 256-thread workgroups per CU when the operators leave room in LDS): with
-// the register budget that gives, the n=16 workload's 2^26-element chain takes 300 us against
-// 337 us at the compiler's default of 2 and 406 us with 512-thread workgroups (measured on MI355X).
-template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_chain(const ChainDesc* __restrict__ d, const float2* A, float2* C,
-                                              ChainOps ops) {
+// Split form on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Operand layout of the
+// instruction: lane l supplies A-operand row l % 16, k = 8 (l / 16) .. + 7 and B-operand column
+// l % 16, same k (8 BF16 values, 16 bytes); accumulator register v holds row 4 (l / 16) + v.  The
+// operator is the A-operand (rows = outputs), the data the B-operand (columns = 16 tile rows of a
+// unit).  Operator pieces sit in LDS in fragment order: the P (or 3) 16-byte pieces a lane feeds
+// to one instruction are consecutive, so a lane's reads are contiguous and conflict free.
+__device__ __forceinline__ floatx4 mfma_bf16(bf16x8 op, bf16x8 x, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(op, x, c, 0, 0, 0);
+}
+
+// Gauss form: T1 = sum Re B . Re A, T2 = sum Im B . Im A, T3 = sum (Re B + Im B)(Re A + Im A),
+// Re C = T1 - T2, Im C = T3 - T1 - T2; MFMA k runs over s (32 per chunk kc), the 16 rows of block mb
+// are n = 16 mb + 0..15.  Fragments (three pieces per lane and instruction) as kernels.h lays out.
+__device__ __forceinline__ void copy_frags(const uint4* __restrict__ src, uint4* dst, int n, int tid, int nt) {
+  for (int i = tid; i < n; i += nt) dst[i] = src[i];
+}
+
+// The Gauss-form split products of one unit (16 columns): a[kc][e] is A at s = 32 kc + 8 g + e for
+// this lane's column (zero past K).  T[x][mb] = T1, T2, T3 of output rows n = 16 mb + 4 g + v.  The
+// step kernel and the chain kernel both call this, so a chain reproduces its steps bit for bit.
+template <int MB, int KC>
+__device__ __forceinline__ void gauss6_products(const float2 (&a)[KC][8], const uint4* __restrict__ fr, int lane,
+                                                floatx4 (&T)[3][MB]) {
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) T[x][mb] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    float vr[8], vi[8], vs[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      vr[e] = a[kc][e].x;
+      vi[e] = a[kc][e].y;
+      vs[e] = vr[e] + vi[e];
+    }
+    bf16x8 A[3][3];
+    split3_oct(vr, A[0][0], A[0][1], A[0][2]);
+    split3_oct(vi, A[1][0], A[1][1], A[1][2]);
+    split3_oct(vs, A[2][0], A[2][1], A[2][2]);
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const uint4* f = fr + ((((x * MB + mb) * KC + kc) * 64 + lane) * 3);
+        const bf16x8 b0 = as_bf16x8(f[0]), b1 = as_bf16x8(f[1]), b2 = as_bf16x8(f[2]);
+        floatx4 t = T[x][mb];
+        t = mfma_bf16(b0, A[x][2], t);
+        t = mfma_bf16(b1, A[x][1], t);
+        t = mfma_bf16(b2, A[x][0], t);
+        t = mfma_bf16(b0, A[x][1], t);
+        t = mfma_bf16(b1, A[x][0], t);
+        T[x][mb] = mfma_bf16(b0, A[x][0], t);
+      }
+  }
+}
+
+// Register-direct Gauss-form split kernel (single-term operators, P = 3).  Units, prefetch and
+// in-place safety as in k_absorb_mfma_rd: a unit is (tile, block of 16 tile rows), each wave takes
+// units independently and loads its next unit while multiplying the current one.
+template <int NT, int MB, int KC>
+__global__ __launch_bounds__(NT) void k_absorb_split_gauss(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                           const float4* __restrict__ B) {
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  __shared__ TileBases tbb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int rbits = L - 4;
+  const long long nUnits = d->nTiles << rbits;
+  load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
+  uint4* fr = reinterpret_cast<uint4*>(smem);
+  copy_frags(reinterpret_cast<const uint4*>(B) + d->frag_gauss, fr, 3 * MB * KC * 64 * 3, threadIdx.x, NT);
+  __syncthreads();  // offset tables and operator visible to every wave
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const long long wstride = (long long)gridDim.x * NW;
+  auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
+  float2 nxt[KC][8];
+  auto fetch = [&](long long v) {
+    const long long bA = tile_base(tbb.chA, v >> rbits) + tb.offRA[row_of_unit(v)];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int sv = 32 * kc + 8 * g + e;
+        const float2 x = ld_stream(&A[bA + tb.offS[sv < K ? sv : K - 1]]);  // in-bounds address for every lane
+        nxt[kc][e] = sv < K ? x : float2{0.f, 0.f};
+      }
+  };
+  long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
+  if (v < nUnits) fetch(v);
+  for (; v < nUnits; v += wstride) {
+    float2 cur[KC][8];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cur[kc][e] = nxt[kc][e];
+    if (v + wstride < nUnits) fetch(v + wstride);
+    floatx4 T[3][MB];
+    gauss6_products<MB, KC>(cur, fr, lane, T);
+    const long long bC = tile_base(tbb.chC, v >> rbits) + tb.offRC[row_of_unit(v)];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = mb * 16 + 4 * g + r;
+        float2 o;
+        o.x = T[0][mb][r] - T[1][mb][r];
+        o.y = T[2][mb][r] - T[0][mb][r] - T[1][mb][r];
+        if (n < Nn) st_stream(&C[bC + tb.offN[n]], o);
+      }
+  }
+}
+
+// Register-direct split kernel on the real embedding (any operator, P = 3 or 4): A_real[r][2s + a],
+// B_real[2s + a][2n + b] = [[Re, Im], [-Im, Re]][a][b] of B[s][n].  Block mb holds outputs
+// n = 8 mb + 0..7, MFMA row 2 (n - 8 mb) + b (so accumulator registers (0, 1) and (2, 3) of a lane
+// are the (Re, Im) pairs of n = 8 mb + 2 g and + 1); chunk kc holds k = 2s + a for s = 16 kc + 4 g
+// + 0..3 in lane group g.  Fragments (P pieces per lane and instruction) as kernels.h lays out.
+template <int NT, int MB, int KC, int P>
+__global__ __launch_bounds__(NT) void k_absorb_split_embed(const StepDesc* __restrict__ d, const float2* A, float2* C,
+                                                           const float4* __restrict__ B) {
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Tables tb;
+  __shared__ TileBases tbb;
+  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
+  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
+  const int rbits = L - 4;
+  const long long nUnits = d->nTiles << rbits;
+  load_tables(d, tb, K, Nn, R, nHi);
+  load_tile_bases(d, tbb, nHi);
+  uint4* fr = reinterpret_cast<uint4*>(smem);
+  copy_frags(reinterpret_cast<const uint4*>(B) + d->frag_embed, fr, MB * KC * 64 * P, threadIdx.x, NT);
+  __syncthreads();  // offset tables and operator visible to every wave
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const long long wstride = (long long)gridDim.x * NW;
+  auto row_of_unit = [&](long long v) { return ((int)(v & ((1 << rbits) - 1)) << 4) + l16; };
+  float2 nxt[KC][4];
+  auto fetch = [&](long long v) {
+    const long long bA = tile_base(tbb.chA, v >> rbits) + tb.offRA[row_of_unit(v)];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int sv = 16 * kc + 4 * g + e;
+        const float2 x = ld_stream(&A[bA + tb.offS[sv < K ? sv : K - 1]]);  // in-bounds address for every lane
+        nxt[kc][e] = sv < K ? x : float2{0.f, 0.f};
+      }
+  };
+  long long v = (long long)blockIdx.x * NW + (threadIdx.x >> 6);
+  if (v < nUnits) fetch(v);
+  for (; v < nUnits; v += wstride) {
+    float2 cur[KC][4];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cur[kc][e] = nxt[kc][e];
+    if (v + wstride < nUnits) fetch(v + wstride);
+    floatx4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = floatx4{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const float vv[8] = {cur[kc][0].x, cur[kc][0].y, cur[kc][1].x, cur[kc][1].y,
+                           cur[kc][2].x, cur[kc][2].y, cur[kc][3].x, cur[kc][3].y};
+      bf16x8 a0, a1, a2;
+      split3_oct(vv, a0, a1, a2);
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        const uint4* f = fr + (((mb * KC + kc) * 64 + lane) * P);
+        const bf16x8 b0 = as_bf16x8(f[0]), b1 = as_bf16x8(f[1]), b2 = as_bf16x8(f[2]);
+        floatx4 t = acc[mb];
+        if (P == 4) t = mfma_bf16(as_bf16x8(f[3]), a0, t);
+        t = mfma_bf16(b0, a2, t);
+        t = mfma_bf16(b1, a1, t);
+        t = mfma_bf16(b2, a0, t);
+        t = mfma_bf16(b0, a1, t);
+        t = mfma_bf16(b1, a0, t);
+        acc[mb] = mfma_bf16(b0, a0, t);
+      }
+    }
+    const long long bC = tile_base(tbb.chC, v >> rbits) + tb.offRC[row_of_unit(v)];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const floatx4 t = acc[mb];
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const int n = 8 * mb + 2 * g + p2;
+        if (n < Nn) st_stream(&C[bC + tb.offN[n]], make_float2(t[2 * p2], t[2 * p2 + 1]));
+      }
+    }
+  }
+}
+
+// One step of a split-form chain on the LDS tile: the Gauss-form split products of
+// k_absorb_split_gauss (gauss6_products, the same operations in the same order), a unit being 16
+// values of the step's untouched tile bits whose outputs overwrite exactly the elements it read.
+template <int NT, int MB>
+__device__ __forceinline__ void chain_step_split(float2* tile, const uint4* __restrict__ fr, const ChainStepDesc& sd,
+                                                 int T) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
+  const int K = 1 << sd.kS;
+  const int units = 1 << (T - sd.kS - 4);
+  for (int u = wave; u < units; u += NW) {
+    const int f = (u << 4) + l16;
+    const int fl = sd.fDig[f & 15] + sd.fDig[16 + ((f >> 4) & 15)] + sd.fDig[32 + ((f >> 8) & 15)];
+    float2 a[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int sv = 8 * g + e;
+      const float2 x = tile[fl + sd.sOff[sv < K ? sv : K - 1]];
+      a[0][e] = sv < K ? x : float2{0.f, 0.f};
+    }
+    floatx4 Tm[3][MB];
+    gauss6_products<MB, 1>(a, fr, lane, Tm);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = mb * 16 + 4 * g + r;
+        if (n < K) {
+          float2 o;
+          o.x = Tm[0][mb][r] - Tm[1][mb][r];
+          o.y = Tm[2][mb][r] - Tm[0][mb][r] - Tm[1][mb][r];
+          tile[fl + sd.sOff[n]] = o;
+        }
+      }
+  }
+}
+
+// A chain of in-place steps, one HBM pass (see ChainDesc).  Each workgroup loops over tiles with
+// the grid stride: the tile's 2^T elements go from registers into LDS, the next tile's loads are
+// issued, every step of the chain runs on the LDS tile (a barrier after each), and the tile goes
+// back to HBM.  Element l of the tile belongs to thread l % NT throughout the loads, the LDS fill
+// and the stores, so the store phase and the next fill need no barrier between them.  SPLIT: the
+// steps compute the split form (operators as BF16 fragments in LDS), else FP32 (complex operators
+// in LDS).
+template <int NT, bool SPLIT>
+__device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, const float2* A, float2* C,
+                                           const ChainOps& ops) {
   static_assert(NT % 256 == 0 && NT <= 1024, "digits 0 and 1 of a thread's elements are its own");
   constexpr int EPT = (1 << CHAIN_T) / NT;
   __shared__ float2 tile[1 << CHAIN_T];
@@ -680,7 +965,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ long long gd[48];
   __shared__ long long hb[NDIG][16];
   extern __shared__ __align__(16) unsigned char smem[];
-  float2* sOp = reinterpret_cast<float2*>(smem);
   const int nsteps = d->nsteps, T = d->T, nHi = d->nHi;
   const long long nTiles = d->nTiles;
   for (int i = threadIdx.x; i < 48; i += NT) gd[i] = d->gDig[i];
@@ -698,8 +982,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     for (int i = threadIdx.x; i < words; i += NT) dst[i] = src[i];
   }
   for (int j = 0; j < nsteps; ++j) {
-    const int KK = 1 << (2 * d->st[j].kS), bo = d->st[j].boff;
-    for (int i = threadIdx.x; i < KK; i += NT) sOp[bo + i] = ops.B[j][i];
+    const int kS = d->st[j].kS, bo = d->st[j].boff;
+    if (SPLIT) {
+      copy_frags(static_cast<const uint4*>(ops.B[j]) + d->st[j].frag, reinterpret_cast<uint4*>(smem) + bo,
+                 576 * split_gauss_mb(kS), threadIdx.x, NT);
+    } else {
+      const float2* Bj = static_cast<const float2*>(ops.B[j]);
+      float2* sOp = reinterpret_cast<float2*>(smem);
+      for (int i = threadIdx.x; i < (1 << (2 * kS)); i += NT) sOp[bo + i] = Bj[i];
+    }
   }
   __syncthreads();  // tables and operators visible to every wave
   const int E = 1 << T;
@@ -727,12 +1018,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __syncthreads();  // the whole tile is in LDS
     if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
     for (int j = 0; j < nsteps; ++j) {
-      const float2* Bj = sOp + sd[j].boff;
-      switch (sd[j].kS) {
-        case 5: chain_step<NT, 8, 2>(tile, Bj, sd[j], T); break;
-        case 4: chain_step<NT, 4, 1>(tile, Bj, sd[j], T); break;
-        case 3: chain_step<NT, 2, 1>(tile, Bj, sd[j], T); break;
-        default: chain_step<NT, 1, 1>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+      if (SPLIT) {
+        const uint4* fr = reinterpret_cast<const uint4*>(smem) + sd[j].boff;
+        if (sd[j].kS == 5) chain_step_split<NT, 2>(tile, fr, sd[j], T);
+        else chain_step_split<NT, 1>(tile, fr, sd[j], T);  // kS = 1 .. 4
+      } else {
+        const float2* Bj = reinterpret_cast<const float2*>(smem) + sd[j].boff;
+        switch (sd[j].kS) {
+          case 5: chain_step<NT, 8, 2>(tile, Bj, sd[j], T); break;
+          case 4: chain_step<NT, 4, 1>(tile, Bj, sd[j], T); break;
+          case 3: chain_step<NT, 2, 1>(tile, Bj, sd[j], T); break;
+          default: chain_step<NT, 1, 1>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+        }
       }
       __syncthreads();  // step j complete on the whole tile
     }
@@ -743,112 +1040,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
   }
 }
 
-// 3xBF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, gfx950).  Every FP32 operand x is split
-// into hi = bf16(x) and lo = bf16(x - hi); a product a*b is hi(a)hi(b) + hi(a)lo(b) + lo(a)hi(b)
-// with FP32 accumulation (the cross terms in their own accumulator, added at the end).
-// Operand layout of the instruction: lane l supplies A-operand row l%16, k = 8(l/16) .. +7 and
-// B-operand column l%16, same k; accumulator register v holds row 4(l/16) + v (as FP32 16x16x4).
-// LDS holds both operands split, as BF16, row-major with the 2K reals of a row contiguous (rows
-// padded to whole 32-k chunks plus 8, so a lane's 8 consecutive k are one 16-byte read).
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as_float(uint32_t(b) << 16); }
-__device__ __forceinline__ bf16x8 lds8(const unsigned short* p) {
-  const uint4 v = *reinterpret_cast<const uint4*>(p);
-  return __builtin_bit_cast(bf16x8, v);
-}
-
+// FP32 chains at occupancy 3 (three 256-thread workgroups per CU when the operators leave room in
+// LDS): with the register budget that gives, the n=16 workload's 2^26-element chain takes 300 us
+// against 337 us at the compiler's default of 2 and 406 us with 512-thread workgroups (measured on
+// MI355X).  Split-form chains hold up to 36 KB of operator fragments beside the 32 KB tile, so
+// two workgroups share a CU.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_absorb_bf16x3_mfma(const StepDesc* __restrict__ d, const float2* A, float2* C,
-                                                           const float2* __restrict__ B) {
-  using M = Mfma<float>;  // same accumulator layout
-  constexpr int MAXE = 4096 / NT;
-  constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ Tables tb;
-  __shared__ TileBases tbb;
-  const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
-  const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
-  const int K2 = 2 * K, M2 = 2 * Nn, KR = K * R;
-  const int K2c = (K2 + 31) & ~31, KP = K2c + 8;  // k chunks of 32, row pitch in BF16 elements
-  const long long nTiles = d->nTiles;
-  load_tables(d, tb, K, Nn, R, nHi);
-  load_tile_bases(d, tbb, nHi);
-  unsigned short* sBh = reinterpret_cast<unsigned short*>(smem);  // [i][KP], i < M2
-  unsigned short* sBl = sBh + M2 * KP;
-  unsigned short* sAh = sBl + M2 * KP;                            // [j][KP], j < R
-  unsigned short* sAl = sAh + R * KP;
-  for (int idx = threadIdx.x; idx < (2 * M2 + 2 * R) * KP; idx += NT) sBh[idx] = 0;  // zero padding
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < K2 * M2; idx += NT) {
-    const int k = idx / M2, i = idx - k * M2;
-    const int n = (i >> 4) * 8 + M::n_of(i & 15), cb = M::c_of(i & 15);
-    const int s = k >> 1, ca = k & 1;
-    const float2 bv = B[s * Nn + n];
-    float v = (ca ^ cb) ? bv.y : bv.x;
-    if (ca && !cb) v = -v;
-    const unsigned short h = bf16_bits(v);
-    sBh[i * KP + k] = h;
-    sBl[i * KP + k] = bf16_bits(v - bf16_value(h));
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, l16 = lane & 15;
-  const int Mb = M2 >> 4, Nb = R >> 4;
-  float2 stage[MAXE];
-  auto fetch = [&](long long t) {
-    const long long bA = tile_base(tbb.chA, t);
-#pragma unroll
-    for (int e = 0; e < MAXE; ++e) {
-      const int i = threadIdx.x + NT * e;
-      if (i < KR) stage[e] = ld_stream(&A[bA + tb.offS[i >> L] + tb.offRA[i & (R - 1)]]);
-    }
-  };
-  long long t = blockIdx.x;
-  if (t < nTiles) fetch(t);
-  for (; t < nTiles; t += gridDim.x) {
-    const long long bC = tile_base(tbb.chC, t);
-    __syncthreads();  // every wave is done with the previous tile
-#pragma unroll
-    for (int e = 0; e < MAXE; ++e) {
-      const int i = threadIdx.x + NT * e;
-      if (i < KR) {
-        const int s = i >> L, r = i & (R - 1);
-        const unsigned short hr = bf16_bits(stage[e].x), hi = bf16_bits(stage[e].y);
-        sAh[r * KP + 2 * s] = hr;
-        sAh[r * KP + 2 * s + 1] = hi;
-        sAl[r * KP + 2 * s] = bf16_bits(stage[e].x - bf16_value(hr));
-        sAl[r * KP + 2 * s + 1] = bf16_bits(stage[e].y - bf16_value(hi));
-      }
-    }
-    __syncthreads();
-    if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
-    for (int nb = wave; nb < Nb; nb += NW) {
-      const int j = nb * 16 + l16;
-      for (int mb = 0; mb < Mb; ++mb) {
-        floatx4 acc = {0, 0, 0, 0}, cross = {0, 0, 0, 0};
-        const unsigned short* bh = sBh + (mb * 16 + l16) * KP + 8 * g;
-        const unsigned short* bl = sBl + (mb * 16 + l16) * KP + 8 * g;
-        const unsigned short* ah = sAh + j * KP + 8 * g;
-        const unsigned short* al = sAl + j * KP + 8 * g;
-        for (int kc = 0; kc < K2c; kc += 32) {
-          const bf16x8 xbh = lds8(bh + kc), xbl = lds8(bl + kc), xah = lds8(ah + kc), xal = lds8(al + kc);
-          cross = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbl, xah, cross, 0, 0, 0);
-          cross = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbh, xal, cross, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xbh, xah, acc, 0, 0, 0);
-        }
-        for (int p = 0; p < 2; ++p) {
-          const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
-          st_stream(&C[bC + tb.offN[n] + tb.offRC[j]], make_float2(acc[2 * p] + cross[2 * p], acc[2 * p + 1] + cross[2 * p + 1]));
-        }
-      }
-    }
-  }
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_chain(const ChainDesc* __restrict__ d,
+                                                                                    const float2* A, float2* C,
+                                                                                    ChainOps ops) {
+  chain_body<NT, false>(d, A, C, ops);
+}
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_chain_split(
+    const ChainDesc* __restrict__ d, const float2* A, float2* C, ChainOps ops) {
+  chain_body<NT, true>(d, A, C, ops);
 }
 
 // ---------------------------------------------------------------------- small kernels ---
@@ -932,6 +1138,15 @@ __global__ __launch_bounds__(256) void k_sumsq_final(const double* part, int G, 
 // computes every output element with one thread (no in-place: the two buffers alternate).
 __device__ __forceinline__ double2 load_op(const void* B, int mode, int idx, int KN) {
   if (mode == KM_F64 || mode == KM_F32_TO_F64) return reinterpret_cast<const double2*>(B)[idx];
+  if (mode == KM_SPLIT || mode == KM_SPLIT4) {  // the sum of the pieces
+    double2 v = make_double2(0.0, 0.0);
+    for (int q = 0; q < (mode == KM_SPLIT4 ? 4 : 3); ++q) {
+      const float4 b = reinterpret_cast<const float4*>(B)[q * KN + idx];
+      v.x += b.x;
+      v.y += b.y;
+    }
+    return v;
+  }
   const float2 h = reinterpret_cast<const float2*>(B)[idx];
   double2 v = make_double2(h.x, h.y);
   if (mode == KM_F32X2) {
@@ -1162,6 +1377,55 @@ void launch_gauss(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc,
   else launch_gauss_mb<T, NT, 4>(h, stream, d_desc, A, C, B);
 }
 
+// Split-form launches with the operator block counts fixed at compile time.
+template <int NT, int MB, int KC>
+void launch_split_gauss_mk(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                           const void* B) {
+  const float2* a = (const float2*)A;
+  const float4* b = (const float4*)B;
+  float2* c = (float2*)C;
+  const long long units = h.nTiles << (h.L - 4);
+  const long long wgs = (units + NT / 64 - 1) / (NT / 64);
+  const size_t sm = size_t(3 * MB * KC * 64 * 3) * sizeof(uint4);
+  JF_LAUNCH_RESIDENT((k_absorb_split_gauss<NT, MB, KC>), wgs);
+}
+template <int NT>
+void launch_split_gauss(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                        const void* B) {
+  if (h.kS == 6) return launch_split_gauss_mk<NT, 1, 2>(h, stream, d_desc, A, C, B);  // kN <= 4
+  if (h.kN <= 4) return launch_split_gauss_mk<NT, 1, 1>(h, stream, d_desc, A, C, B);
+  if (h.kN == 5) return launch_split_gauss_mk<NT, 2, 1>(h, stream, d_desc, A, C, B);
+  launch_split_gauss_mk<NT, 4, 1>(h, stream, d_desc, A, C, B);
+}
+template <int MB, int KC, int P>
+void launch_split_embed_mkp(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                            const void* B) {
+  constexpr int NT = 256;
+  const float2* a = (const float2*)A;
+  const float4* b = (const float4*)B;
+  float2* c = (float2*)C;
+  const long long units = h.nTiles << (h.L - 4);
+  const long long wgs = (units + NT / 64 - 1) / (NT / 64);
+  const size_t sm = size_t(MB * KC * 64 * P) * sizeof(uint4);
+  JF_LAUNCH_RESIDENT((k_absorb_split_embed<NT, MB, KC, P>), wgs);
+}
+template <int P>
+void launch_split_embed(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
+                        const void* B) {
+  const int MB = h.kN <= 3 ? 1 : 1 << (h.kN - 3), KC = h.kS <= 4 ? 1 : 1 << (h.kS - 4);
+  switch (MB * 16 + KC) {
+    case 16 + 1: return launch_split_embed_mkp<1, 1, P>(h, stream, d_desc, A, C, B);
+    case 16 + 2: return launch_split_embed_mkp<1, 2, P>(h, stream, d_desc, A, C, B);
+    case 16 + 4: return launch_split_embed_mkp<1, 4, P>(h, stream, d_desc, A, C, B);
+    case 32 + 1: return launch_split_embed_mkp<2, 1, P>(h, stream, d_desc, A, C, B);
+    case 32 + 2: return launch_split_embed_mkp<2, 2, P>(h, stream, d_desc, A, C, B);
+    case 32 + 4: return launch_split_embed_mkp<2, 4, P>(h, stream, d_desc, A, C, B);
+    case 64 + 1: return launch_split_embed_mkp<4, 1, P>(h, stream, d_desc, A, C, B);
+    case 64 + 2: return launch_split_embed_mkp<4, 2, P>(h, stream, d_desc, A, C, B);
+    default: /* MB 8, KC 1 (split_direct_ok admits no other shape) */ return launch_split_embed_mkp<8, 1, P>(h, stream, d_desc, A, C, B);
+  }
+}
+
 static bool staged_ok(const StepDesc& h) {
   const int K = 1 << h.kS, R = 1 << h.L;
   return R >= 16 && K >= 2 && K * R <= 4096;
@@ -1170,6 +1434,15 @@ static bool direct_ok(const StepDesc& h) { return h.L >= 4 && h.kS <= 5 && h.kN 
 // (kS + kN <= 10: the larger blocks would spill registers)
 static bool gauss_ok(const StepDesc& h) {
   return h.L >= 4 && h.kS <= 6 && h.kN <= 6 && h.kS + h.kN <= 10 && h.mode != KM_F32X2;
+}
+// split form: Gauss products for single-term operators; the real embedding for any operator with
+// at most 8 blocks x chunks of fragments (<= 32 KB of LDS, registers within budget)
+static bool split_gauss_ok(const StepDesc& h) {
+  return h.mode == KM_SPLIT && h.L >= 4 && h.kS <= 6 && h.kN <= 6 && h.kS + h.kN <= 10;
+}
+static bool split_direct_ok(const StepDesc& h) {
+  const int MB = h.kN <= 3 ? 1 : 1 << (h.kN - 3), KC = h.kS <= 4 ? 1 : 1 << (h.kS - 4);
+  return h.L >= 4 && MB * KC <= 8;
 }
 
 bool variant_applies(const StepDesc& h, int v) {
@@ -1182,8 +1455,12 @@ bool variant_applies(const StepDesc& h, int v) {
       if (v == KV_DIRECT_256 || v == KV_DIRECT_512) return direct_ok(h);
       if (v == KV_GAUSS_256 || v == KV_GAUSS_512) return gauss_ok(h);
       return false;
-    case KM_BF16X3:
-      return v == KV_AUTO || v == KV_FMA || (v == KV_STAGED_256 && (1 << h.kN) >= 8 && h.L >= 4 && (1 << (h.kS + h.L)) <= 4096);
+    case KM_SPLIT:
+    case KM_SPLIT4:
+      if (v == KV_AUTO || v == KV_FMA) return true;
+      if (v == KV_DIRECT_256) return split_direct_ok(h);
+      if (v == KV_GAUSS_256 || v == KV_GAUSS_512) return split_gauss_ok(h);
+      return false;
     case KM_F32_TO_F64:
       return v == KV_AUTO || v == KV_FMA;
     default:
@@ -1194,7 +1471,8 @@ bool variant_applies(const StepDesc& h, int v) {
 // The fixed rule (KV_AUTO), from measurements on MI355X: register-direct for FP64 up to Nn = 32
 // and for FP32 with Nn <= 8; for FP32 blocks with K * Nn >= 512 (matrix-core bound at
 // 4 products per complex one) the Gauss form; staged MFMA otherwise; FMA for shapes no MFMA
-// kernel takes.
+// kernel takes.  Split form: Gauss products where the operator is single-term, the real
+// embedding otherwise, FMA where neither applies.
 static int auto_variant(const StepDesc& h) {
   const int Nn = 1 << h.kN;
   switch (h.mode) {
@@ -1206,8 +1484,10 @@ static int auto_variant(const StepDesc& h) {
       if (direct_ok(h) && Nn <= 8) return KV_DIRECT_512;
       if (h.kS + h.kN >= 9 && gauss_ok(h)) return KV_GAUSS_512;
       return staged_ok(h) ? KV_STAGED_256 : KV_FMA;
-    case KM_BF16X3:
-      return variant_applies(h, KV_STAGED_256) ? KV_STAGED_256 : KV_FMA;
+    case KM_SPLIT:
+    case KM_SPLIT4:
+      if (split_gauss_ok(h)) return KV_GAUSS_512;
+      return split_direct_ok(h) ? KV_DIRECT_256 : KV_FMA;
     default:
       return KV_FMA;
   }
@@ -1271,17 +1551,24 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
                          (const float2*)A, (double2*)C, (const double2*)B);
       break;
     }
-    case KM_BF16X3: {
-      if (v == KV_STAGED_256) {
-        const int KP = ((2 * K + 31) & ~31) + 8;
-        size_t sm = size_t(4 * Nn + 2 * R) * KP * sizeof(unsigned short);
-        JF_LAUNCH(k_absorb_bf16x3_mfma<256>, dim3(JF_RESIDENT(k_absorb_bf16x3_mfma<256>, 256, sm, h.nTiles)), dim3(256), sm, stream, d_desc, (const float2*)A,
-                           (float2*)C, (const float2*)B);
-        break;
+    case KM_SPLIT:
+    case KM_SPLIT4: {
+      const bool four = h.mode == KM_SPLIT4;
+      if (v == KV_GAUSS_256) launch_split_gauss<256>(h, stream, d_desc, A, C, B);
+      else if (v == KV_GAUSS_512) launch_split_gauss<512>(h, stream, d_desc, A, C, B);
+      else if (v == KV_DIRECT_256) {
+        if (four) launch_split_embed<4>(h, stream, d_desc, A, C, B);
+        else launch_split_embed<3>(h, stream, d_desc, A, C, B);
+      } else {
+        const int P = four ? 4 : 3;
+        const size_t sm = size_t(P * K * Nn) * sizeof(uint32_t) + size_t(K * R) * sizeof(float2);
+        if (four)
+          JF_LAUNCH(k_absorb_split<4>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+                    (const float4*)B);
+        else
+          JF_LAUNCH(k_absorb_split<3>, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
+                    (const float4*)B);
       }
-      size_t sm = size_t(K * Nn + K * R) * sizeof(SplitC);
-      JF_LAUNCH(k_absorb_bf16x3, dim3(grid), dim3(256), sm, stream, d_desc, (const float2*)A, (float2*)C,
-                         (const float2*)B);
       break;
     }
     default: return hipErrorInvalidValue;
@@ -1291,15 +1578,24 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
 
 hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void* A, void* C, const ChainOps& ops,
                         hipStream_t stream) {
-  if (h.nsteps < 1 || h.nsteps > CHAIN_STEPS || h.T < 4 || h.T > CHAIN_T || h.ops > CHAIN_OPS || h.nHi > DMAXHI)
+  if (h.nsteps < 1 || h.nsteps > CHAIN_STEPS || h.T < 4 || h.T > CHAIN_T || h.nHi > DMAXHI ||
+      h.ops > (h.split ? CHAIN_OPS_SPLIT : CHAIN_OPS))
     return hipErrorInvalidValue;
-  for (int j = 0; j < h.nsteps; ++j)
-    if (h.st[j].kS < 1 || h.st[j].kS > 5 || h.T - h.st[j].kS < 4 || h.st[j].boff + (1 << (2 * h.st[j].kS)) > h.ops)
-      return hipErrorInvalidValue;
+  for (int j = 0; j < h.nsteps; ++j) {
+    const int kS = h.st[j].kS;
+    const int need = h.split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : 1 << (2 * kS);
+    if (kS < 1 || kS > 5 || h.T - kS < 4 || h.st[j].boff + need > h.ops) return hipErrorInvalidValue;
+  }
   constexpr int NT = 256;
-  const size_t sm = size_t(h.ops) * sizeof(float2);
-  JF_LAUNCH(k_chain<NT>, dim3(JF_RESIDENT(k_chain<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
-            (const float2*)A, (float2*)C, ops);
+  if (h.split) {
+    const size_t sm = size_t(h.ops) * sizeof(uint4);
+    JF_LAUNCH(k_chain_split<NT>, dim3(JF_RESIDENT(k_chain_split<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
+              (const float2*)A, (float2*)C, ops);
+  } else {
+    const size_t sm = size_t(h.ops) * sizeof(float2);
+    JF_LAUNCH(k_chain<NT>, dim3(JF_RESIDENT(k_chain<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
+              (const float2*)A, (float2*)C, ops);
+  }
   return hipGetLastError();
 }
 

@@ -181,10 +181,11 @@ std::vector<int> step_s_positions(const Step& st) {
   return pos;
 }
 
-// In-place complex64 step with a single-term FP32 operator of at most 32 x 32 (the Gauss-form
-// products the chain kernel applies).
+// In-place complex64 step with a single-term FP32 or split-form operator of at most 32 x 32 (the
+// Gauss-form products the chain kernels apply).
 bool chainable(const Step& st) {
-  return st.inplace_ok && !st.final_step && st.compute == C_F32 && !st.two_term && st.in_prec == P_C64 &&
+  return st.inplace_ok && !st.final_step && (st.compute == C_F32 || st.compute == C_SPLIT) && !st.two_term &&
+         st.in_prec == P_C64 &&
          st.out_prec == P_C64 && st.kS == st.kN && st.kS >= 1 && st.kS <= 5;
 }
 
@@ -229,7 +230,8 @@ bool chain_tile(const std::set<int>& U, int rA, int ksmax, Chain& ch) {
 
 // What chain grouping needs to know of a step.
 struct ChainCand {
-  bool ok = false;         // chainable (in place, single-term FP32, K = Nn <= 32)
+  bool ok = false;         // chainable (in place, single-term FP32 or split form, K = Nn <= 32)
+  bool split = false;      // split-form step (its operator's LDS budget)
   int kS = 0, rA = 0;
   std::vector<int> spos;   // bit positions of its contracted legs
 };
@@ -247,7 +249,8 @@ void group_chains(const std::vector<ChainCand>& c, int first, int last, Emit&& e
       continue;
     }
     std::set<int> U(c[i].spos.begin(), c[i].spos.end());
-    int ops = 1 << (2 * c[i].kS), ksmax = c[i].kS;
+    const int budget = c[i].split ? CHAIN_MAX_OPS_SPLIT : CHAIN_MAX_OPS;
+    int ops = chain_step_ops(c[i].kS, c[i].split), ksmax = c[i].kS;
     Chain best;
     const bool have = chain_tile(U, c[i].rA, ksmax, best);
     int j = i + 1;
@@ -255,9 +258,9 @@ void group_chains(const std::vector<ChainCand>& c, int first, int last, Emit&& e
       if (!c[j].ok || c[j].rA != c[i].rA) break;
       std::set<int> U2 = U;
       U2.insert(c[j].spos.begin(), c[j].spos.end());
-      const int ops2 = ops + (1 << (2 * c[j].kS)), ks2 = std::max(ksmax, c[j].kS);
+      const int ops2 = ops + chain_step_ops(c[j].kS, c[j].split), ks2 = std::max(ksmax, c[j].kS);
       Chain c2;
-      if (ops2 > CHAIN_MAX_OPS || !chain_tile(U2, c[i].rA, ks2, c2)) break;
+      if (ops2 > budget || !chain_tile(U2, c[i].rA, ks2, c2)) break;
       U = U2;
       ops = ops2;
       ksmax = ks2;
@@ -280,6 +283,7 @@ double build_level_chains(ComponentProgram& cp, int first, int last, const CostM
   for (int q = first; q < last; ++q) {
     const Step& st = cp.steps[q];
     c[q].ok = chainable(st);
+    c[q].split = st.compute == C_SPLIT;
     c[q].kS = st.kS;
     c[q].rA = st.rA;
     if (c[q].ok) c[q].spos = step_s_positions(st);
@@ -381,7 +385,10 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   const int elem_lo = low ? 8 : 16;
   CostModel cm;
   if (opt.dtype == JF_C64) cm.flops = 70e12;  // FP32 MFMA contraction rate measured at K = 32 to 64
-  if (opt.dtype == JF_C64_BF16X3) cm.flops = 110e12;
+  if (opt.dtype == JF_C64_BF16X6) {
+    cm.flops = 200e12;        // split form on BF16 matrix cores: the steps stay HBM-bound
+    cm.chain_flops = 120e12;  // split-form chains: measured 80-137 TFLOP/s (2^24 to 2^26 elements)
+  }
 
   auto comps = components(net);
   std::mt19937_64 rng(opt.seed);
@@ -575,11 +582,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           std::sort(Sv.begin(), Sv.end(), [&](int a, int b) { return posT[a] < posT[b]; });
           std::sort(Nv.begin(), Nv.end(), [&](int a, int b) { return L.glob[a] < L.glob[b]; });
           ChainCand cc;
-          if (opt.dtype == JF_C64 && k < sw && !final_step && kS == kN && kS >= 1 && kS <= 5) {
+          if (opt.dtype != JF_C128 && k < sw && !final_step && kS == kN && kS >= 1 && kS <= 5) {
             bool noise = false;
             for (int q = k; q < e; ++q) noise = noise || L.ts[p.order[q]]->site >= 0;
             if (!noise) {
               cc.ok = true;
+              cc.split = opt.dtype == JF_C64_BF16X6;
               for (int l : Sv) cc.spos.push_back(posT[l]);
             }
           }
@@ -1008,13 +1016,14 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           st.in_prec = cur_prec;
           bool fp64 = (k >= switch_at) || final_step;
           st.out_prec = fp64 ? P_C128 : P_C64;
-          st.compute = fp64 ? C_F64 : (opt.dtype == JF_C64 ? C_F32 : C_BF16X3);
+          st.compute = fp64 ? C_F64 : (opt.dtype == JF_C64 ? C_F32 : C_SPLIT);
           cur_prec = st.out_prec;
           // Noise operators are near-identity blocks repeated at many sites: their FP32
           // rounding errors share a sign and add up linearly over the sites, so blocks that
-          // carry one keep the operator as an FP32 pair (hi + lo).  Gate-only blocks round
-          // with uncorrelated errors and stay single.
-          if (st.compute == C_F32)
+          // carry one keep the operator as an FP32 pair (hi + lo), or in the split form a fourth
+          // BF16 piece for the residual.  Gate-only blocks round with uncorrelated errors and
+          // stay single.
+          if (st.compute == C_F32 || st.compute == C_SPLIT)
             for (int q = k; q < e; ++q)
               if (L.ts[pth.order[q]]->site >= 0) st.two_term = true;
         }

@@ -18,8 +18,8 @@ import weakref
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjf.so")
 
-JF_C128, JF_C64, JF_C64_BF16X3 = 0, 1, 2
-DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x3": JF_C64_BF16X3}
+JF_C128, JF_C64, JF_C64_BF16X6 = 0, 1, 2
+DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x6": JF_C64_BF16X6}
 JF_FLAG_NO_CANCEL, JF_FLAG_NO_FUSE, JF_FLAG_NO_BATCH, JF_FLAG_GRAPH, JF_FLAG_NO_CHAIN = 1, 2, 4, 8, 16
 
 

@@ -274,7 +274,7 @@ def test_describe_bit_positions_are_consistent():
             assert len(set(a)) == len(a) and all(0 <= x < d["rA"] for x in a)
             c = d["rowsC"] + d["nC"]
             assert len(set(c)) == len(c) and all(0 <= x < d["rC"] for x in c)
-            assert d["compute"] in ("f64", "f32", "f32x2", "bf16x3")
+            assert d["compute"] in ("f64", "f32", "f32x2", "split", "split4")
 
 
 def test_estimated_time_grows_with_the_work():
@@ -315,9 +315,12 @@ def test_chains_group_consecutive_in_place_steps():
                 assert x["sA"] == x["nC"] and x["rowsA"] == x["rowsC"] and x["rA"] == x["rC"]
                 union |= set(x["sA"])
             assert len(union) <= 10
-    # complex128 and 3xBF16 plans and JF_FLAG_NO_CHAIN have none
-    for dt, flags in (("c128", 0), ("bf16x3", 0), ("c64", jf.JF_FLAG_NO_CHAIN)):
+    # complex128 plans and JF_FLAG_NO_CHAIN have none; split-form plans have their own
+    for dt, flags in (("c128", 0), ("c64", jf.JF_FLAG_NO_CHAIN), ("bf16x6", jf.JF_FLAG_NO_CHAIN)):
         assert all(x["chain"] == -1 for x in jf.plan(gen.config2(), 1, dt, flags=flags).describe())
+    split = jf.plan(gen.config2(), 1, "bf16x6").describe()
+    assert any(x["chain"] >= 0 for x in split)
+    assert all(x["compute"] == "split" for x in split if x["chain"] >= 0)
 
 
 def test_emulated_chains_match_oracle_and_unchained_program():
@@ -328,6 +331,21 @@ def test_emulated_chains_match_oracle_and_unchained_program():
         plain = jf.plan(inst, 1, "c64", flags=jf.JF_FLAG_NO_CHAIN).emulate()
         assert np.max(np.abs(chained - want)) < 1e-12
         assert np.max(np.abs(chained - plain)) < 1e-13
+
+
+def test_emulated_split_form_plans_match_oracle():
+    # split-form plans: noise blocks with the fourth operator piece, chains with their own LDS budget;
+    # the emulation runs the lowered program (chains through the chain tile tables) in FP64
+    n_chains = 0
+    for inst in _chain_instances():
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+        p = jf.plan(inst, 1, "bf16x6")
+        d = p.describe()
+        assert any(x["compute"] == "split4" for x in d)
+        n_chains += len({x["chain"] for x in d if x["chain"] >= 0})
+        assert np.max(np.abs(p.emulate() - want)) < 1e-12
+    assert n_chains > 0
 
 
 def _alg2_chain_instances():
