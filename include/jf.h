@@ -187,6 +187,8 @@ typedef struct {
   int alg;             /* 1 or 2: the algorithm of the plan */
   double est_seconds;  /* planner's cost-model estimate of one run's device time */
   int n_swaps_rewired; /* SWAP gates (after the cancellation) replaced by crossed wires */
+  int n_sliced_wires;  /* wire legs sliced: each is fixed to 0 and 1 in turn and the partial results
+                          of the depth-first leaves are added (plans over the cap) */
 } jf_plan_stats;
 jf_status jf_plan_stats_get(const jf_plan* plan, jf_plan_stats* stats);
 

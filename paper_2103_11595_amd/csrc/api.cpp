@@ -104,6 +104,7 @@ extern "C" jf_status jf_plan_stats_get(const jf_plan* p, jf_plan_stats* s) {
   r.alg = p->prog.opt.alg;
   r.est_seconds = p->prog.est_seconds;
   r.n_swaps_rewired = p->prog.n_swaps_rewired;
+  r.n_sliced_wires = p->prog.n_sliced_wires;
   *s = r;
   return JF_OK;
 }

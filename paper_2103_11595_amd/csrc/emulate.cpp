@@ -37,7 +37,7 @@ bool validate_program(const Program& P, std::string& why) {
       maxA = hA + mS + mRA;
       maxC = hC + mN + mRC;
       const long long sizeA = 1LL << st.rA;
-      const long long sizeC = st.final_step ? cp.out_len : (1LL << st.rC);
+      const long long sizeC = st.final_step ? (cp.accumulate ? cp.leaf_len : cp.out_len) : (1LL << st.rC);
       if (maxA >= sizeA || maxC >= sizeC) {
         why = "step " + std::to_string(s) + " addresses outside its tensors";
         return false;
@@ -47,6 +47,24 @@ bool validate_program(const Program& P, std::string& why) {
           why = "operator block size mismatch";
           return false;
         }
+      // operator variants: one per combination of the values of levels at or above the step's own
+      int own = -1;
+      for (size_t l = 0; l < cp.levels.size(); ++l)
+        if ((int)s >= cp.levels[l].first && (int)s < cp.levels[l].last) own = int(l);
+      long long nv = 1;
+      int prev = -1;
+      for (int lv : st.var_levels) {
+        if (lv <= prev || lv > own) {
+          why = "step " + std::to_string(s) + " depends on a level it does not lie in";
+          return false;
+        }
+        prev = lv;
+        nv *= cp.levels[lv].nvar;
+      }
+      if ((long long)st.B.size() != nv) {
+        why = "step " + std::to_string(s) + " has the wrong number of operator variants";
+        return false;
+      }
     }
     for (size_t q = 0; q < cp.chains.size(); ++q) {
       const Chain& ch = cp.chains[q];
@@ -82,6 +100,15 @@ bool validate_program(const Program& P, std::string& why) {
       const int q = cp.steps[s].chain;
       if (q >= 0 && (q >= (int)cp.chains.size() || (int)s < cp.chains[q].first || (int)s >= cp.chains[q].last)) {
         why = "step " + std::to_string(s) + " names a chain that does not hold it";
+        return false;
+      }
+    }
+    {  // the offsets of the Kraus-site levels and a leaf's output stay inside the output array
+      long long top = 0;
+      for (auto& lv : cp.levels) top += (lv.nvar - 1) * lv.out_stride;
+      const long long span = cp.accumulate ? cp.leaf_len : 1;
+      if (top + span > cp.out_len || (cp.accumulate && cp.leaf_len < 1)) {
+        why = "component " + std::to_string(c) + " output offsets exceed its array";
         return false;
       }
     }
@@ -215,30 +242,38 @@ void emulate_chain(const ComponentProgram& cp, const Chain& ch, const std::vecto
 }
 
 void emulate_level(const ComponentProgram& cp, int lv, const std::vector<cd>& parent, long long out_base,
-                   std::vector<cd>& out) {
+                   std::vector<int>& vv, std::vector<cd>& out) {
   const Level& L = cp.levels[lv];
   for (int v = 0; v < L.nvar; ++v) {
+    vv[lv] = v;
     std::vector<cd> cur = parent, nxt;
     for (int si = L.first; si < L.last; ++si) {
       const Step& st = cp.steps[si];
-      const std::vector<cd>& B = st.B[si == L.first && L.site >= 0 ? v : 0];
+      const std::vector<cd>& B = st.B[variant_index(cp, st, vv)];
       if (st.chain >= 0 && cp.chains[st.chain].first == si) {
         const Chain& ch = cp.chains[st.chain];
         std::vector<const std::vector<cd>*> Bs;
-        for (int q = ch.first; q < ch.last; ++q) Bs.push_back(&cp.steps[q].B[q == L.first && L.site >= 0 ? v : 0]);
+        for (int q = ch.first; q < ch.last; ++q) Bs.push_back(&cp.steps[q].B[variant_index(cp, cp.steps[q], vv)]);
         emulate_chain(cp, ch, Bs, cur);
         si = ch.last - 1;
         continue;
       }
       if (st.final_step) {
-        emulate_step(st, B, cur.data(), out.data() + out_base + v * L.out_stride);
+        cd* dst = out.data() + out_base + v * L.out_stride;
+        if (cp.accumulate) {  // a partial result of the sliced wires: added in
+          std::vector<cd> leaf(size_t(cp.leaf_len), 0.0);
+          emulate_step(st, B, cur.data(), leaf.data());
+          for (long long i = 0; i < cp.leaf_len; ++i) dst[i] += leaf[size_t(i)];
+        } else {
+          emulate_step(st, B, cur.data(), dst);
+        }
       } else {
         nxt.assign(size_t(1) << st.rC, 0.0);
         emulate_step(st, B, cur.data(), nxt.data());
         cur.swap(nxt);
       }
     }
-    if (lv + 1 < (int)cp.levels.size()) emulate_level(cp, lv + 1, cur, out_base + v * L.out_stride, out);
+    if (lv + 1 < (int)cp.levels.size()) emulate_level(cp, lv + 1, cur, out_base + v * L.out_stride, vv, out);
   }
 }
 
@@ -249,7 +284,8 @@ void emulate_program(const Program& p, std::vector<std::vector<cd>>& comp_out) {
   for (auto& cp : p.comps) {
     std::vector<cd> out(size_t(cp.out_len), 0.0);
     std::vector<cd> one(1, 1.0);
-    emulate_level(cp, 0, one, 0, out);
+    std::vector<int> vv(cp.levels.size(), 0);
+    emulate_level(cp, 0, one, 0, vv, out);
     comp_out.push_back(std::move(out));
   }
 }

@@ -35,6 +35,7 @@ struct DevLayout {
   size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
   size_t sumsq_off = 0;  // scratch of the two-pass sum of |t|^2 (2 SUMSQ_BLOCKS doubles)
   size_t lds_items_off = 0, lds_steps_off = 0;
+  std::vector<size_t> leaf_off;                           // per component with sliced wires: its leaf buffer
   std::vector<int> lds_comps;                             // components run by the persistent kernel
   int lds_steps = 0;
   std::vector<std::vector<size_t>> step_desc;             // per component, per step: descriptor offset
@@ -306,6 +307,12 @@ void build_layout(const Program& P, DevState& S) {
   long long outn = 0;
   for (auto& cp : P.comps) outn += cp.out_len;
   off += align256(size_t(outn) * 16);
+  L.leaf_off.assign(P.comps.size(), 0);
+  for (size_t c = 0; c < P.comps.size(); ++c)
+    if (P.comps[c].accumulate) {
+      L.leaf_off[c] = off;
+      off += align256(size_t(P.comps[c].leaf_len) * 16);
+    }
   L.sums_off = off;
   off += align256(P.comps.size() * 4 * sizeof(double));
   L.sumsq_off = off;
@@ -585,8 +592,9 @@ jf_status tune_chain(DevState& S, size_t c, int q, const ChainDesc* dd, const Ch
 // Enqueue the steps of level lv of component c for Kraus variant v of the level's sliced site,
 // starting from `parent` (nullptr: the constant 1 of the first step's precision), the component's
 // output at element offset `base`; *end receives the level's last output (no synchronisation).
-jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, int lv, int v,
-                        const void* parent, long long base, const void** end, Prof* prof, Tune* tune) {
+jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, int lv,
+                        const std::vector<int>& vv, const void* parent, long long base, const void** end, Prof* prof,
+                        Tune* tune) {
   const ComponentProgram& cp = p->prog.comps[c];
   DevState& S = state_of(p);
   const DevLayout& L = S.lay;
@@ -608,8 +616,7 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
       ChainOps ops = {};
       std::vector<const StepDesc*> sdd, shd;
       for (int q = ch.first; q < ch.last; ++q) {
-        const int var = (q == lev.first && lev.site >= 0) ? v : 0;
-        ops.B[q - ch.first] = ws + L.step_b[c][q][var];
+        ops.B[q - ch.first] = ws + L.step_b[c][q][variant_index(cp, cp.steps[q], vv)];
         sdd.push_back(reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][q]));
         shd.push_back(reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][q]]));
       }
@@ -659,13 +666,14 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
     }
     void* dst;
     if (st.final_step) {
-      dst = out + size_t(base) * 16;
+      // with sliced wires the leaf's partial result goes to the leaf buffer and is added in below
+      dst = cp.accumulate ? static_cast<void*>(ws + L.leaf_off[c]) : static_cast<void*>(out + size_t(base) * 16);
     } else if (st.inplace_ok && st.in_prec == st.out_prec && (cur == b0 || cur == b1)) {
       dst = const_cast<void*>(cur);
     } else {
       dst = (cur == b0) ? b1 : b0;
     }
-    const int var = (si == lev.first && lev.site >= 0) ? v : 0;
+    const size_t var = variant_index(cp, st, vv);
     const StepDesc* dd = reinterpret_cast<const StepDesc*>(ws + L.step_desc[c][si]);
     const StepDesc* hd = reinterpret_cast<const StepDesc*>(&S.host_image[L.step_desc[c][si]]);
     const void* B = ws + L.step_b[c][si][var];
@@ -700,6 +708,8 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
     } else {
       JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));
     }
+    if (st.final_step && cp.accumulate)
+      JF_HIP(launch_accumulate(out + size_t(base) * 16, dst, cp.leaf_len, stream));
     cur = dst;
   }
   *end = cur;
@@ -718,6 +728,7 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, s
     const void* parent;
     long long base;
   };
+  std::vector<int> vv(cp.levels.size(), 0);  // the values of the levels on the current path
   std::vector<Frame> stack;
   stack.push_back({0, 0, nullptr, 0});
   while (!stack.empty()) {
@@ -725,9 +736,10 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, s
     stack.pop_back();
     const Level& lev = cp.levels[f.lv];
     if (f.v + 1 < lev.nvar) stack.push_back({f.lv, f.v + 1, f.parent, f.base});
+    vv[f.lv] = f.v;
     const long long base = f.base + f.v * lev.out_stride;
     const void* cur = nullptr;
-    jf_status st = enqueue_level(p, ws, stream, c, f.lv, f.v, f.parent, base, &cur, prof, tune);
+    jf_status st = enqueue_level(p, ws, stream, c, f.lv, vv, f.parent, base, &cur, prof, tune);
     if (st != JF_OK) return st;
     if (f.lv + 1 < (int)cp.levels.size()) stack.push_back({f.lv + 1, 0, cur, base});
   }
@@ -1140,7 +1152,9 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
   };
   int last = -1;
   long long most = 1;
-  if (P.opt.alg == 1)
+  bool wires = false;  // a leaf of a component with sliced wires holds partial sums, not terms
+  for (const ComponentProgram& cp : P.comps) wires = wires || cp.accumulate;
+  if (P.opt.alg == 1 && !wires)
     for (size_t c = 0; c < P.comps.size(); ++c)
       if (!P.comps[c].lds_resident && P.comps[c].leaves > most) {
         most = P.comps[c].leaves;
@@ -1213,7 +1227,7 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
     while (true) {
       for (int lv = from; lv < nl; ++lv) {
         base[lv] = (lv ? base[lv - 1] : 0) + v[lv] * cp.levels[lv].out_stride;
-        st = enqueue_level(p, w, stream, size_t(last), lv, v[lv], lv ? end[lv - 1] : nullptr, base[lv], &end[lv],
+        st = enqueue_level(p, w, stream, size_t(last), lv, v, lv ? end[lv - 1] : nullptr, base[lv], &end[lv],
                            nullptr, nullptr);
         if (st != JF_OK) return st;
       }

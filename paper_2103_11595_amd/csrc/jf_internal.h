@@ -103,7 +103,11 @@ struct Step {
   std::vector<int> hiA, hiC;     // bit positions in A / C of the tile-index bits (LSB first)
   bool inplace_ok = false;       // C layout == A layout (can run in place)
   int in_prec = P_C128, out_prec = P_C128, compute = C_F64;
-  int nvar = 1;                  // >1: first step of a sliced level, B per Kraus variant
+  // Variants of the operator: one per combination of the values of the levels in var_levels
+  // (ascending; mixed radix, the first level lowest) -- the levels whose sliced index (a Kraus
+  // site's operator, a wire's value) this block carries.  nvar = B.size().
+  int nvar = 1;
+  std::vector<int> var_levels;
   std::vector<std::vector<cd>> B; // per variant: K x Nn row-major ([s][n])
   bool final_step = false;       // writes the component output (strided into the out array)
   bool two_term = false;         // FP32 steps: operator stored as an FP32 pair (hi + lo)
@@ -145,8 +149,9 @@ struct ChainTables {
 
 struct Level {
   int first = 0, last = 0;       // steps [first, last)
-  int site = -1;                 // sliced site starting this level (-1 for level 0)
-  int nvar = 1;                  // Kraus operators iterated at this level
+  int site = -1;                 // sliced Kraus site iterated at this level (-1: none)
+  int wire = -1;                 // sliced wire leg iterated at this level (network leg id; -1: none)
+  int nvar = 1;                  // values iterated at this level (Kraus operators, or 2 for a wire)
   long long out_stride = 0;      // output offset per variant of this level's site
   int max_log2 = 0;              // largest tensor of the segment
   size_t buf_bytes = 0;          // bytes of each of the level's two buffers
@@ -161,6 +166,10 @@ struct ComponentProgram {
   // step's own layout, so its writes are as contiguous as its reads.
   std::vector<std::vector<int>> out_bit;
   long long out_len = 1;         // complex entries of the component output
+  // sliced wires: a leaf's final step writes leaf_len partial values, added into the output at the
+  // leaf's Kraus-site offset (the sum over the wires' values is the trace)
+  bool accumulate = false;
+  long long leaf_len = 0;
   long long leaves = 1;          // DFS leaves
   double flops = 0, bytes = 0;
   double est_seconds = 0;          // cost-model estimate of the device time of one run
@@ -174,6 +183,15 @@ struct ComponentProgram {
 };
 
 void chain_tables(const ComponentProgram& cp, const Chain& ch, ChainTables& out);
+// index into st.B of the variant selected by the values vv[lv] of the enclosing levels
+inline size_t variant_index(const ComponentProgram& cp, const Step& st, const std::vector<int>& vv) {
+  size_t idx = 0, stride = 1;
+  for (int lv : st.var_levels) {
+    idx += stride * size_t(vv[lv]);
+    stride *= size_t(cp.levels[lv].nvar);
+  }
+  return idx;
+}
 // positions of a step's contracted bits in A (offS_A is their scatter), in its s-bit order
 std::vector<int> step_s_positions(const Step& st);
 // in-place complex64 step with a single-term FP32 operator of at most 32 x 32
@@ -203,6 +221,7 @@ struct Program {
   std::vector<std::vector<double>> site_norm2;  // squared operator norm of every Kraus operator
   long long kraus_terms = 1;
   int n_before_cancel = 0, n_after_cancel = 0, empty_loops = 0, n_swaps_rewired = 0;
+  int n_sliced_wires = 0;
   double planner_seconds = 0;
   double flops = 0, bytes = 0;
   double est_seconds = 0;          // cost-model estimate of the device time of one run

@@ -148,6 +148,8 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
+// out[i] += part[i] for i < n (double2 entries): a leaf's partial result of sliced wires
+hipError_t launch_accumulate(void* out, const void* part, long long n_double2, hipStream_t stream);
 
 // sums[0..1] = double-double sum_i |x_i|^2 (TwoSum, fixed partition and reduction trees);
 // sums[2..3] = x_0 (re, im).  scratch: 2 SUMSQ_BLOCKS doubles of device memory for the partial

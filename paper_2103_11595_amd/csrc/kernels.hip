@@ -1606,6 +1606,21 @@ hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* s
   return hipGetLastError();
 }
 
+__global__ void k_accumulate(double2* out, const double2* part, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double2 a = out[i], b = part[i];
+    out[i] = make_double2(a.x + b.x, a.y + b.y);
+  }
+}
+
+hipError_t launch_accumulate(void* out, const void* part, long long n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_accumulate, dim3(unsigned(blocks)), dim3(256), 0, stream, (double2*)out, (const double2*)part, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void* out, long long n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   long long blocks = (n + 255) / 256;

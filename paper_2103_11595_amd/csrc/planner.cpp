@@ -29,6 +29,8 @@
 
 namespace jf {
 static constexpr int kMaxOutLog2 = 34;
+// at most 2^24 depth-first leaves from sliced wire legs per component
+static constexpr int kMaxWireSlices = 24;
 
 namespace {
 
@@ -76,6 +78,8 @@ struct Path {
   double cost = 0;          // sum of 2^uni: the unfused work, used to guide the greedy search
   double est = 0;           // cost-model time of the fused, sliced program (ranks the restarts)
   int maxw = 0;
+  int bw = 0;               // widest intermediate with every Kraus-index leg removed
+  int tier = 2;             // 0 Kraus slicing suffices, 1 wire slices too, 2 neither (see evaluate)
 };
 
 Path greedy(const LocalNet& L, int start, std::mt19937_64& rng, double temp) {
@@ -434,14 +438,91 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     for (int si : comp_sites)
       for (size_t b = 0; b < net.site_var_legs[si].size(); ++b) open_of[net.site_var_legs[si][b]] = {si, int(b)};
 
+    // ---- slicing: the indices a path slices to fit the cap.  Kraus sites first (the earliest slot
+    // at or before the widest position: a sliced site iterates its Kraus operators depth first and
+    // every step before its slot is computed once for all of them), then ordinary wire legs alive at
+    // the widest position (a sliced wire is fixed to each of its two values in turn and the leaves'
+    // partial results add up): the one that covers the most positions still over the cap, ties to
+    // the later start (a longer shared prefix), then the lower leg id.  False when that would take
+    // more than kMaxWireSlices wire slices.
+    struct Slices {
+      std::vector<char> site;   // sliced Kraus sites (by site index)
+      std::vector<int> wires;   // sliced wire legs (local ids), in the order chosen
+      std::vector<int> cut;     // per path position: sliced bits alive there
+    };
+    auto positions = [&](const Path& p) {
+      std::vector<int> pos(N);
+      for (int k = 0; k < N; ++k) pos[p.order[k]] = k;
+      return pos;
+    };
+    auto wire_span = [&](const std::vector<int>& pos, int l) {  // positions [a, b) where wire l is in T
+      const int x = pos[L.leg_tensors[l][0]], y = pos[L.leg_tensors[l][1]];
+      return std::make_pair(std::min(x, y), std::max(x, y));
+    };
+    auto decide_slices = [&](const Path& p, Slices& S) -> bool {
+      const std::vector<int> pos = positions(p);
+      S.site.assign(c.sites.size(), 0);
+      S.wires.clear();
+      S.cut.assign(N, 0);
+      std::vector<int> slot(c.sites.size(), N);
+      for (int k = 0; k < N; ++k) {
+        const Tensor* t = L.ts[p.order[k]];
+        if (opt.alg == 1 && t->site >= 0) slot[t->site] = k;
+      }
+      auto slice_site = [&](int si) {
+        S.site[si] = 1;
+        for (int k = slot[si]; k < N; ++k) S.cut[k] += int(net.site_var_legs[si].size());
+      };
+      if (opt.flags & JF_FLAG_NO_BATCH)
+        for (int si : comp_sites)
+          if (!net.site_var_legs[si].empty()) slice_site(si);
+      std::vector<char> wcut(L.nl, 0);
+      while (true) {
+        int worst = -1, ww = -1;
+        for (int k = 0; k < N; ++k)
+          if (p.width[k] - S.cut[k] > ww) {
+            ww = p.width[k] - S.cut[k];
+            worst = k;
+          }
+        if (ww <= opt.cap_log2) return true;
+        int pickc = -1;
+        for (int si : comp_sites)
+          if (!S.site[si] && !net.site_var_legs[si].empty() && slot[si] <= worst &&
+              (pickc < 0 || slot[si] < slot[pickc]))
+            pickc = si;
+        if (pickc >= 0) {
+          slice_site(pickc);
+          continue;
+        }
+        if ((int)S.wires.size() >= kMaxWireSlices) return false;
+        int pick = -1, pick_cover = -1, pick_start = -1;
+        for (int l = 0; l < L.nl; ++l) {
+          if (L.open[l] || wcut[l] || L.leg_tensors[l].size() != 2) continue;
+          const auto ab = wire_span(pos, l);
+          if (!(ab.first <= worst && worst < ab.second)) continue;
+          int cover = 0;
+          for (int k = ab.first; k < ab.second; ++k) cover += p.width[k] - S.cut[k] > opt.cap_log2;
+          if (cover > pick_cover || (cover == pick_cover && ab.first > pick_start)) {
+            pick = l;
+            pick_cover = cover;
+            pick_start = ab.first;
+          }
+        }
+        if (pick < 0) return false;
+        wcut[pick] = 1;
+        S.wires.push_back(pick);
+        const auto ab = wire_span(pos, pick);
+        for (int k = ab.first; k < ab.second; ++k) S.cut[k] += 1;
+      }
+    };
+
     // ---- greedy path search with restarts
-    // A path is feasible when slicing every Kraus index brings it under the cap; among the
-    // feasible paths the one whose fused, sliced program the cost model prices lowest wins
-    // (ties: the smaller unfused work).
+    // Paths rank in tiers: those that slicing Kraus indices alone brings under the cap, then those
+    // that also need wire slices, then the rest (narrower first); within the first two tiers the
+    // cost-model time of the fused, sliced program decides (ties: the smaller unfused work).
     Path best;
     best.cost = 1e300;
     bool have = false;
-    int best_base = 1 << 30, min_base_seen = 1 << 30;
     auto base_width = [&](const Path& p) {
       int open = 0, w = 0;
       for (size_t k = 0; k < p.order.size(); ++k) {
@@ -453,45 +534,34 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // Cost-model time of the program a path lowers to: the slicing, precision switch and block
     // fusion below, decided on leg sets only (no tensor data), each step priced like the real
     // lowering prices it.  Used only to rank candidate paths; the lowering itself decides again.
-    // Legs are the component's local ids; per tensor, its legs with and without Kraus-index legs.
-    std::vector<std::vector<int>> legs_novar(N);
-    for (int i = 0; i < N; ++i) {
-      const Tensor* t = L.ts[i];
-      for (size_t j = 0; j < t->legs.size(); ++j)
-        if (std::find(t->var_legs.begin(), t->var_legs.end(), t->legs[j]) == t->var_legs.end())
-          legs_novar[i].push_back(L.legs[i][j]);
-    }
+    // Legs are the component's local ids.
     auto fused_estimate = [&](const Path& p) -> double {
-      std::vector<int> sstep(c.sites.size(), -1);
+      Slices S;
+      if (!decide_slices(p, S)) return 1e300;
+      const std::vector<int> pos = positions(p);
+      // legs the slicing removes, and the levels' starts (the factor each multiplies the work by)
+      std::vector<char> gone(L.nl, 0);
+      std::vector<double> head_mult(N, 1.0);
+      for (int l : S.wires) {
+        gone[l] = 1;
+        head_mult[wire_span(pos, l).first] *= 2;
+      }
+      int sliced_bits = 0;
       for (int k = 0; k < N; ++k) {
         const Tensor* t = L.ts[p.order[k]];
-        if (opt.alg == 1 && t->site >= 0) sstep[t->site] = k;
-      }
-      std::vector<char> sl(c.sites.size(), 0);
-      std::vector<int> drop(N + 1, 0);  // Kraus legs of sliced sites leaving the width from step k on
-      auto effw = [&](int k) {
-        int w = p.width[k];
-        for (int si : comp_sites)
-          if (sl[si] && sstep[si] <= k) w -= int(net.site_var_legs[si].size());
-        return w;
-      };
-      if (opt.flags & JF_FLAG_NO_BATCH)
-        for (int si : comp_sites)
-          if (!net.site_var_legs[si].empty()) sl[si] = 1;
-      while (true) {
-        int worst = -1, ww = -1;
-        for (int k = 0; k < N; ++k) {
-          const int w = effw(k);
-          if (w > ww) { ww = w; worst = k; }
+        if (opt.alg == 1 && t->site >= 0 && S.site[t->site]) {
+          head_mult[k] *= net.site_nk[t->site];
+          sliced_bits += int(net.site_var_legs[t->site].size());
+          for (size_t j = 0; j < t->legs.size(); ++j)
+            if (std::find(t->var_legs.begin(), t->var_legs.end(), t->legs[j]) != t->var_legs.end())
+              gone[L.legs[p.order[k]][j]] = 1;
         }
-        if (ww <= opt.cap_log2) break;
-        int pickc = -1;
-        for (int si : comp_sites)
-          if (!sl[si] && !net.site_var_legs[si].empty() && sstep[si] <= worst && (pickc < 0 || sstep[si] < sstep[pickc]))
-            pickc = si;
-        if (pickc < 0) return 1e300;
-        sl[pickc] = 1;
       }
+      std::vector<std::vector<int>> eff(N);
+      for (int i = 0; i < N; ++i)
+        for (int l : L.legs[i])
+          if (!gone[l]) eff[i].push_back(l);
+      auto effw = [&](int k) { return p.width[k] - S.cut[k]; };
       int sw = N;
       if (low) {
         sw = 0;
@@ -507,7 +577,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       int rT = 0;
       double est = 0, mult = 1;
       int in_e = low ? 8 : 16;
-      int k = 0, lvstart = 0;
+      int k = 0;
       std::vector<int> blk, trial;
       // bit positions of the intermediate's legs, laid out as the lowering lays them out, and the
       // steps of the current level as chain candidates with their cost-model times
@@ -515,24 +585,18 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       std::vector<ChainCand> seg;
       std::vector<double> segt;
       while (k < N) {
-        // a sliced slot starts a level: its Kraus operator is fixed, its Kraus legs are gone
-        const Tensor* t0 = L.ts[p.order[k]];
-        const bool level_head = opt.alg == 1 && t0->site >= 0 && sl[t0->site];
-        if (level_head) {
-          mult *= net.site_nk[t0->site];
-          lvstart = k;
-        }
+        // a sliced index starts a level: its value is fixed per leaf, its legs are gone
+        mult *= head_mult[k];
         int kend = N;
-        for (int j = k + 1; j < N; ++j) {
-          const Tensor* tj = L.ts[p.order[j]];
-          if (opt.alg == 1 && tj->site >= 0 && sl[tj->site]) { kend = j; break; }
-        }
-        (void)lvstart;
+        for (int j = k + 1; j < N; ++j)
+          if (head_mult[j] > 1) {
+            kend = j;
+            break;
+          }
         seg.clear();
         segt.clear();
         while (k < kend) {
-          const bool head = level_head && k == lvstart;
-          blk = head ? legs_novar[p.order[k]] : L.legs[p.order[k]];
+          blk = eff[p.order[k]];
           for (int l : blk) inB[l] = 1;
           const int rA = rT;
           int kS = 0;
@@ -541,7 +605,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           int e = k + 1;
           while (!(opt.flags & JF_FLAG_NO_FUSE) && e < kend) {
             if (low && e == sw) break;
-            const std::vector<int>& nx = L.legs[p.order[e]];
+            const std::vector<int>& nx = eff[p.order[e]];
             // trial = blk xor nx
             trial.clear();
             for (int l : blk)
@@ -629,21 +693,33 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           est += mult * cm.chain(seg[i].rA, fl);
         });
       }
+      // with sliced wires every leaf adds its output into the component's
+      if (!S.wires.empty()) est += mult * (cm.launch + 32.0 * std::ldexp(1.0, cp.n_open_bits - sliced_bits) / cm.bw);
       return est;
     };
-    auto consider = [&](const Path& p) {
-      int bw = base_width(p);
-      min_base_seen = std::min(min_base_seen, bw);
-      bool feas = bw <= opt.cap_log2;
-      bool best_feas = best_base <= opt.cap_log2;
-      bool better;
-      if (!have) better = true;
-      else if (feas != best_feas) better = feas;
-      else if (!feas) better = bw < best_base;
-      else better = p.est < best.est * (1 - 1e-12) || (p.est <= best.est * (1 + 1e-12) && p.cost < best.cost);
-      if (better) {
+    // tier 0: Kraus slicing suffices; 1: wire slices too; 2: beyond kMaxWireSlices.  A path that
+    // cannot beat the best seen (tier 1 against a tier 0) skips the estimate.
+    auto evaluate = [&](Path& p, bool tier0_seen) {
+      p.bw = base_width(p);
+      if (p.bw <= opt.cap_log2) {
+        p.tier = 0;
+        p.est = fused_estimate(p);
+      } else if (tier0_seen) {
+        p.tier = 1;
+        p.est = 1e300;
+      } else {
+        p.est = fused_estimate(p);
+        p.tier = p.est < 1e300 ? 1 : 2;
+      }
+    };
+    auto better_path = [&](const Path& a, const Path& b) {
+      if (a.tier != b.tier) return a.tier < b.tier;
+      if (a.tier == 2) return a.bw < b.bw;
+      return a.est < b.est * (1 - 1e-12) || (a.est <= b.est * (1 + 1e-12) && a.cost < b.cost);
+    };
+    auto consider = [&](Path& p) {
+      if (!have || better_path(p, best)) {
         best = p;
-        best_base = bw;
         have = true;
       }
     };
@@ -658,13 +734,13 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       for (int i = 0; i < N; ++i) starts.push_back(i);
     for (int s : starts) {
       Path p = greedy(L, s, rng, 0.0);
-      if (base_width(p) <= opt.cap_log2) p.est = fused_estimate(p);
+      evaluate(p, have && best.tier == 0);
       consider(p);
     }
     // The default search is also sized to the stakes: when the deterministic starts already give a
     // program estimated under 200 us of device time, seconds of host search could save only
     // microseconds, so it takes 512 restarts (an explicit effort is kept as given).
-    const int tries_total = (opt.restarts <= 0 && N > 24 && have && best_base <= opt.cap_log2 && best.est < 2e-4)
+    const int tries_total = (opt.restarts <= 0 && N > 24 && have && best.tier == 0 && best.est < 2e-4)
                                 ? std::min(restarts_total, 512)
                                 : restarts_total;
     {
@@ -680,23 +756,15 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         std::uniform_int_distribution<int> pick(0, N - 1);
         const int mine = tries_total / workers + (w < tries_total % workers ? 1 : 0);
         Path bestw;
-        int bw_base = 1 << 30;
         bool hv = false;
         for (int tries = 0; tries < mine; ++tries) {
           double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
           if (el > opt.time_budget_s && tries >= 8) break;
           int s = (tries % 2 == 0 && !starts.empty()) ? starts[(tries / 2 + w) % starts.size()] : pick(wr);
           Path p = greedy(L, s, wr, 0.5 + ((tries + w) % 5) * 0.5);
-          int bw = base_width(p);
-          bool feas = bw <= opt.cap_log2, bfeas = bw_base <= opt.cap_log2;
-          if (feas) p.est = fused_estimate(p);
-          bool better = !hv || (feas != bfeas ? feas
-                                              : (!feas ? bw < bw_base
-                                                       : (p.est < bestw.est * (1 - 1e-12) ||
-                                                          (p.est <= bestw.est * (1 + 1e-12) && p.cost < bestw.cost))));
-          if (better) {
+          evaluate(p, hv && bestw.tier == 0);
+          if (!hv || better_path(p, bestw)) {
             bestw = std::move(p);
-            bw_base = bw;
             hv = true;
           }
         }
@@ -715,7 +783,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
     // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
     // Part of a thorough search only (>= 2^12 restarts): its sweeps cost O(tensors^2).
-    if (have && best_base <= opt.cap_log2 && (tries_total >= 4096 || N <= 24)) {
+    if (have && best.tier <= 1 && (tries_total >= 4096 || N <= 24)) {
       auto recompute = [&](Path& p) {
         std::vector<char> inT(L.nl, 0);
         int width = 0;
@@ -748,9 +816,9 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
             q.order.erase(q.order.begin() + i);
             q.order.insert(q.order.begin() + j, v);
             recompute(q);
-            if (base_width(q) > opt.cap_log2) continue;
-            q.est = fused_estimate(q);
-            if (q.est < best.est * (1 - 1e-9)) {
+            if (best.tier == 0 && base_width(q) > opt.cap_log2) continue;
+            evaluate(q, best.tier == 0);
+            if (q.tier < best.tier || (q.tier == best.tier && q.est < best.est * (1 - 1e-9))) {
               best = std::move(q);
               improved = true;
             }
@@ -758,40 +826,19 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
     }
 
-    // ---- slicing of Kraus indices
+    // ---- slicing of the chosen path
     const Path& pth = best;
-    std::vector<int> site_step(c.sites.size(), -1);   // path position of each site's slot
-    for (int k = 0; k < N; ++k) {
-      const Tensor* t = L.ts[pth.order[k]];
-      if (opt.alg == 1 && t->site >= 0) site_step[t->site] = k;
+    Slices SL;
+    if (!have || !decide_slices(pth, SL)) {
+      int ww = 0;
+      for (int k = 0; k < N; ++k) ww = std::max(ww, pth.width[k]);
+      set_error("no contraction order fits 2^" + std::to_string(opt.cap_log2) + " elements (needs 2^" +
+                std::to_string(ww) + " with its Kraus indices open; slicing would take more than " +
+                std::to_string(kMaxWireSlices) + " wire legs)");
+      throw jf_status(JF_E_TOO_LARGE);
     }
-    std::vector<char> sliced(c.sites.size(), 0);
-    auto eff_width = [&](int k) {
-      int w = pth.width[k];
-      for (int si : comp_sites)
-        if (sliced[si] && site_step[si] <= k) w -= int(net.site_var_legs[si].size());
-      return w;
-    };
-    if (opt.flags & JF_FLAG_NO_BATCH)
-      for (int si : comp_sites)
-        if (!net.site_var_legs[si].empty()) sliced[si] = 1;
-    while (true) {
-      int worst = -1, ww = -1;
-      for (int k = 0; k < N; ++k)
-        if (eff_width(k) > ww) { ww = eff_width(k); worst = k; }
-      if (ww <= opt.cap_log2) break;
-      int pickc = -1;
-      for (int si : comp_sites)
-        if (!sliced[si] && !net.site_var_legs[si].empty() && site_step[si] <= worst &&
-            (pickc < 0 || site_step[si] < site_step[pickc]))
-          pickc = si;
-      if (pickc < 0) {
-        set_error("no contraction order fits 2^" + std::to_string(opt.cap_log2) + " elements (needs 2^" +
-                  std::to_string(ww) + ")");
-        throw jf_status(JF_E_TOO_LARGE);
-      }
-      sliced[pickc] = 1;
-    }
+    const std::vector<int> pth_pos = positions(pth);
+    auto eff_width = [&](int k) { return pth.width[k] - SL.cut[k]; };
 
     // ---- block fusion and lowering
     // Current intermediate: legs (global ids) with bit positions.
@@ -808,19 +855,44 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
       cur_prec = P_C64;
     }
-    // levels: split the path at sliced slots
-    std::vector<int> level_start = {0};
-    std::vector<int> level_site = {-1};
+    // levels: one per sliced index, in path order of where it starts (a sliced site at its slot, a
+    // sliced wire at its first tensor); a level 0 without one when none starts at position 0, and
+    // empty levels where several start at one position
+    struct SliceStart {
+      int start, site, wire;  // wire: global leg id
+    };
+    std::vector<SliceStart> sis;
     for (int k = 0; k < N; ++k) {
       const Tensor* t = L.ts[pth.order[k]];
-      if (opt.alg == 1 && t->site >= 0 && sliced[t->site] && k > 0) {
-        level_start.push_back(k);
-        level_site.push_back(t->site);
-      } else if (opt.alg == 1 && t->site >= 0 && sliced[t->site] && k == 0) {
-        level_site[0] = t->site;  // path starts at a sliced slot: level 0 iterates it
-      }
+      if (opt.alg == 1 && t->site >= 0 && SL.site[t->site]) sis.push_back({k, t->site, -1});
+    }
+    for (int l : SL.wires) sis.push_back({wire_span(pth_pos, l).first, -1, L.glob[l]});
+    std::stable_sort(sis.begin(), sis.end(), [](const SliceStart& x, const SliceStart& y) { return x.start < y.start; });
+    std::vector<int> level_start, level_site, level_wire;
+    if (sis.empty() || sis[0].start > 0) {
+      level_start.push_back(0);
+      level_site.push_back(-1);
+      level_wire.push_back(-1);
+    }
+    for (const SliceStart& x : sis) {
+      level_start.push_back(x.start);
+      level_site.push_back(x.site);
+      level_wire.push_back(x.wire);
     }
     level_start.push_back(N);
+    const int levels_n = int(level_start.size()) - 1;
+    std::vector<int> level_nvar(levels_n, 1);
+    std::map<int, int> level_of_site, level_of_wire;
+    for (int lv = 0; lv < levels_n; ++lv) {
+      if (level_site[lv] >= 0) {
+        level_nvar[lv] = net.site_nk[level_site[lv]];
+        level_of_site[level_site[lv]] = lv;
+      }
+      if (level_wire[lv] >= 0) {
+        level_nvar[lv] = 2;
+        level_of_wire[level_wire[lv]] = lv;
+      }
+    }
     // output bits: the sliced sites take the top ones (last level lowest, one run per site, so a
     // variant's offset is v << run start); the open sites' bits are placed by the final step
     {
@@ -836,21 +908,57 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
     }
 
-    auto restrict_variant = [&](const Tensor& t, int v) {
-      // fix the Kraus-index legs of a slot tensor to operator v
+    // The levels whose sliced index a tensor carries (ascending): a sliced site's slot, the two
+    // tensors a sliced wire joins.  A block's operator has one variant per combination of their
+    // values, indexed mixed-radix with the first level lowest.
+    auto deps_of = [&](const Tensor& t) {
+      std::vector<int> D;
+      if (opt.alg == 1 && t.site >= 0 && level_of_site.count(t.site)) D.push_back(level_of_site[t.site]);
+      for (int g : t.legs) {
+        auto it = level_of_wire.find(g);
+        if (it != level_of_wire.end()) D.push_back(it->second);
+      }
+      std::sort(D.begin(), D.end());
+      return D;
+    };
+    auto n_variants = [&](const std::vector<int>& D) {
+      long long n = 1;
+      for (int lv : D) n *= level_nvar[lv];
+      return n;
+    };
+    // the values of the levels D in variant idx (mixed radix over D, first lowest)
+    auto values_of = [&](const std::vector<int>& D, long long idx) {
+      std::vector<int> v(D.size());
+      for (size_t i = 0; i < D.size(); ++i) {
+        v[i] = int(idx % level_nvar[D[i]]);
+        idx /= level_nvar[D[i]];
+      }
+      return v;
+    };
+    // t with the legs of the sliced indices of levels D fixed to the values v (a site's Kraus-index
+    // legs to the bits of its operator number, a wire to its value)
+    auto restrict_to = [&](const Tensor& t, const std::vector<int>& D, const std::vector<int>& v) {
+      std::map<int, int> fix;  // leg -> bit
+      for (size_t i = 0; i < D.size(); ++i) {
+        const int lv = D[i];
+        if (level_site[lv] >= 0) {
+          const std::vector<int>& vl = net.site_var_legs[level_site[lv]];
+          for (size_t b = 0; b < vl.size(); ++b) fix[vl[b]] = (v[i] >> b) & 1;
+        } else {
+          fix[level_wire[lv]] = v[i];
+        }
+      }
       Tensor u;
       u.site = t.site;
       std::vector<int> keep;
-      size_t idxmask = 0, idxval = 0;
+      size_t idxval = 0;
       for (size_t i = 0; i < t.legs.size(); ++i) {
-        auto it = std::find(t.var_legs.begin(), t.var_legs.end(), t.legs[i]);
-        if (it == t.var_legs.end()) {
+        auto it = fix.find(t.legs[i]);
+        if (it == fix.end()) {
           keep.push_back(int(i));
           u.legs.push_back(t.legs[i]);
         } else {
-          int b = int(it - t.var_legs.begin());
-          idxmask |= size_t(1) << i;
-          idxval |= size_t((v >> b) & 1) << i;
+          idxval |= size_t(it->second) << i;
         }
       }
       u.data.assign(size_t(1) << u.legs.size(), 0.0);
@@ -861,8 +969,13 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
       return u;
     };
+    auto all_variants = [&](const Tensor& t, const std::vector<int>& D) {
+      std::vector<Tensor> out;
+      const long long n = n_variants(D);
+      for (long long i = 0; i < n; ++i) out.push_back(D.empty() ? t : restrict_to(t, D, values_of(D, i)));
+      return out;
+    };
 
-    int levels_n = int(level_start.size()) - 1;
     std::vector<size_t> level_bytes(levels_n, 0);
     std::vector<int> level_maxw(levels_n, 0);
     double comp_flops = 0, comp_bytes = 0;
@@ -871,21 +984,17 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       Level Lv;
       Lv.first = int(cp.steps.size());
       Lv.site = level_site[lv];
-      Lv.nvar = Lv.site >= 0 ? net.site_nk[Lv.site] : 1;
+      Lv.wire = level_wire[lv];
+      Lv.nvar = level_nvar[lv];
       Lv.out_stride = (Lv.site >= 0 && !cp.out_bit[Lv.site].empty()) ? (1LL << cp.out_bit[Lv.site][0]) : 0;
       mult *= Lv.nvar;
       int k = level_start[lv];
       const int kend = level_start[lv + 1];
       while (k < kend) {
         // ---- grow a block [k, e)
-        const bool var_first = (Lv.site >= 0 && k == level_start[lv]);
         std::set<int> Tset(Tlegs.begin(), Tlegs.end());
-        std::vector<Tensor> blk;  // per variant
-        int nv = var_first ? Lv.nvar : 1;
-        for (int v = 0; v < nv; ++v) {
-          const Tensor& t0 = *L.ts[pth.order[k]];
-          blk.push_back(var_first ? restrict_variant(t0, v) : t0);
-        }
+        std::vector<int> D = deps_of(*L.ts[pth.order[k]]);
+        std::vector<Tensor> blk = all_variants(*L.ts[pth.order[k]], D);  // per variant
         auto split = [&](const Tensor& b, std::vector<int>& S, std::vector<int>& Nn) {
           S.clear();
           Nn.clear();
@@ -898,12 +1007,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         auto block_cost = [&](int kS, int kN, int ein, int eout) {
           return cm.step(rA, rA - kS + kN, kS, kN, ein, eout);
         };
-        const bool prec_switch_inside = false;
-        (void)prec_switch_inside;
         while (!(opt.flags & JF_FLAG_NO_FUSE) && e < kend) {
           // never fuse across the precision switch
           if (low && e == switch_at) break;
-          const Tensor& nx = *L.ts[pth.order[e]];
+          const Tensor& nxt = *L.ts[pth.order[e]];
+          const std::vector<int> Dx = deps_of(nxt);
+          const Tensor nx = Dx.empty() ? nxt : restrict_to(nxt, Dx, std::vector<int>(Dx.size(), 0));
           Tensor trial = contract_pair(blk[0], nx);
           std::vector<int> S2, N2;
           split(trial, S2, N2);
@@ -923,14 +1032,37 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
                        cm.step(rmid, rmid - s3 + n3, s3, n3, ein, ein);
           double fused = block_cost(int(S2.size()), int(N2.size()), ein, ein);
           if (fused > sep) break;
-          for (auto& b : blk) b = contract_pair(b, nx);
+          if (Dx.empty()) {
+            for (auto& b : blk) b = contract_pair(b, nxt);
+          } else {
+            std::vector<int> D2 = D;
+            for (int x : Dx)
+              if (!std::count(D2.begin(), D2.end(), x)) D2.push_back(x);
+            std::sort(D2.begin(), D2.end());
+            std::vector<Tensor> blk2;
+            const long long n2v = n_variants(D2);
+            for (long long i = 0; i < n2v; ++i) {
+              const std::vector<int> v2 = values_of(D2, i);
+              long long io = 0, stride = 1;  // index of the same values in blk (levels D)
+              for (int lvd : D) {
+                io += stride * v2[std::find(D2.begin(), D2.end(), lvd) - D2.begin()];
+                stride *= level_nvar[lvd];
+              }
+              std::vector<int> vx;
+              for (int lvd : Dx) vx.push_back(v2[std::find(D2.begin(), D2.end(), lvd) - D2.begin()]);
+              blk2.push_back(contract_pair(blk[size_t(io)], restrict_to(nxt, Dx, vx)));
+            }
+            blk.swap(blk2);
+            D = D2;
+          }
           S = S2;
           NN = N2;
           ++e;
         }
         // ---- lower block [k, e) to one device step
         Step st;
-        st.nvar = nv;
+        st.nvar = int(blk.size());
+        st.var_levels = D;
         st.kS = int(S.size());
         st.kN = int(NN.size());
         st.rA = rA;
@@ -1054,6 +1186,16 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       cp.levels.push_back(Lv);
     }
     cp.leaves = mult;
+    // sliced wires: every leaf's final step writes a partial result that is added into the output
+    for (auto& lv : cp.levels)
+      if (lv.wire >= 0) {
+        cp.accumulate = true;
+        ++P.n_sliced_wires;
+      }
+    if (cp.accumulate) {
+      cp.leaf_len = 1LL << cp.steps.back().rC;
+      P.est_seconds += double(cp.leaves) * (cm.launch + 32.0 * double(cp.leaf_len) / cm.bw);
+    }
     for (int si : comp_sites)
       for (int ob : cp.out_bit[si])
         if (ob < 0 || ob >= cp.n_open_bits) throw std::logic_error("Kraus bit without an output position");

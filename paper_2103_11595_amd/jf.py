@@ -68,7 +68,7 @@ class jf_plan_stats(C.Structure):
                 ("n_open_bits", C.c_int), ("n_tensors_before_cancel", C.c_int),
                 ("n_tensors_after_cancel", C.c_int), ("planner_seconds", C.c_double),
                 ("empty_loops", C.c_double), ("alg", C.c_int), ("est_seconds", C.c_double),
-                ("n_swaps_rewired", C.c_int)]
+                ("n_swaps_rewired", C.c_int), ("n_sliced_wires", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

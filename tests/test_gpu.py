@@ -328,6 +328,69 @@ def test_batch_graph_follows_its_members():
         gc.collect()
 
 
+# --- slicing of ordinary wire legs (plans under a cap below the network's width) ----------
+
+def test_wire_sliced_alg1_per_term_against_oracle():
+    # every leaf fixes the sliced wires to one combination of values; each Kraus tuple's trace is the
+    # sum of the leaves' partial traces: per-term parity in complex128, F_J in the FP32 forms
+    for n, g, m, seed, cut in [(6, 80, 2, 700, 2), (6, 80, 2, 700, 4), (5, 60, 3, 701, 2), (7, 100, 3, 702, 2)]:
+        inst = gen.random_circuit(n, g, m, 1e-3, 0.2, seed)
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        cap = int(jf.plan(inst, 1, "c128").info()["max_log2_intermediate"]) - cut
+        for dtype in ("c128", "c64", "bf16x6"):
+            p = jf.plan(inst, 1, dtype, max_log2=cap)
+            assert p.stats()["n_sliced_wires"] > 0
+            say("wire-sliced alg1", n, g, m, "cap", cap, dtype, "wires", p.stats()["n_sliced_wires"],
+                "leaves", p.info()["work_items"])
+            got = jf.jf_fidelity_alg1(p, want_terms=True)
+            assert abs(got["fj"] - ref["fj"]) <= TOL[dtype], (dtype, got["fj"] - ref["fj"])
+            if dtype == "c128":
+                assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12
+
+
+def test_wire_sliced_alg2_against_oracle():
+    # the doubled network has no Kraus legs: a cap under its width can only slice wires
+    for seed, caps in [(1, (7,)), (3, (7, 5)), (2, (4,))]:
+        inst = gen.random_circuit(5 + seed % 2, 60 + 10 * seed, 2 + seed % 2, 1e-3, 0.2, 810 + seed)
+        if seed % 2:
+            inst["noise"][0]["channel"] = "amplitude_damping"
+        want = dense.fidelity_alg2(inst)["fj"]
+        for cap in caps:
+            for dtype in ("c128", "c64"):
+                p = jf.plan(inst, 2, dtype, max_log2=cap)
+                assert p.stats()["n_sliced_wires"] > 0
+                say("wire-sliced alg2 seed", seed, "cap", cap, dtype, "leaves", p.info()["work_items"])
+                got = jf.jf_fidelity_alg2(p)
+                assert abs(got["fj"] - want) <= TOL[dtype], (seed, cap, dtype)
+                assert got["imag_residual"] <= TOL[dtype]
+
+
+def test_wire_sliced_plans_in_graphs_batches_decisions_and_noalloc():
+    import torch
+    inst = gen.random_circuit(6, 80, 2, 1e-3, 0.2, 700)
+    ref = dense.fidelity_alg1(inst)["fj"]
+    cap = int(jf.plan(inst, 1, "c128").info()["max_log2_intermediate"]) - 3
+    p = jf.plan(inst, 1, "c128", max_log2=cap, flags=jf.JF_FLAG_GRAPH)
+    q = jf.plan(gen.random_circuit(5, 70, 3, 1e-3, 0.2, 813), 2, "c128", max_log2=5)
+    assert p.stats()["n_sliced_wires"] > 0 and q.stats()["n_sliced_wires"] > 0
+    s = torch.cuda.Stream()
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    say("wire-sliced plan: graph replays")
+    vals = [jf.jf_fidelity_alg1(p, ws, s)["fj"] for _ in range(3)]
+    assert len(set(vals)) == 1 and abs(vals[0] - ref) <= 1e-12
+    say("wire-sliced plans: one batch")
+    singles = [jf.jf_fidelity_alg1(p)["fj"], jf.jf_fidelity_alg2(q)["fj"]]
+    bws = jf.workspace(jf.jf_batch_workspace([p, q]))
+    with torch.cuda.stream(s):
+        got = [r["fj"] for r in jf.jf_fidelity_batch([p, q], bws, s)]
+    torch.cuda.synchronize()
+    assert got == singles
+    say("wire-sliced plan: early decision (one pass) and the no-allocation entry point")
+    d = jf.jf_decide_equivalence(p, 1 - ref + 1e-3, ws)
+    assert d["decision"] == 1 and d["leaves_run"] == d["leaves_total"]
+    assert abs(jf.jf_fidelity_noalloc(p)["fj"] - ref) <= 1e-12
+
+
 def test_batch_then_larger_plan_on_one_workspace():
     # a batch member's tables sit at an offset inside the workspace; a larger plan run alone on the
     # same workspace writes over them, so the batch after it must upload its members again

@@ -216,6 +216,55 @@ def test_kraus_term_count_saturates():
     assert jf.plan(inst, 2, "c64").info()["kraus_terms"] == 4**31
 
 
+def _wire_sliced(inst, alg, dtype, cut):
+    """A plan capped `cut` bits under its free width, so that ordinary wire legs are sliced."""
+    free = jf.plan(inst, alg, dtype)
+    return jf.plan(inst, alg, dtype, max_log2=int(free.info()["max_log2_intermediate"]) - cut)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_wire_sliced_alg1_emulated_against_oracle(seed):
+    # wire legs fixed to 0 and 1 in turn, the leaves' partial traces added (per Kraus tuple)
+    n, g, m = [(6, 80, 2), (5, 60, 3), (7, 100, 3), (6, 100, 3)][seed]
+    inst = gen.random_circuit(n, g, m, 1e-3, 0.2, 700 + seed)
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    want = np.array([ref["terms"][k] for k in sorted(ref["terms"])])
+    wires = 0
+    for dtype in ("c128", "c64"):
+        for cut in (2, 4):
+            p = _wire_sliced(inst, 1, dtype, cut)
+            wires += p.stats()["n_sliced_wires"]
+            assert p.info()["work_items"] >= 2 ** p.stats()["n_sliced_wires"]
+            assert np.max(np.abs(p.emulate() - want)) < 1e-12, (dtype, cut)
+    assert wires > 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_wire_sliced_alg2_emulated_against_oracle(seed):
+    inst = gen.random_circuit(5 + seed % 2, 60 + 10 * seed, 2 + seed % 2, 1e-3, 0.2, 810 + seed)
+    if seed % 2:
+        inst["noise"][0]["channel"] = "amplitude_damping"
+    ref = dense.fidelity_alg2(inst)["fj"]
+    wires = 0
+    for cap in (7, 5, 4):   # the doubled network has no Kraus legs: only wires can be sliced
+        try:
+            p = jf.plan(inst, 2, "c128", max_log2=cap)
+        except jf.JfError as e:
+            assert e.status == -5
+            continue
+        wires += p.stats()["n_sliced_wires"]
+        assert abs(p.emulate()[0].real - ref) < 1e-12, cap
+    assert wires > 0
+
+
+def test_wire_slicing_has_a_limit():
+    # a doubled network capped far under its width would need more than 2^24 leaves
+    inst = gen.random_circuit(5, 60, 3, 1e-3, 0.2, 701)
+    c = jf.jf_load_circuit(inst)
+    assert _status(lambda: jf.jf_plan_contraction(c, 2, "c128", max_log2=2)) == -5
+    assert "wire legs" in jf.lib().jf_last_error().decode()
+
+
 def test_alg1_output_is_bounded_by_the_cap():
     # 30 sites of 1.5 Kraus bits each: 2^45 per-tuple values cannot be held; Algorithm II can
     inst = gen.config3()
