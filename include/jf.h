@@ -224,10 +224,14 @@ jf_status jf_fidelity_alg2(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* s
 
 /*
  * jf_fidelity_batch -- run n plans (Alg I or Alg II, any mix, one dtype per plan) as one
- * batched submission: small networks execute LDS-resident, one workgroup per slice, in a single
- * persistent launch; larger ones run their step programs back to back; the whole submission is
- * captured once into a hipGraph (cached on the first plan) and replayed.
- * out[i] receives plan i's result.  The workspace must hold jf_batch_workspace bytes.
+ * batched submission (the networks are independent, Section IV-A): small networks execute
+ * LDS-resident, one workgroup per slice, in a single persistent launch; larger ones run their
+ * step programs back to back; the whole submission is captured once into a hipGraph (cached on
+ * the first plan, keyed by the plans, the workspace and the stream) and replayed.  Each plan keeps
+ * its tables, outputs and sums in a region of its own; since the programs run one after another,
+ * their level buffers share one region sized for the largest, so the workspace is the sum of the
+ * plans' small parts plus the largest buffer set.  out[i] receives plan i's result.  The workspace
+ * must hold jf_batch_workspace bytes.
  */
 jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* workspace_bytes);
 jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* dev_ws, size_t ws_bytes,

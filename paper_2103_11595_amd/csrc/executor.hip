@@ -33,6 +33,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct DevLayout {
   size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
+  size_t image_end = 0;  // end of the host image (descriptors, operators, constants, LDS tables)
   size_t sumsq_off = 0;  // scratch of the two-pass sum of |t|^2 (2 SUMSQ_BLOCKS doubles)
   size_t lds_items_off = 0, lds_steps_off = 0;
   std::vector<size_t> leaf_off;                           // per component with sliced wires: its leaf buffer
@@ -41,7 +42,8 @@ struct DevLayout {
   std::vector<std::vector<size_t>> step_desc;             // per component, per step: descriptor offset
   std::vector<std::vector<size_t>> chain_desc;            // per component, per chain: descriptor offset
   std::vector<std::vector<std::vector<size_t>>> step_b;   // per component, step, variant: B offset
-  std::vector<std::vector<size_t>> level_buf;             // per component: 2 buffers per level
+  std::vector<std::vector<size_t>> level_buf;             // per component: 2 buffers per level, offsets in
+                                                          // the buffer region [buf_off, total)
 };
 
 struct DevState {
@@ -285,24 +287,7 @@ void build_layout(const Program& P, DevState& S) {
   off += align256(L.lds_comps.size() * sizeof(LdsItem));
   L.lds_steps_off = off;
   off += align256(size_t(L.lds_steps) * sizeof(LdsStep));
-  L.buf_off = off;
-  size_t maxbuf = 0;
-  L.level_buf.resize(P.comps.size());
-  for (size_t c = 0; c < P.comps.size(); ++c) {
-    size_t o = 0;
-    if (P.comps[c].lds_resident) {
-      L.level_buf[c].assign(2 * P.comps[c].levels.size(), L.buf_off);
-      continue;
-    }
-    for (auto& lv : P.comps[c].levels) {
-      L.level_buf[c].push_back(L.buf_off + o);
-      o += align256(lv.buf_bytes);
-      L.level_buf[c].push_back(L.buf_off + o);
-      o += align256(lv.buf_bytes);
-    }
-    maxbuf = std::max(maxbuf, o);
-  }
-  off += maxbuf;
+  L.image_end = off;
   L.out_off = off;
   long long outn = 0;
   for (auto& cp : P.comps) outn += cp.out_len;
@@ -317,10 +302,29 @@ void build_layout(const Program& P, DevState& S) {
   off += align256(P.comps.size() * 4 * sizeof(double));
   L.sumsq_off = off;
   off += align256(2 * SUMSQ_BLOCKS * sizeof(double));
-  L.total = off;
+  // the level buffers last: the members of a batch, which run one after another on one stream,
+  // share one buffer region (jf_fidelity_batch)
+  L.buf_off = off;
+  size_t maxbuf = 0;
+  L.level_buf.resize(P.comps.size());
+  for (size_t c = 0; c < P.comps.size(); ++c) {
+    size_t o = 0;
+    if (P.comps[c].lds_resident) {
+      L.level_buf[c].assign(2 * P.comps[c].levels.size(), 0);
+      continue;
+    }
+    for (auto& lv : P.comps[c].levels) {
+      L.level_buf[c].push_back(o);
+      o += align256(lv.buf_bytes);
+      L.level_buf[c].push_back(o);
+      o += align256(lv.buf_bytes);
+    }
+    maxbuf = std::max(maxbuf, o);
+  }
+  L.total = off + maxbuf;
 
   // host image of descriptors, pools and constants
-  S.host_image.assign(L.buf_off, 0);
+  S.host_image.assign(L.image_end, 0);
   for (size_t c = 0; c < P.comps.size(); ++c)
     for (size_t s = 0; s < P.comps[c].steps.size(); ++s) {
       const Step& st = P.comps[c].steps[s];
@@ -592,7 +596,7 @@ jf_status tune_chain(DevState& S, size_t c, int q, const ChainDesc* dd, const Ch
 // Enqueue the steps of level lv of component c for Kraus variant v of the level's sliced site,
 // starting from `parent` (nullptr: the constant 1 of the first step's precision), the component's
 // output at element offset `base`; *end receives the level's last output (no synchronisation).
-jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, int lv,
+jf_status enqueue_level(jf_plan* p, unsigned char* ws, unsigned char* bufs, hipStream_t stream, size_t c, int lv,
                         const std::vector<int>& vv, const void* parent, long long base, const void** end, Prof* prof,
                         Tune* tune) {
   const ComponentProgram& cp = p->prog.comps[c];
@@ -605,8 +609,8 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
     const Step& s0 = cp.steps[lev.first < lev.last ? lev.first : 0];
     cur = ws + L.const_off + (s0.in_prec == P_C64 ? 16 : 0);
   }
-  unsigned char* b0 = ws + L.level_buf[c][2 * lv];
-  unsigned char* b1 = ws + L.level_buf[c][2 * lv + 1];
+  unsigned char* b0 = bufs + L.level_buf[c][2 * lv];
+  unsigned char* b1 = bufs + L.level_buf[c][2 * lv + 1];
   for (int si = lev.first; si < lev.last; ++si) {
     const Step& st = cp.steps[si];
     if (st.chain >= 0 && cp.chains[st.chain].first == si && (tune || !S.chain_off[c][st.chain])) {
@@ -718,7 +722,8 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, hipStream_t stream, size_
 
 // Clear component c's output and walk its levels depth first: every prefix is computed once and
 // kept in its level buffer while the Kraus operators of the next sliced site are iterated.
-jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, size_t c, Prof* prof, Tune* tune) {
+jf_status enqueue_component(jf_plan* p, unsigned char* ws, unsigned char* bufs, hipStream_t stream, size_t c, Prof* prof,
+                            Tune* tune) {
   const ComponentProgram& cp = p->prog.comps[c];
   const DevLayout& L = state_of(p).lay;
   JF_HIP(launch_zero(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len, stream));
@@ -739,7 +744,7 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, s
     vv[f.lv] = f.v;
     const long long base = f.base + f.v * lev.out_stride;
     const void* cur = nullptr;
-    jf_status st = enqueue_level(p, ws, stream, c, f.lv, vv, f.parent, base, &cur, prof, tune);
+    jf_status st = enqueue_level(p, ws, bufs, stream, c, f.lv, vv, f.parent, base, &cur, prof, tune);
     if (st != JF_OK) return st;
     if (f.lv + 1 < (int)cp.levels.size()) stack.push_back({f.lv + 1, 0, cur, base});
   }
@@ -747,17 +752,19 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, hipStream_t stream, s
 }
 
 // Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
+// bufs: the level-buffer region (nullptr: the plan's own, at the end of its workspace).
 jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
-                          bool skip_lds = false, Tune* tune = nullptr) {
+                          bool skip_lds = false, Tune* tune = nullptr, unsigned char* bufs = nullptr) {
   const Program& P = p->prog;
   const DevLayout& L = state_of(p).lay;
+  if (!bufs) bufs = ws + L.buf_off;
   if (!skip_lds && !L.lds_comps.empty())
     JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off), int(L.lds_comps.size()),
                              reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), stream));
   for (size_t c = 0; c < P.comps.size(); ++c) {
     const ComponentProgram& cp = P.comps[c];
     if (cp.lds_resident) continue;
-    jf_status st = enqueue_component(p, ws, stream, c, prof, tune);
+    jf_status st = enqueue_component(p, ws, bufs, stream, c, prof, tune);
     if (st != JF_OK) return st;
     JF_HIP(launch_sumsq(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
                         reinterpret_cast<double*>(ws + L.sums_off) + 4 * c,
@@ -766,8 +773,11 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
   return JF_OK;
 }
 
-jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
+// Copy the plan's tables into ws (unless they are there already).  region: the bytes from ws on
+// that the plan's runs write (0: its whole workspace); every other upload in it is forgotten.
+jf_status upload(jf_plan* p, void* ws, hipStream_t stream, size_t region = 0) {
   DevState& S = state_of(p);
+  if (!region) region = S.lay.total;
   std::lock_guard<std::mutex> g(g_upload_mu);
   if (S.uploaded_to == ws) {
     auto it = g_last_upload.find(ws);
@@ -780,8 +790,8 @@ jf_status upload(jf_plan* p, void* ws, hipStream_t stream) {
   JF_HIP(hipStreamSynchronize(stream));
   S.uploaded_to = ws;
   const auto a = reinterpret_cast<uintptr_t>(ws);
-  forget_uploads(a, a + S.lay.total);
-  g_last_upload[ws] = Upload{p, S.lay.total};
+  forget_uploads(a, a + region);
+  g_last_upload[ws] = Upload{p, region};
   return JF_OK;
 }
 
@@ -1177,7 +1187,7 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
     for (size_t c = 0; c < P.comps.size(); ++c) {
       const ComponentProgram& cp = P.comps[c];
       if (cp.lds_resident || int(c) == last) continue;
-      st = enqueue_component(p, w, stream, c, nullptr, nullptr);
+      st = enqueue_component(p, w, w + L.buf_off, stream, c, nullptr, nullptr);
       if (st != JF_OK) return st;
       JF_HIP(launch_sumsq(w + L.out_off + size_t(cp.out_off) * 16, cp.out_len,
                           reinterpret_cast<double*>(w + L.sums_off) + 4 * c,
@@ -1227,7 +1237,7 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
     while (true) {
       for (int lv = from; lv < nl; ++lv) {
         base[lv] = (lv ? base[lv - 1] : 0) + v[lv] * cp.levels[lv].out_stride;
-        st = enqueue_level(p, w, stream, size_t(last), lv, v, lv ? end[lv - 1] : nullptr, base[lv], &end[lv],
+        st = enqueue_level(p, w, w + L.buf_off, stream, size_t(last), lv, v, lv ? end[lv - 1] : nullptr, base[lv], &end[lv],
                            nullptr, nullptr);
         if (st != JF_OK) return st;
       }
@@ -1276,27 +1286,49 @@ extern "C" jf_status jf_fidelity_alg2(jf_plan* p, void* ws, size_t ws_bytes, voi
   return run_one(p, ws, ws_bytes, static_cast<hipStream_t>(stream), out, nullptr);
 }
 
-// A batch shares one workspace: plans run back to back, each in its own region.
+// A batch shares one workspace: each plan keeps its tables, outputs and sums in a region of its
+// own, and since the plans run one after another on one stream, their level buffers share one
+// region sized for the largest; the persistent kernel's item and step tables follow.
+namespace jf {
+namespace {
+struct BatchLayout {
+  std::vector<size_t> base;  // each plan's region
+  size_t bufs = 0, items = 0, steps = 0, total = 0;
+};
+BatchLayout batch_layout(jf_plan* const* plans, int n) {
+  BatchLayout b;
+  size_t off = 0, maxbuf = 0, items = 0, steps = 0;
+  for (int i = 0; i < n; ++i) {
+    const DevLayout& L = state_of(plans[i]).lay;
+    b.base.push_back(off);
+    off += align256(L.buf_off);
+    maxbuf = std::max(maxbuf, L.total - L.buf_off);
+    items += L.lds_comps.size();
+    steps += L.lds_steps;
+  }
+  b.bufs = off;
+  off += align256(maxbuf);
+  b.items = off;
+  off += align256(items * sizeof(LdsItem));
+  b.steps = off;
+  off += align256(steps * sizeof(LdsStep));
+  b.total = off;
+  return b;
+}
+}  // namespace
+}  // namespace jf
+
 extern "C" jf_status jf_batch_workspace(jf_plan* const* plans, int n, size_t* bytes) {
   if (!plans || n < 0 || !bytes) {
     set_error("jf_batch_workspace: bad argument");
     return JF_E_ARG;
   }
-  size_t tot = 0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     if (!plans[i]) {
       set_error("jf_batch_workspace: NULL plan");
       return JF_E_ARG;
     }
-    tot += (state_of(plans[i]).lay.total + 255) / 256 * 256;
-  }
-  size_t items = 0, steps = 0;
-  for (int i = 0; i < n; ++i) {
-    items += state_of(plans[i]).lay.lds_comps.size();
-    steps += state_of(plans[i]).lay.lds_steps;
-  }
-  tot += align256(items * sizeof(LdsItem)) + align256(steps * sizeof(LdsStep));
-  *bytes = tot;
+  *bytes = batch_layout(plans, n).total;
   return JF_OK;
 }
 
@@ -1329,14 +1361,22 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     return JF_E_OOM;
   }
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  const BatchLayout bl = batch_layout(plans, n);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  unsigned char* bufs = w + bl.bufs;
+  {
+    // the shared buffers and the persistent tables are written by this call: no plan's tables
+    // uploaded there before survive it
+    std::lock_guard<std::mutex> g(g_upload_mu);
+    const auto a = reinterpret_cast<uintptr_t>(bufs);
+    forget_uploads(a, a + (bl.total - bl.bufs));
+  }
   std::vector<unsigned char*> base(n);
-  size_t off = 0;
   for (int i = 0; i < n; ++i) {
-    base[i] = static_cast<unsigned char*>(ws) + off;
-    off += (state_of(plans[i]).lay.total + 255) / 256 * 256;
+    base[i] = w + bl.base[i];
     st = check_ws(plans[i], base[i], state_of(plans[i]).lay.total);
     if (st != JF_OK) return st;
-    st = upload(plans[i], base[i], stream);
+    st = upload(plans[i], base[i], stream, state_of(plans[i]).lay.buf_off);
     if (st != JF_OK) return st;
   }
   // every small component of every plan in one persistent launch
@@ -1350,8 +1390,8 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     items.insert(items.end(), it.begin(), it.end());
     lsteps.insert(lsteps.end(), ss.begin(), ss.end());
   }
-  unsigned char* items_dev = static_cast<unsigned char*>(ws) + off;
-  unsigned char* steps_dev = items_dev + align256(items.size() * sizeof(LdsItem));
+  unsigned char* items_dev = w + bl.items;
+  unsigned char* steps_dev = w + bl.steps;
   if (!items.empty()) {
     JF_HIP(hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(LdsItem), hipMemcpyHostToDevice, stream));
     JF_HIP(hipMemcpyAsync(steps_dev, lsteps.data(), lsteps.size() * sizeof(LdsStep), hipMemcpyHostToDevice, stream));
@@ -1379,7 +1419,7 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
         launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
                           reinterpret_cast<const LdsStep*>(steps_dev), stream) != hipSuccess)
       st = JF_E_HIP;
-    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream, nullptr, true);
+    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs);
     hipError_t ce = hipStreamEndCapture(stream, &g);
     if (st != JF_OK) {
       if (ce == hipSuccess && g) hipGraphDestroy(g);
@@ -1404,7 +1444,7 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
       JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
                                reinterpret_cast<const LdsStep*>(steps_dev), stream));
     for (int i = 0; i < n; ++i) {
-      st = enqueue_program(plans[i], base[i], stream, nullptr, true);
+      st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs);
       if (st != JF_OK) return st;
     }
   }
