@@ -252,25 +252,28 @@ def run_paper_shapes(args, torch, gen, jf, stream):
 
 def run_batch(args, torch, gen, jf, stream):
     """The 512-circuit batch under the budget rule: plan every member (reduced search effort, size
-    cap 2^32), spend more search on the costliest ones within --replan-s of host time (keeping the
-    cheaper plan), run the feasible ones in cost order -- the small ones together in one captured
-    jf_fidelity_batch launch, then one at a time -- until the GPU time budget is spent, and project
-    the rest from the planner's cost model."""
+    cap 2^32; members wider than the cap slice wire legs), spend more search on the costliest ones
+    within --replan-s of host time (keeping the cheaper plan), then run the cheapest members whose
+    estimated time fits --budget-s as ONE jf_fidelity_batch submission -- one hipGraph: the
+    LDS-resident members in one persistent launch, the others' step programs back to back sharing
+    one buffer region -- and project the rest from the planner's cost model.  Parity: the same
+    members as complex128 plans in one more batch, member by member."""
     insts = gen.config4()
     cap = args.batch_cap
     free, _ = torch.cuda.mem_get_info()
     t0 = time.perf_counter()
-    plans, infeasible = [], []
+    plans = []
     for inst in insts:
-        try:
-            p = jf.plan(inst, 1, args.dtype, max_log2=cap, flags=jf.JF_FLAG_EFFORT(3))
-            plans.append([p.stats()["est_seconds"], p.info(), p, inst])
-        except jf.JfError as e:
-            infeasible.append({"name": inst["name"], "reason": str(e)[:100]})
+        p = jf.plan(inst, 1, args.dtype, max_log2=cap, flags=jf.JF_FLAG_EFFORT(3))
+        plans.append([p.stats()["est_seconds"], p.info(), p, inst])
     plan_s = time.perf_counter() - t0
-    progress(f"planned {len(plans)} members in {plan_s:.1f} s ({len(infeasible)} over the cap)")
+    wired = sum(1 for x in plans if x[2].stats()["n_sliced_wires"])
+    progress(f"planned {len(plans)} members in {plan_s:.1f} s ({wired} slice wire legs)")
     replanned, t1 = 0, time.perf_counter()
+    # members far beyond the budget stay out of reach even at a much cheaper plan: not re-planned
     for x in sorted(plans, key=lambda x: -x[0]):
+        if x[0] > 20 * args.budget_s:
+            continue
         if time.perf_counter() - t1 > args.replan_s or x[0] < 0.02:
             break
         q = jf.plan(x[3], 1, args.dtype, max_log2=cap, flags=jf.JF_FLAG_EFFORT(8))
@@ -282,100 +285,97 @@ def run_batch(args, torch, gen, jf, stream):
             progress(f"re-planned {replanned}")
     replan_s = time.perf_counter() - t1
     progress(f"re-planned {replanned} members in {replan_s:.1f} s")
-    too_big = [x for x in plans if x[1]["workspace_bytes"] > 0.9 * free]
-    plans = [x for x in plans if x not in too_big]
     plans.sort(key=lambda x: x[0])
-    small = [x for x in plans if x[1]["workspace_bytes"] <= (64 << 20) and x[1]["path_bytes"] <= 2e8]
-    large = [x for x in plans if x not in small]
-    done_terms, gpu_s, done = 0, 0.0, 0
-    # the small members: one batch (persistent launch for the tiny ones + every step program),
-    # captured in a hipGraph on the first call and replayed
-    bp = [x[2] for x in small]
+    # the work list: the cheapest members whose estimates fit the budget and whose batch workspace
+    # (their small parts plus the largest buffer set) fits the free memory
+    chosen, est_sum = [], 0.0
+    for x in plans:
+        if est_sum + x[0] > args.budget_s:
+            break
+        if jf.jf_batch_workspace([y[2] for y in chosen] + [x[2]]) > 0.8 * free:
+            break
+        chosen.append(x)
+        est_sum += x[0]
+    rest = plans[len(chosen):]
+    bp = [x[2] for x in chosen]
     need = jf.jf_batch_workspace(bp)
     ws = jf.workspace(need)
     side = torch.cuda.Stream()  # a non-null stream (default priority): the batch is graph-captured there
+    progress(f"one batch of {len(bp)} members (estimated {est_sum:.1f} s, workspace {need / 2**30:.1f} GiB): capture and run")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     jf.jf_fidelity_batch(bp, ws, side)
     torch.cuda.synchronize()
-    reps = 5
+    first_s = time.perf_counter() - t2
+    progress(f"captured and ran in {first_s:.1f} s; timed replay")
     t2 = time.perf_counter()
-    for _ in range(reps):
-        out_small = jf.jf_fidelity_batch(bp, ws, side)
+    res = jf.jf_fidelity_batch(bp, ws, side)
     torch.cuda.synchronize()
-    batch_s = (time.perf_counter() - t2) / reps
+    gpu_s = time.perf_counter() - t2
     del ws
-    done_terms += sum(x[1]["kraus_terms"] for x in small)
-    gpu_s += batch_s
-    done += len(small)
-    # the large members, cheapest first, until the budget is spent
-    bytes_done, ws = 0.0, None
-    for est, info, p, inst in large:
-        if gpu_s + est > args.budget_s:
-            break
-        if ws is None or ws.numel() < info["workspace_bytes"]:
-            ws = None
-            torch.cuda.empty_cache()
-            ws = jf.workspace(info["workspace_bytes"])
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        jf.jf_fidelity_alg1(p, ws, stream)
-        torch.cuda.synchronize()
-        gpu_s += time.perf_counter() - t2
-        done += 1
-        done_terms += info["kraus_terms"]
-        bytes_done += info["path_bytes"]
-        if (done - len(small)) % 20 == 0:
-            progress(f"large members done: {done - len(small)}, GPU time {gpu_s:.1f} s")
-    ws = None
     torch.cuda.empty_cache()
-    rest = large[done - len(small):]
-    # parity of the completed members (not timed): complex64 against complex128 where the
-    # complex128 plan's workspace fits
-    worst, checked, unchecked, worst_member = 0.0, 0, 0, None
-    if args.dtype != "c128":
-        res_b = dict(zip([id(x[2]) for x in small], out_small))
-        for est, info, p, inst in small + large[:done - len(small)]:
-            q = jf.plan(inst, 1, "c128", max_log2=cap, flags=jf.JF_FLAG_EFFORT(3))
-            need = max(info["workspace_bytes"], q.info()["workspace_bytes"])
-            if need > 0.45 * free or q.stats()["est_seconds"] > 2.0:
-                unchecked += 1
+    done_terms = sum(x[1]["kraus_terms"] for x in chosen)
+    bytes_done = sum(x[1]["path_bytes"] for x in chosen)
+    flops_done = sum(x[1]["path_flops"] for x in chosen)
+    progress(f"replay {gpu_s:.2f} s: {done_terms / gpu_s:.0f} Kraus-term contractions/s")
+    # parity: the same members as complex128 plans, in as few batches as the free memory allows
+    parity = {"checked": 0, "max_abs_dfj_vs_c128": None, "worst_member": None}
+    if args.dtype != "c128" and not args.no_parity:
+        t3 = time.perf_counter()
+        q128 = [jf.plan(x[3], 1, "c128", max_log2=cap, flags=jf.JF_FLAG_EFFORT(3)) for x in chosen]
+        limit = 0.8 * free
+        chunks, cur, skipped = [], [], []
+        for i, q in enumerate(q128):
+            if jf.jf_batch_workspace([q]) > limit:
+                skipped.append(i)
                 continue
-            if ws is None or ws.numel() < need:
-                ws = None
-                torch.cuda.empty_cache()
-                ws = jf.workspace(need)
-            f64 = res_b[id(p)]["fj"] if id(p) in res_b else jf.jf_fidelity_alg1(p, ws, stream)["fj"]
-            dfj = abs(f64 - jf.jf_fidelity_alg1(q, ws, stream)["fj"])
-            if dfj > worst:
-                worst = dfj
-                worst_member = {"name": inst.get("name", ""), "n": inst["n"], "gates": len(inst["gates"]),
-                                "sites": len(inst.get("noise", [])), "max_log2": info["max_log2_intermediate"],
-                                "fj": f64}
-            checked += 1
-            if checked % 50 == 0:
-                progress(f"parity checked: {checked}, worst {worst:.2e}")
-        ws = None
-    large_s = gpu_s - batch_s
+            if cur and jf.jf_batch_workspace([q128[j] for j in cur] + [q]) > limit:
+                chunks.append(cur)
+                cur = []
+            cur.append(i)
+        if cur:
+            chunks.append(cur)
+        d = {}
+        for ch in chunks:
+            qs = [q128[j] for j in ch]
+            ws = jf.workspace(jf.jf_batch_workspace(qs))
+            progress(f"complex128 parity batch of {len(qs)} members")
+            for j, r in zip(ch, jf.jf_fidelity_batch(qs, ws, side)):
+                d[j] = abs(res[j]["fj"] - r["fj"])
+            torch.cuda.synchronize()
+            del ws
+            torch.cuda.empty_cache()
+        if d:
+            k = max(d, key=d.get)
+            inst = chosen[k][3]
+            parity = {"checked": len(d), "batches": len(chunks), "unchecked_c128_beyond_memory": len(skipped),
+                      "max_abs_dfj_vs_c128": d[k], "members_over_1e-6": sum(x > 1e-6 for x in d.values()),
+                      "worst_member": {"name": inst["name"], "n": inst["n"], "gates": len(inst["gates"]),
+                                       "sites": len(inst["noise"]), "fj": res[k]["fj"]},
+                      "seconds": time.perf_counter() - t3}
+    lds = sum(1 for x in chosen if x[1]["max_log2_intermediate"] <= 11)
     out = {"metric": "Kraus-term contractions/s + contraction TFLOP/s, c64 vs c128 at |dF_J|<=1e-6",
            "value": done_terms / gpu_s, "unit": "Kraus-term contractions/s", "n_gpus": 1, "steps": 1, "warmup": 1,
            "ms_per_step": gpu_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": args.dtype, "data": "synthetic (seeded generator, no datasets)",
            "config": {"workload": "512 circuits: n~U{8..20}, gates~U{100..800} (70% H/S/T/RZ, 30% CX), "
-                                  "1-6 depolarising sites p~U[1e-4,1e-2]; budget rule (cost-sorted, time budget)",
-                      "budget_s": args.budget_s, "max_log2_intermediate": cap},
-           "members": len(insts), "planned": len(plans) + len(too_big),
-           "infeasible_at_cap": len(infeasible), "workspace_beyond_free_memory": len(too_big),
-           "completed": done, "completed_terms": done_terms, "gpu_seconds": gpu_s,
-           "small_batch": {"members": len(small), "terms": sum(x[1]["kraus_terms"] for x in small),
-                           "seconds_per_replay": batch_s,
-                           "terms_per_s": sum(x[1]["kraus_terms"] for x in small) / batch_s},
-           "large_members": {"completed": done - len(small), "seconds": large_s,
-                             "hbm_gbs": bytes_done / large_s / 1e9 if large_s > 0 else None},
-           "remaining_feasible": len(rest), "remaining_terms": sum(x[1]["kraus_terms"] for x in rest),
+                                  "1-6 depolarising sites p~U[1e-4,1e-2]; budget rule (cost-sorted, time budget), "
+                                  "the work list as one batched submission",
+                      "budget_s": args.budget_s, "max_log2_intermediate": cap,
+                      "launch": "one jf_fidelity_batch call: one hipGraph replay"},
+           "members": len(insts), "planned": len(plans), "members_slicing_wires": wired,
+           "completed": len(chosen), "completed_terms": done_terms, "gpu_seconds": gpu_s,
+           "first_call_seconds_with_capture": first_s, "estimated_seconds_of_completed": est_sum,
+           "completed_lds_resident_or_tiny": lds, "completed_step_programs": len(chosen) - lds,
+           "contraction_tflops": flops_done / gpu_s / 1e12, "hbm_gbs_algorithmic": bytes_done / gpu_s / 1e9,
+           "batch_workspace_bytes": need,
+           "remaining": len(rest), "remaining_terms": sum(x[1]["kraus_terms"] for x in rest),
            "projected_seconds_for_remaining": sum(x[0] for x in rest),
-           "parity": {"max_abs_dfj_vs_c128": worst, "checked": checked, "unchecked_c128_too_large": unchecked,
-                      "worst_member": worst_member},
-           "planning_seconds": plan_s, "replanned": replanned, "replanning_seconds": replan_s,
-           "infeasible_examples": infeasible[:5]}
+           "remaining_slicing_wires": sum(1 for x in rest if x[2].stats()["n_sliced_wires"]),
+           "most_expensive_projected": [{"name": x[3]["name"], "est_s": x[0], "sliced_wires": x[2].stats()["n_sliced_wires"],
+                                         "leaves": x[1]["work_items"], "workspace_gb": x[1]["workspace_bytes"] / 1e9}
+                                        for x in rest[-3:]],
+           "parity": parity, "planning_seconds": plan_s, "replanned": replanned, "replanning_seconds": replan_s}
     print(json.dumps(out))
 
 
@@ -392,7 +392,8 @@ def main():
                     help="workload: cfg2 (default) the n=16 Alg I workload; cfg1 n=5 Alg I; cfg3 n=25 chain Alg II; "
                          "cfg4 the 512-circuit batch (budget rule); cfg5 n=36 chain Alg II; crossover Alg I vs II "
                          "over the noise count; paper-shapes random circuits of the paper's Table 1 shapes (context)")
-    ap.add_argument("--budget-s", type=float, default=60.0, help="cfg4: GPU time budget for the cost-sorted work list")
+    ap.add_argument("--budget-s", type=float, default=30.0, help="cfg4: GPU time budget for the cost-sorted work list")
+    ap.add_argument("--no-parity", action="store_true", help="cfg4: skip the complex128 parity batch")
     ap.add_argument("--batch-cap", type=int, default=32, help="cfg4: log2 size cap of the members' intermediates")
     ap.add_argument("--replan-s", type=float, default=60.0,
                     help="cfg4: host time for re-planning the costliest members at a higher search effort")

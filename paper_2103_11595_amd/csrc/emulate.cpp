@@ -125,30 +125,8 @@ bool validate_program(const Program& P, std::string& why) {
   return true;
 }
 
-void assemble_result(const Program& p, const std::vector<CompSum>& sums, jf_result* out) {
+void static_result(const Program& p, jf_result* out) {
   jf_result r = {};
-  const double s = std::exp2(p.log2_scale);  // exact: an integer power of two
-  if (p.opt.alg == 1) {
-    // F_J = (s |scalar|)^2 * prod_c sum_k |t_ck|^2, each sum a double-double (hi, lo)
-    double a = s * s * std::norm(p.scalar);
-    double hi = a, lo = 0;
-    for (auto& cs : sums) {
-      double h = hi * cs.hi;
-      double l = std::fma(hi, cs.hi, -h) + hi * cs.lo + lo * cs.hi;
-      hi = h + l;
-      lo = l - (hi - h);
-    }
-    r.fj = hi + lo;
-    // 1 - F_J: 1 - hi is exact when hi is in [0.5, 2] (Sterbenz); then subtract lo
-    r.one_minus_fj = (1.0 - hi) - lo;
-    r.imag_residual = 0;
-  } else {
-    cd v = s * p.scalar;
-    for (auto& cs : sums) v *= cs.value;
-    r.fj = v.real();
-    r.one_minus_fj = 1.0 - v.real();
-    r.imag_residual = std::abs(v.imag());
-  }
   r.kraus_terms = p.kraus_terms;
   r.work_items = p.work_items;
   r.max_log2_intermediate = p.max_log2;

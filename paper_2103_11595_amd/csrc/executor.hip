@@ -27,6 +27,8 @@
 
 namespace jf {
 
+static_assert(LDS_RESIDENT_MAX == LDS_RESIDENT_LOG2, "the planner's LDS-resident components fit the persistent kernel");
+
 namespace {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -35,6 +37,7 @@ struct DevLayout {
   size_t desc_off = 0, pool_off = 0, const_off = 0, buf_off = 0, out_off = 0, sums_off = 0, total = 0;
   size_t image_end = 0;  // end of the host image (descriptors, operators, constants, LDS tables)
   size_t sumsq_off = 0;  // scratch of the two-pass sum of |t|^2 (2 SUMSQ_BLOCKS doubles)
+  size_t res_off = 0;    // F_J, 1 - F_J, |Im|, written by the device
   size_t lds_items_off = 0, lds_steps_off = 0;
   std::vector<size_t> leaf_off;                           // per component with sliced wires: its leaf buffer
   std::vector<int> lds_comps;                             // components run by the persistent kernel
@@ -300,6 +303,8 @@ void build_layout(const Program& P, DevState& S) {
     }
   L.sums_off = off;
   off += align256(P.comps.size() * 4 * sizeof(double));
+  L.res_off = off;
+  off += 256;
   L.sumsq_off = off;
   off += align256(2 * SUMSQ_BLOCKS * sizeof(double));
   // the level buffers last: the members of a batch, which run one after another on one stream,
@@ -480,7 +485,7 @@ struct Prof {
   Prof(const Prof&) = delete;
   Prof& operator=(const Prof&) = delete;
   ~Prof() {
-    for (auto e : ev) hipEventDestroy(e);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -770,6 +775,12 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
                         reinterpret_cast<double*>(ws + L.sums_off) + 4 * c,
                         reinterpret_cast<double*>(ws + L.sumsq_off), stream));
   }
+  // the product over components and 1 - F_J, on the device
+  const double s = std::exp2(P.log2_scale);  // exact: an integer power of two
+  const cd v0 = s * P.scalar;
+  JF_HIP(launch_assemble(reinterpret_cast<const double*>(ws + L.sums_off), int(P.comps.size()), P.opt.alg,
+                         s * s * std::norm(P.scalar), v0.real(), v0.imag(), reinterpret_cast<double*>(ws + L.res_off),
+                         stream));
   return JF_OK;
 }
 
@@ -833,16 +844,13 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
                        bool pinned = true) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
-  std::vector<double> sums(P.comps.size() * 4 + 1);
-  const size_t sums_bytes = P.comps.size() * 4 * sizeof(double);
-  if (!P.comps.empty()) {
-    double* pin = sums.data();
-    if (pinned) {
-      const jf_status ps = pinned_sums(p, &pin);
-      if (ps != JF_OK) return ps;
-    }
-    JF_HIP(hipMemcpyAsync(pin, ws + S.lay.sums_off, sums_bytes, hipMemcpyDeviceToHost, stream));
+  double res[4];
+  double* land = res;
+  if (pinned) {
+    const jf_status ps = pinned_sums(p, &land);
+    if (ps != JF_OK) return ps;
   }
+  JF_HIP(hipMemcpyAsync(land, ws + S.lay.res_off, sizeof(res), hipMemcpyDeviceToHost, stream));
   std::vector<std::vector<cd>> co;
   if (terms) {
     for (auto& cp : P.comps) {
@@ -853,14 +861,13 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
     }
   }
   JF_HIP(hipStreamSynchronize(stream));
-  if (!P.comps.empty() && pinned) std::memcpy(sums.data(), S.pinned_sums, sums_bytes);
-  std::vector<CompSum> cs(P.comps.size());
-  for (size_t c = 0; c < P.comps.size(); ++c) {
-    cs[c].hi = sums[4 * c];
-    cs[c].lo = sums[4 * c + 1];
-    cs[c].value = cd(sums[4 * c + 2], sums[4 * c + 3]);
-  }
-  assemble_result(P, cs, out);
+  if (pinned) std::memcpy(res, land, sizeof(res));
+  jf_result r;
+  static_result(P, &r);
+  r.fj = res[0];
+  r.one_minus_fj = res[1];
+  r.imag_residual = res[2];
+  *out = r;
   if (terms) gather_terms(P, co, terms);
   return JF_OK;
 }

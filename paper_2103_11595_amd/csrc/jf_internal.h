@@ -93,6 +93,11 @@ enum Compute { C_F64 = 0, C_F32 = 1, C_SPLIT = 2 };
 constexpr int MAXK = 64;     // max K (=2^kS) and Nn (=2^kN) of one device step
 constexpr int MAXR = 256;    // max rows per tile
 constexpr int MAXHI = 48;    // max high (tile-index) bits
+// components whose intermediates all fit 2^11 elements run whole in one workgroup of the persistent
+// kernel (two FP64 ping-pong buffers of 32 KB in LDS).  2^12 would fit the 160 KB of a gfx950
+// compute unit, but one workgroup per component is slower there than the step kernels: the
+// 36-qubit chain took 0.297 ms against 0.160 ms in complex64 (measured on MI355X).
+constexpr int LDS_RESIDENT_MAX = 11;
 
 // One device step: C[f, n] = sum_s A[f, s] * B[s, n]  (complex), see kernels.hip.
 struct Step {
@@ -177,7 +182,7 @@ struct ComponentProgram {
   int n_tensors = 0;
   // device: offset of the component output (double2 elements) in the output region
   long long out_off = 0;
-  // one level and every intermediate <= 2^11 elements: runs whole in one workgroup (LDS)
+  // one level and every intermediate <= 2^LDS_RESIDENT_MAX elements: runs whole in one workgroup (LDS)
   bool lds_resident = false;
   std::vector<Chain> chains;
 };
@@ -241,9 +246,9 @@ bool validate_program(const Program& P, std::string& why);
 // host emulation of the lowered program (validation only; no fidelity entry point calls it)
 void emulate_program(const Program& p, std::vector<std::vector<cd>>& comp_out);
 
-// assemble F_J etc. from per-component sums (shared by GPU run and emulation)
-struct CompSum { double hi = 0, lo = 0; cd value = 0; };
-void assemble_result(const Program& p, const std::vector<CompSum>& sums, jf_result* out);
+// the fields of a result that the plan fixes (terms covered, leaves, sizes, flops, bytes); F_J,
+// 1 - F_J and the residual come from the device
+void static_result(const Program& p, jf_result* out);
 void gather_terms(const Program& p, const std::vector<std::vector<cd>>& comp_out, double* term_traces);
 
 }  // namespace jf

@@ -127,7 +127,7 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h_desc, const 
 // points at its descriptor and operator block (compute type given by mode; FP32 two-term blocks
 // are summed hi + lo); the final step writes the item's output and its double-double sum of
 // |t|^2 (sums[0..1]) and t_0 (sums[2..3]).
-constexpr int LDS_RESIDENT_LOG2 = 11;
+constexpr int LDS_RESIDENT_LOG2 = 11;  // two FP64 buffers of 32 KB
 struct LdsStep {
   const StepDesc* desc;
   const void* B;
@@ -148,6 +148,10 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
+// res[0..3] = F_J, 1 - F_J, |Im| (Algorithm II), 0 from the components' sums (4 doubles each:
+// double-double sum of |t|^2, first entry): the product over components on the device
+hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
+                           hipStream_t stream);
 // out[i] += part[i] for i < n (double2 entries): a leaf's partial result of sliced wires
 hipError_t launch_accumulate(void* out, const void* part, long long n_double2, hipStream_t stream);
 

@@ -1606,6 +1606,46 @@ hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* s
   return hipGetLastError();
 }
 
+// F_J of a plan from its components' sums, on the device (one thread).  Algorithm I: the
+// double-double product a prod_c (hi_c + lo_c), a = (2^scale |scalar|)^2 (a power of two times the
+// squared modulus of the traced-out scalar), F_J = hi + lo and 1 - F_J = (1 - hi) - lo, where 1 - hi
+// is exact for hi in [0.5, 2] (Sterbenz).  Algorithm II: T / d^2 = v0 prod_c value_c (complex),
+// F_J = Re, 1 - F_J = 1 - Re (exact for Re in [0.5, 2]), |Im| the residual.  res[0..2].
+__global__ void k_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (alg == 1) {
+    double hi = a, lo = 0.0;
+    for (int c = 0; c < ncomp; ++c) {
+      const double sh = sums[4 * c], sl = sums[4 * c + 1];
+      const double h = hi * sh;
+      const double l = fma(hi, sh, -h) + hi * sl + lo * sh;
+      hi = h + l;
+      lo = l - (hi - h);
+    }
+    res[0] = hi + lo;
+    res[1] = (1.0 - hi) - lo;
+    res[2] = 0.0;
+  } else {
+    double vr = v0re, vi = v0im;
+    for (int c = 0; c < ncomp; ++c) {
+      const double cr = sums[4 * c + 2], ci = sums[4 * c + 3];
+      const double nr = vr * cr - vi * ci;
+      vi = vr * ci + vi * cr;
+      vr = nr;
+    }
+    res[0] = vr;
+    res[1] = 1.0 - vr;
+    res[2] = fabs(vi);
+  }
+  res[3] = 0.0;
+}
+
+hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_assemble, dim3(1), dim3(64), 0, stream, sums, ncomp, alg, a, v0re, v0im, res);
+  return hipGetLastError();
+}
+
 __global__ void k_accumulate(double2* out, const double2* part, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double2 a = out[i], b = part[i];

@@ -1201,7 +1201,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         if (ob < 0 || ob >= cp.n_open_bits) throw std::logic_error("Kraus bit without an output position");
     cp.lds_resident = cp.levels.size() == 1 && cp.levels[0].nvar == 1;
     for (auto& st : cp.steps)
-      if (st.rA > 11 || (!st.final_step && st.rC > 11)) cp.lds_resident = false;
+      if (st.rA > LDS_RESIDENT_MAX || (!st.final_step && st.rC > LDS_RESIDENT_MAX)) cp.lds_resident = false;
     // outside the persistent kernel a component also clears its output (one fill launch) and sums
     // |t|^2 over it (two launches): with many open Kraus bits the output itself is large
     if (!cp.lds_resident) P.est_seconds += 2.0 * 16.0 * double(cp.out_len) / cm.bw + 3 * cm.launch;

@@ -16,7 +16,8 @@ import os
 import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libjf.so")
+# JF_LIB selects another build of the library (the sanitizer build of the host code, see build.py)
+LIB_PATH = os.environ.get("JF_LIB") or os.path.join(HERE, "libjf.so")
 
 JF_C128, JF_C64, JF_C64_BF16X6 = 0, 1, 2
 DTYPES = {"c128": JF_C128, "c64": JF_C64, "bf16x6": JF_C64_BF16X6}
