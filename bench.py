@@ -66,10 +66,10 @@ def cpu_plan_executor(plan, fj_gpu: float) -> dict:
             "abs_dfj_vs_gpu_c128": abs(fj - fj_gpu)}
 
 
-def traffic_record(kernel_sha: str, launches: int, algorithmic_bytes: float):
-    """HBM bytes per launch from the committed counter record, if it was taken with the same
-    kernels on the same program (same launches and algorithmic bytes); else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_absorb_cfg2.json")
+def counter_record(name: str, kernel_sha: str, launches: int, algorithmic_bytes: float):
+    """A committed counter record (profiles/<name>.json), if it was taken with the same kernels on
+    the same program (same launches and algorithmic bytes per pass); else None."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -77,7 +77,31 @@ def traffic_record(kernel_sha: str, launches: int, algorithmic_bytes: float):
         return None
     if abs(rec.get("algorithmic_bytes_per_launch", 0) * launches - algorithmic_bytes) > 1e-6 * algorithmic_bytes:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
+
+
+def copy_ceiling(torch, jf, stream, mib: int = 1024) -> dict:
+    """The HBM rate of the library's plain streaming copy (nontemporal, resident grid) of mib MiB,
+    8 and 16 bytes per lane, best of three: the ceiling the step kernels' access pattern can reach."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"copied_mib": mib}
+    for bpl in (8, 16):
+        ms = min(jf.jf_stream_copy(src, dst, bpl, stream) for _ in range(3))
+        out[f"gbs_{bpl}_bytes_per_lane"] = 2 * (mib << 20) / (ms * 1e-3) / 1e9
+    # the runtime's own device-to-device copy, for reference
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = None
+    for _ in range(3):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = e0.elapsed_time(e1) if best is None else min(best, e0.elapsed_time(e1))
+    out["gbs_runtime_copy"] = 2 * (mib << 20) / (best * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 OTHER = {
@@ -430,6 +454,8 @@ def main():
     inst = gen.config2()
     stream = torch.cuda.Stream()  # default priority; the passes replay a hipGraph captured on it
 
+    ceiling = copy_ceiling(torch, jf, stream)
+    progress(f"streaming-copy ceiling: {ceiling}")
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 2**20
         src = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -507,7 +533,15 @@ def main():
     for x in main_form["per_step"]:
         kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
     ksha = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
-    traffic = traffic_record(ksha, prof["launches"], byts)
+    tag = {"c64": "cfg2", "c128": "cfg2_c128", "bf16x6": "cfg2_bf16x6"}[args.dtype]
+    trec = counter_record("traffic_absorb_" + tag, ksha, prof["launches"], byts)
+    traffic = trec["traffic_bytes_per_launch"] if trec else None
+    mrec = counter_record("mfma_absorb_" + tag, ksha, prof["launches"], byts)
+    per_launch = [{"us": x["ms"] * 1e3, "kS": x["kS"], "kN": x["kN"], "L": x["L"], "mode": x["mode"],
+                   "kernel": kv_names[x["variant"]], "steps": x["steps"], "bytes": x["bytes"], "flops": x["flops"],
+                   "gbs": x["bytes"] / (x["ms"] * 1e-3) / 1e9 if x["ms"] else None,
+                   "tflops": x["flops"] / (x["ms"] * 1e-3) / 1e12 if x["ms"] else None}
+                  for x in main_form["per_step"]]
     out = {
         "metric": "Kraus-term contractions/s + contraction TFLOP/s, c64 vs c128 at |dF_J|<=1e-6",
         "value": value,
@@ -542,9 +576,17 @@ def main():
         "kernels_used": kernels_used,
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "contraction steps (k_absorb*, k_chain)", "launches": prof["launches"],
-                     "algorithmic_bytes": byts, "flops": flops, "kernel_ms": kms,
-                     "avg_launch_us": kms * 1e3 / max(1, prof["launches"])},
+                     "traffic_unit": "HBM bytes per launch, average over one pass's launches (scaled FETCH_SIZE + "
+                                     "WRITE_SIZE from the committed counter record; null when the kernels changed)",
+                     "kernel": "contraction steps (k_absorb*, k_chain*)", "launches": prof["launches"],
+                     "algorithmic_bytes_per_launch": byts / max(1, prof["launches"]),
+                     "algorithmic_bytes_per_pass": byts, "flops_per_pass": flops, "kernel_ms_per_pass": kms,
+                     "avg_launch_us": kms * 1e3 / max(1, prof["launches"]),
+                     "frac_of_copy_ceiling": achieved / ceiling["gbs_16_bytes_per_lane"] if bound == "hbm" else None},
+        "hbm_copy_ceiling": ceiling,
+        "mfma_counters": ({k: mrec[k] for k in ("large_contractions", "chains", "all_step_launches", "source") if k in mrec}
+                          if mrec else None),
+        "per_launch": per_launch,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

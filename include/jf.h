@@ -296,6 +296,16 @@ jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* s
                            int cap, int* n_launches);
 
 /*
+ * jf_stream_copy -- measurement aid: copies bytes from src to dst (device buffers, 16-byte aligned;
+ * bytes a multiple of bytes_per_lane = 8 or 16) with a plain streaming kernel -- nontemporal loads
+ * and stores of bytes_per_lane per lane, a resident grid striding over the buffer -- and returns its
+ * duration in *ms (HIP events attached to the dispatch).  2 bytes / ms is the HBM rate the step
+ * kernels' access pattern can reach, the ceiling their per-launch rates are set against.
+ * Synchronises the stream.  Errors: JF_E_ARG, JF_E_HIP.
+ */
+jf_status jf_stream_copy(const void* src, void* dst, size_t bytes, int bytes_per_lane, void* stream, double* ms);
+
+/*
  * Kernels that can run a contraction step.  The staged kernels stage a tile of the input in LDS
  * and multiply it on the matrix cores; the direct kernels load every lane's matrix-core operands
  * straight into registers; FMA multiplies on the vector units; the Gauss kernels are direct

@@ -1028,6 +1028,25 @@ extern "C" jf_status jf_fidelity_noalloc(jf_plan* p, void* stream_v, jf_result* 
   return JF_OK;
 }
 
+extern "C" jf_status jf_stream_copy(const void* src, void* dst, size_t bytes, int bytes_per_lane, void* stream_v,
+                                    double* ms) {
+  if (!src || !dst || !ms || (bytes_per_lane != 8 && bytes_per_lane != 16) || bytes % size_t(bytes_per_lane) ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16) {
+    set_error("jf_stream_copy: bad argument (16-byte aligned buffers, bytes a multiple of 8 or 16 bytes per lane)");
+    return JF_E_ARG;
+  }
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  EventPair ev;
+  JF_HIP(hipEventCreate(&ev.a));
+  JF_HIP(hipEventCreate(&ev.b));
+  JF_HIP(launch_stream_copy(src, dst, bytes, bytes_per_lane, stream, ev.a, ev.b));
+  JF_HIP(hipEventSynchronize(ev.b));
+  float t = 0;
+  JF_HIP(hipEventElapsedTime(&t, ev.a, ev.b));
+  *ms = t;
+  return JF_OK;
+}
+
 extern "C" jf_status jf_profile_run(jf_plan* p, void* ws, size_t ws_bytes, void* stream_v, jf_profile* out) {
   if (!p || !out) {
     set_error("jf_profile_run: bad argument");

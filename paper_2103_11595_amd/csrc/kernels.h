@@ -148,6 +148,10 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop);
 
 // out[i] = 0 for i < n (double2 entries)
 hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
+// Streaming copy of bytes (a multiple of bpl = 8 or 16 bytes per lane, nontemporal, resident grid)
+// between the two events: the HBM ceiling of the step kernels' access pattern.
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bpl, hipStream_t stream, hipEvent_t ev0,
+                              hipEvent_t ev1);
 // res[0..3] = F_J, 1 - F_J, |Im| (Algorithm II), 0 from the components' sums (4 doubles each:
 // double-double sum of |t|^2, first entry): the product over components on the device
 hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,

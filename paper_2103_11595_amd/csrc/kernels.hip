@@ -26,6 +26,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -1603,6 +1604,46 @@ hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* s
   if (n_items <= 0) return hipSuccess;
   const int grid = n_items < 2048 ? n_items : 2048;
   hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(256), 0, stream, items, n_items, steps);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- streaming-copy ceiling ---
+// A plain streaming copy, the reference for what HBM sustains with the access pattern of the
+// step kernels: nontemporal loads and stores of BPL bytes per lane, a resident grid looping with
+// the grid stride, the next element's load issued before the current one is stored.  (Four loads
+// in flight per lane measured slower on MI355X: 4.7 / 4.4 TB/s against 5.3 / 5.0.)
+template <int BPL>
+__global__ __launch_bounds__(256) void k_stream_copy(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                                                     long long n) {
+  typedef float f32v4 __attribute__((ext_vector_type(4)));
+  using W = typename std::conditional<BPL == 16, f32v4, f32v2>::type;
+  const W* s = reinterpret_cast<const W*>(src);
+  W* d = reinterpret_cast<W*>(dst);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  W v = __builtin_nontemporal_load(&s[i]);
+  for (; i + stride < n; i += stride) {
+    const W w = __builtin_nontemporal_load(&s[i + stride]);
+    __builtin_nontemporal_store(v, &d[i]);
+    v = w;
+  }
+  __builtin_nontemporal_store(v, &d[i]);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bpl, hipStream_t stream,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+  if ((bpl != 8 && bpl != 16) || bytes % size_t(bpl)) return hipErrorInvalidValue;
+  const long long n = (long long)(bytes / size_t(bpl));
+  if (n == 0) return hipSuccess;
+  const void* k = bpl == 16 ? reinterpret_cast<const void*>(k_stream_copy<16>) : reinterpret_cast<const void*>(k_stream_copy<8>);
+  const unsigned grid = resident_grid(k, 256, 0, (n + 255) / 256);
+  if (bpl == 16)
+    hipExtLaunchKernelGGL(k_stream_copy<16>, dim3(grid), dim3(256), 0, stream, ev0, ev1, 0, (const unsigned char*)src,
+                          (unsigned char*)dst, n);
+  else
+    hipExtLaunchKernelGGL(k_stream_copy<8>, dim3(grid), dim3(256), 0, stream, ev0, ev1, 0, (const unsigned char*)src,
+                          (unsigned char*)dst, n);
   return hipGetLastError();
 }
 

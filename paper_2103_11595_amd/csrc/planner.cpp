@@ -148,9 +148,11 @@ long long scatter(long long x, const std::vector<int>& pos) {
   return o;
 }
 
-// Step cost for fusion decisions, calibrated on MI355X with a microbenchmark of the step kernel
-// on 2^26-element tensors: tile-structured streaming reaches ~5.2 TB/s, and the complex GEMM of a
-// tile sustains ~55 TFLOP/s on FP32 MFMA and ~28 TFLOP/s on FP64 MFMA (K = 32 operators).
+// Step cost for fusion decisions, calibrated on MI355X: HBM at 5.2 TB/s, what a plain streaming
+// copy sustains there (the library's nontemporal copy, jf_stream_copy, 5.0-5.3 TB/s at 8 and 16
+// bytes per lane; the runtime's device copy 5.2 TB/s) and what the large step kernels reach (4.2 to
+// 5.9 TB/s, read-heavy steps above the copy rate); the complex GEMM of a tile sustains ~55 TFLOP/s
+// on FP32 MFMA and ~28 TFLOP/s on FP64 MFMA (K = 32 operators).
 struct CostModel {
   double bw = 5.2e12;        // effective bytes/s
   double flops = 28e12;      // effective flop/s (FP64 MFMA)

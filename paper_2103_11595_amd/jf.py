@@ -111,7 +111,7 @@ EXPORTS = ["jf_load_circuit", "jf_plan_contraction", "jf_plan_info", "jf_plan_st
            "jf_fidelity_alg1", "jf_fidelity_alg2", "jf_batch_workspace", "jf_fidelity_batch",
            "jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_emulate_plan",
            "jf_profile_run", "jf_plan_describe", "jf_profile_steps", "jf_autotune", "jf_set_kernel_variant",
-           "jf_decide_equivalence", "jf_workspace_release", "jf_fidelity_noalloc"]
+           "jf_decide_equivalence", "jf_workspace_release", "jf_fidelity_noalloc", "jf_stream_copy"]
 
 _lib = None
 
@@ -154,6 +154,7 @@ def lib():
     L.jf_decide_equivalence.argtypes = [vp, C.c_double, vp, sz, vp, C.POINTER(jf_decision)]
     L.jf_workspace_release.argtypes = [vp, sz]
     L.jf_fidelity_noalloc.argtypes = [vp, vp, C.POINTER(jf_result), C.POINTER(C.c_double)]
+    L.jf_stream_copy.argtypes = [vp, vp, sz, C.c_int, vp, C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name not in ("jf_is_equivalent", "jf_free_circuit", "jf_free_plan", "jf_last_error", "jf_plan_describe"):
             getattr(L, name).restype = C.c_int
@@ -391,6 +392,17 @@ def jf_fidelity_noalloc(plan: Plan, stream=None, want_terms: bool = False) -> di
         a = np.frombuffer(terms, dtype=np.float64).copy()
         d["terms"] = a[0::2] + 1j * a[1::2]
     return d
+
+
+def jf_stream_copy(src, dst, bytes_per_lane: int = 16, stream=None) -> float:
+    """Milliseconds of the library's streaming copy of src into dst (torch device tensors of equal
+    byte size): the HBM ceiling measurement."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    ms = C.c_double()
+    _check(lib().jf_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, int(bytes_per_lane),
+                                _stream_ptr(stream), C.byref(ms)))
+    return ms.value
 
 
 def jf_batch_workspace(plans) -> int:

@@ -17,6 +17,13 @@ found from the end of the trace (the shortest sequence of kernel names that the 
 repetitions share), and the last ``--passes`` periods are summarised per kernel, with the device
 time and the span of a pass.
 
+``mfma`` reads one ``--pmc`` run of bench.py with the matrix-core counters (``MfmaUtil``: busy cycles
+of the MFMA units over the dispatch's active cycles and SIMDs; ``SQ_INSTS_VALU_MFMA_MOPS_*``:
+executed matrix-core operations / 512) and joins the last program run's step dispatches with the
+per-launch table bench.py printed for that run: per launch the algorithmic and the executed flops,
+the time (of a run without the profiler when its launch sequence is the same), and the measured
+MFMA utilisation; per class (chains, large contractions, all) the time-weighted utilisation.
+
 ``traffic`` reads two ``--pmc`` runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of bench.py with
 ``--copy-calibration-mib M``: the copy of M MiB (one ``__amd_rocclr_copyBuffer`` dispatch that reads
 and writes M MiB) gives the factor from counter units to bytes, which then scales the counters of
@@ -165,7 +172,8 @@ def traffic(args):
         res[key] = {"scale": scale, "bytes": kib * 1024.0 * scale, "raw_kib": kib}
     alg = b["roofline"]["algorithmic_bytes"]
     tr = res["fetch"]["bytes"] + res["write"]["bytes"]
-    rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "launches": n,
+    rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "dtype": b["dtype"], "launches": n,
+           "traffic_bytes_per_pass": tr, "algorithmic_bytes_per_pass": alg,
            "traffic_bytes_per_launch": tr / n, "fetch_bytes_per_launch": res["fetch"]["bytes"] / n,
            "write_bytes_per_launch": res["write"]["bytes"] / n, "algorithmic_bytes_per_launch": alg / n,
            "fetch_scale": res["fetch"]["scale"], "write_scale": res["write"]["scale"]}
@@ -183,6 +191,81 @@ def traffic(args):
             f"| HBM traffic | {tr / 1e9:.3f} GB | {tr / n / 1e6:.1f} MB |",
             f"| algorithmic bytes (every launch reads its input and writes its output once; a chain counts one pass) | {alg / 1e9:.3f} GB | {alg / n / 1e6:.1f} MB |", "",
             f"Traffic / algorithmic = **{tr / alg:.4f}**."]
+    open(args.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+MOPS = ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+        "SQ_INSTS_VALU_MFMA_MOPS_F16")
+
+
+def mfma(args):
+    b = bench_line(args.log)
+    n = int(b["roofline"]["launches"])
+    per = b["per_launch"]
+    if len(per) != n:
+        raise SystemExit("bench line without a per-launch table of the program run")
+    vals, names = {}, {}
+    for r in csv.DictReader(open(os.path.join(args.dir, "bench_counter_collection.csv"))):
+        d = int(r["Dispatch_Id"])
+        names[d] = r["Kernel_Name"]
+        v = vals.setdefault(d, {})
+        c = r["Counter_Name"]
+        x = float(r["Counter_Value"])
+        v[c] = max(v.get(c, x), x) if c == "MfmaUtil" else v.get(c, 0.0) + x
+    steps = [d for d in sorted(vals) if is_step(names[d])][-n:]
+    if len(steps) != n:
+        raise SystemExit(f"counter run holds {len(steps)} step dispatches, fewer than {n}")
+    timing = per
+    if args.live_log:
+        live = bench_line(args.live_log)["per_launch"]
+        if [x["kernel"] for x in live] == [x["kernel"] for x in per]:
+            timing = live
+    rows = []
+    for i, (d, x, t) in enumerate(zip(steps, per, timing)):
+        ex = 512.0 * sum(vals[d].get(c, 0.0) for c in MOPS)
+        rows.append({"launch": i, "kernel": x["kernel"], "kS": x["kS"], "kN": x["kN"], "L": x["L"], "steps": x["steps"],
+                     "bytes": x["bytes"], "flops": x["flops"], "executed_mfma_flops": ex, "us": t["us"],
+                     "mfma_util_pct": vals[d].get("MfmaUtil"), "name": short(names[d]).split("(")[0]})
+
+    def summary(sel):
+        us = sum(r["us"] for r in sel)
+        if not sel or us <= 0:
+            return None
+        util = sum((r["mfma_util_pct"] or 0.0) * r["us"] for r in sel) / us
+        return {"launches": len(sel), "us": us, "algorithmic_tflops": sum(r["flops"] for r in sel) / us / 1e6,
+                "executed_mfma_tflops": sum(r["executed_mfma_flops"] for r in sel) / us / 1e6,
+                "mfma_busy_pct_time_weighted": util}
+    classes = {"chains": summary([r for r in rows if r["kernel"] == "chain"]),
+               "large_contractions": summary([r for r in rows if r["flops"] >= 8 * r["bytes"]]),
+               "all_step_launches": summary(rows)}
+    alg = b["roofline"].get("algorithmic_bytes_per_pass", b["roofline"].get("algorithmic_bytes"))
+    rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "dtype": b["dtype"], "launches": n,
+           "algorithmic_bytes_per_launch": alg / n, "source": args.out, **classes}
+    json.dump(rec, open(args.json, "w"), indent=1)
+    out = [f"# {args.title}", "", "Commands (from the repository root, on one MI355X):", ""]
+    out += ["    " + c for c in args.command.split(" ;; ")]
+    out += ["", f"kernels.hip sha256[:16] = {rec['kernels_sha']}", "",
+            "Counters of the last program run's contraction-step dispatches: `MfmaUtil` = MFMA busy cycles / "
+            "(active cycles x SIMDs) x 100; executed MFMA flops = 512 x the `SQ_INSTS_VALU_MFMA_MOPS_*` counts "
+            "(what the matrix cores executed: the Gauss form runs 3 real products per complex one, the split form 6 "
+            "BF16 products per real one, padding included); algorithmic flops count a complex MAC as 8. "
+            + ("Times from the run without the profiler (same launch sequence)." if timing is not per else
+               "Times from the profiled run."), "",
+            "| # | kernel | kS kN L | steps | MB moved | alg. GFLOP | us | GB/s | alg. TFLOP/s | exec. MFMA TFLOP/s | MFMA busy % |",
+            "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        us = r["us"] or 1e-9
+        out.append(f"| {r['launch']} | {r['kernel']} | {r['kS']} {r['kN']} {r['L']} | {r['steps']} | {r['bytes'] / 1e6:.1f} | "
+                   f"{r['flops'] / 1e9:.2f} | {us:.1f} | {r['bytes'] / us / 1e3:.0f} | {r['flops'] / us / 1e6:.1f} | "
+                   f"{r['executed_mfma_flops'] / us / 1e6:.1f} | "
+                   + (f"{r['mfma_util_pct']:.1f}" if r["mfma_util_pct"] is not None else "-") + " |")
+    out += ["", "| class | launches | us per pass | alg. TFLOP/s | executed MFMA TFLOP/s | MFMA busy % (time-weighted) |",
+            "|---|---|---|---|---|---|"]
+    for k, v in classes.items():
+        if v:
+            out.append(f"| {k} | {v['launches']} | {v['us']:.1f} | {v['algorithmic_tflops']:.1f} | "
+                       f"{v['executed_mfma_tflops']:.1f} | {v['mfma_busy_pct_time_weighted']:.1f} |")
     open(args.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -215,8 +298,16 @@ def main():
     f.add_argument("--json", required=True)
     f.add_argument("--title", default="HBM traffic of the contraction-step kernels")
     f.add_argument("--command", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("--dir", required=True)
+    m.add_argument("--log", required=True)
+    m.add_argument("--live-log", default=None, help="bench.py log of a run without the profiler (per-launch times)")
+    m.add_argument("--out", required=True)
+    m.add_argument("--json", required=True)
+    m.add_argument("--title", default="Matrix-core utilisation of the contraction-step kernels")
+    m.add_argument("--command", required=True)
     a = ap.parse_args()
-    {"trace": trace, "passes": passes, "traffic": traffic}[a.cmd](a)
+    {"trace": trace, "passes": passes, "traffic": traffic, "mfma": mfma}[a.cmd](a)
 
 
 if __name__ == "__main__":
