@@ -66,6 +66,10 @@ struct DevState {
   hipStream_t run_graph_stream = nullptr;
   unsigned run_graph_gen = 0;
   hipStream_t own_stream = nullptr;         // used when the caller passes the null stream
+  // the persistent launch of the small components runs on this stream beside the other
+  // components' steps (fork and join by events, also inside a captured graph)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // per component, per chain: 1 = run its steps one launch each (the autotuner found the chain
   // slower, or a kernel variant was forced on every step)
   std::vector<std::vector<char>> chain_off;
@@ -758,14 +762,64 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, unsigned char* bufs, 
 
 // Enqueue the whole program (no synchronisation, no host copies): used eagerly and for capture.
 // bufs: the level-buffer region (nullptr: the plan's own, at the end of its workspace).
-jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
-                          bool skip_lds = false, Tune* tune = nullptr, unsigned char* bufs = nullptr) {
+// The plan's side stream and its fork / join events (created on first use, default priority).
+jf_status side_of(jf_plan* p, hipStream_t* side) {
+  DevState& S = state_of(p);
+  if (!S.side_stream) {
+    JF_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
+    JF_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
+    JF_HIP(hipStreamCreateWithFlags(&S.side_stream, hipStreamNonBlocking));
+  }
+  *side = S.side_stream;
+  return JF_OK;
+}
+
+// Launch the persistent kernel over items on `side` (forked from and joined back to `stream` by
+// fork / join; the caller waits on join) or, with no side stream, on `stream` itself.
+jf_status launch_persistent_beside(const LdsItem* items, int n, const LdsStep* steps, hipStream_t stream,
+                                   hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+  if (!side) {
+    JF_HIP(launch_persistent(items, n, steps, stream));
+    return JF_OK;
+  }
+  JF_HIP(hipEventRecord(fork, stream));
+  JF_HIP(hipStreamWaitEvent(side, fork, 0));
+  JF_HIP(launch_persistent(items, n, steps, side));
+  JF_HIP(hipEventRecord(join, side));
+  return JF_OK;
+}
+
+// Enqueue one whole pass of a plan.  side: a stream for the persistent launch of the small
+// components, which then overlaps the other components' steps (one workgroup per component, so
+// it leaves the rest of the device to them); null runs everything on `stream` in order.
+// The product over components and 1 - F_J of a plan, on the device (after all its components).
+jf_status enqueue_assemble(jf_plan* p, unsigned char* ws, hipStream_t stream) {
   const Program& P = p->prog;
   const DevLayout& L = state_of(p).lay;
+  const double s = std::exp2(P.log2_scale);  // exact: an integer power of two
+  const cd v0 = s * P.scalar;
+  JF_HIP(launch_assemble(reinterpret_cast<const double*>(ws + L.sums_off), int(P.comps.size()), P.opt.alg,
+                         s * s * std::norm(P.scalar), v0.real(), v0.imag(), reinterpret_cast<double*>(ws + L.res_off),
+                         stream));
+  return JF_OK;
+}
+
+jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Prof* prof = nullptr,
+                          bool skip_lds = false, Tune* tune = nullptr, unsigned char* bufs = nullptr,
+                          hipStream_t side = nullptr, bool assemble = true) {
+  const Program& P = p->prog;
+  DevState& S = state_of(p);
+  const DevLayout& L = S.lay;
   if (!bufs) bufs = ws + L.buf_off;
-  if (!skip_lds && !L.lds_comps.empty())
-    JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off), int(L.lds_comps.size()),
-                             reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), stream));
+  const bool lds = !skip_lds && !L.lds_comps.empty();
+  if (!lds) side = nullptr;
+  if (lds) {
+    const jf_status st = launch_persistent_beside(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off),
+                                                  int(L.lds_comps.size()),
+                                                  reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), stream,
+                                                  side, S.ev_fork, S.ev_join);
+    if (st != JF_OK) return st;
+  }
   for (size_t c = 0; c < P.comps.size(); ++c) {
     const ComponentProgram& cp = P.comps[c];
     if (cp.lds_resident) continue;
@@ -775,13 +829,8 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
                         reinterpret_cast<double*>(ws + L.sums_off) + 4 * c,
                         reinterpret_cast<double*>(ws + L.sumsq_off), stream));
   }
-  // the product over components and 1 - F_J, on the device
-  const double s = std::exp2(P.log2_scale);  // exact: an integer power of two
-  const cd v0 = s * P.scalar;
-  JF_HIP(launch_assemble(reinterpret_cast<const double*>(ws + L.sums_off), int(P.comps.size()), P.opt.alg,
-                         s * s * std::norm(P.scalar), v0.real(), v0.imag(), reinterpret_cast<double*>(ws + L.res_off),
-                         stream));
-  return JF_OK;
+  if (side) JF_HIP(hipStreamWaitEvent(stream, S.ev_join, 0));
+  return assemble ? enqueue_assemble(p, ws, stream) : JF_OK;
 }
 
 // Copy the plan's tables into ws (unless they are there already).  region: the bytes from ws on
@@ -896,6 +945,11 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
     JF_HIP(hipStreamWaitEvent(S.own_stream, S.ev_order, 0));
     s = S.own_stream;
   }
+  hipStream_t side = nullptr;
+  if (!S.lay.lds_comps.empty() && S.lay.lds_comps.size() < p->prog.comps.size()) {
+    st = side_of(p, &side);
+    if (st != JF_OK) return st;
+  }
   if (graph && (!S.run_graph || S.run_graph_ws != ws || S.run_graph_stream != s || S.run_graph_gen != S.variant_gen)) {
     if (S.run_graph) {
       hipGraphExecDestroy(S.run_graph);
@@ -903,7 +957,7 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
     }
     hipGraph_t g = nullptr;
     JF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    st = enqueue_program(p, w, s);
+    st = enqueue_program(p, w, s, nullptr, false, nullptr, nullptr, side);
     const hipError_t ce = hipStreamEndCapture(s, &g);
     if (st != JF_OK) {
       if (ce == hipSuccess && g) hipGraphDestroy(g);
@@ -928,7 +982,7 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
   if (graph) {
     JF_HIP(hipGraphLaunch(S.run_graph, s));
   } else {
-    st = enqueue_program(p, w, s);
+    st = enqueue_program(p, w, s, nullptr, false, nullptr, nullptr, side);
     if (st != JF_OK) return st;
   }
   JF_HIP(hipEventRecord(S.ev1, s));
@@ -1429,6 +1483,14 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   hipEvent_t e0 = ev.a, e1 = ev.b;
   DevState& S0 = state_of(plans[0]);
   const bool use_graph = n > 0 && stream != nullptr;
+  // the small members' persistent launch beside the larger members' programs
+  bool large = false;
+  for (int i = 0; i < n; ++i) large = large || state_of(plans[i]).lay.lds_comps.size() < plans[i]->prog.comps.size();
+  hipStream_t side = nullptr;
+  if (!items.empty() && large) {
+    st = side_of(plans[0], &side);
+    if (st != JF_OK) return st;
+  }
   std::vector<unsigned long long> key(n);
   for (int i = 0; i < n; ++i) key[i] = plans[i]->uid;
   std::vector<unsigned> gens(n);
@@ -1441,11 +1503,17 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     }
     hipGraph_t g = nullptr;
     JF_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    if (!items.empty() &&
-        launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
-                          reinterpret_cast<const LdsStep*>(steps_dev), stream) != hipSuccess)
-      st = JF_E_HIP;
-    for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs);
+    if (!items.empty())
+      st = launch_persistent_beside(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
+                                    reinterpret_cast<const LdsStep*>(steps_dev), stream, side, S0.ev_fork, S0.ev_join);
+    // with the persistent launch beside them, every member's assembly (which reads its small
+    // components' sums) waits for it
+    for (int i = 0; i < n && st == JF_OK; ++i)
+      st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs, nullptr, side == nullptr);
+    if (st == JF_OK && side) {
+      if (hipStreamWaitEvent(stream, S0.ev_join, 0) != hipSuccess) st = JF_E_HIP;
+      for (int i = 0; i < n && st == JF_OK; ++i) st = enqueue_assemble(plans[i], base[i], stream);
+    }
     hipError_t ce = hipStreamEndCapture(stream, &g);
     if (st != JF_OK) {
       if (ce == hipSuccess && g) hipGraphDestroy(g);
@@ -1466,12 +1534,21 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
   if (use_graph) {
     JF_HIP(hipGraphLaunch(S0.graph, stream));
   } else {
-    if (!items.empty())
-      JF_HIP(launch_persistent(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
-                               reinterpret_cast<const LdsStep*>(steps_dev), stream));
-    for (int i = 0; i < n; ++i) {
-      st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs);
+    if (!items.empty()) {
+      st = launch_persistent_beside(reinterpret_cast<const LdsItem*>(items_dev), int(items.size()),
+                                    reinterpret_cast<const LdsStep*>(steps_dev), stream, side, S0.ev_fork, S0.ev_join);
       if (st != JF_OK) return st;
+    }
+    for (int i = 0; i < n; ++i) {
+      st = enqueue_program(plans[i], base[i], stream, nullptr, true, nullptr, bufs, nullptr, side == nullptr);
+      if (st != JF_OK) return st;
+    }
+    if (side) {
+      JF_HIP(hipStreamWaitEvent(stream, S0.ev_join, 0));
+      for (int i = 0; i < n; ++i) {
+        st = enqueue_assemble(plans[i], base[i], stream);
+        if (st != JF_OK) return st;
+      }
     }
   }
   JF_HIP(hipEventRecord(e1, stream));
@@ -1495,7 +1572,11 @@ extern "C" void jf_free_plan(jf_plan* p) {
       hipStreamSynchronize(s->own_stream);
       hipStreamDestroy(s->own_stream);
     }
-    for (hipEvent_t e : {s->ev0, s->ev1, s->ev_order})
+    if (s->side_stream) {
+      hipStreamSynchronize(s->side_stream);
+      hipStreamDestroy(s->side_stream);
+    }
+    for (hipEvent_t e : {s->ev0, s->ev1, s->ev_order, s->ev_fork, s->ev_join})
       if (e) hipEventDestroy(e);
     if (s->pinned_sums) hipHostFree(s->pinned_sums);
     {

@@ -382,6 +382,24 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
   T* sBt = reinterpret_cast<T*>(smem);            // [k][i] (hi), then [k][i] (lo)
   T* sAr = sBt + (TWO_TERM ? 2 : 1) * K2 * M2;    // [s][r]
   T* sAi = sAr + KR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int Nb = R >> 4;  // MB = M2 / 16 output blocks per row block (the launcher checks)
+  C2 stage[MAXE];
+  auto fetch = [&](long long t) {
+    const long long bA = tile_base(tbb.chA, t);
+#pragma unroll
+    for (int e = 0; e < MAXE; ++e) {
+      const int i = threadIdx.x + NT * e;
+      if (i < KR) stage[e] = ld_stream(&A[bA + tb.offS[i >> L] + tb.offRA[i & (R - 1)]]);
+    }
+  };
+  __syncthreads();  // offset tables visible
+  // a workgroup with a single tile issues its loads before the operator's, so that the two
+  // latencies overlap (measured: shorter small steps; longer large ones if every workgroup does it)
+  long long t = blockIdx.x;
+  const bool early = nTiles <= (long long)gridDim.x;
+  if (early && t < nTiles) fetch(t);
   // B^T operand: row i of M-block mb maps to complex column mb * 8 + n_of(i % 16), component c_of
   for (int idx = threadIdx.x; idx < K2 * M2; idx += NT) {
     const int k = idx / M2, i = idx - k * M2;
@@ -396,21 +414,48 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
       sBt[K2 * M2 + idx] = (ca && !cb) ? -w : w;
     }
   }
-  __syncthreads();  // offset tables and B^T visible to every wave before the first tile
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, l16 = lane & 15;
-  const int Nb = R >> 4;  // MB = M2 / 16 output blocks per row block (the launcher checks)
-  C2 stage[MAXE];
-  auto fetch = [&](long long t) {
-    const long long bA = tile_base(tbb.chA, t);
+  if (!early && t < nTiles) fetch(t);
+  __syncthreads();  // B^T visible to every wave before the first tile
+  // Work of a tile: Nb row blocks x MB output blocks.  Where there are fewer row blocks than
+  // waves, the output blocks of a row block are shared out in groups of MU, so that every wave
+  // (and so every SIMD) has products to issue; a group's waves read the same A values.
+  const int want = (NW + Nb - 1) / Nb;  // groups per row block that would occupy every wave
+  auto products = [&](auto mu_tag, long long bC) {
+    constexpr int MU = decltype(mu_tag)::value, SG = MB / MU;
+    for (int u = wave; u < Nb * SG; u += NW) {
+      const int nb = u / SG, m0 = (u - nb * SG) * MU;
+      const int j = nb * 16 + l16;  // tile row supplied / produced by this lane
+      // k outermost: each A value is read from LDS once and used by all MU output blocks
+      typename M::acc_t acc[MU];
 #pragma unroll
-    for (int e = 0; e < MAXE; ++e) {
-      const int i = threadIdx.x + NT * e;
-      if (i < KR) stage[e] = ld_stream(&A[bA + tb.offS[i >> L] + tb.offRA[i & (R - 1)]]);
+      for (int mb = 0; mb < MU; ++mb) acc[mb] = typename M::acc_t{0, 0, 0, 0};
+      const T* bt = sBt + l16 + 16 * m0;
+      if (TWO_TERM) {
+        for (int kk = 0; kk < K2; kk += 4) {
+          const int k = kk + g;
+          const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
+#pragma unroll
+          for (int mb = 0; mb < MU; ++mb) acc[mb] = M::op(bt[K2 * M2 + k * M2 + 16 * mb], a, acc[mb]);
+        }
+      }
+      for (int kk = 0; kk < K2; kk += 4) {
+        const int k = kk + g;
+        const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
+#pragma unroll
+        for (int mb = 0; mb < MU; ++mb) acc[mb] = M::op(bt[k * M2 + 16 * mb], a, acc[mb]);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MU; ++mb) {
+        for (int p = 0; p < 2; ++p) {
+          const int n = (m0 + mb) * 8 + M::n_of(M::row_of(g, 2 * p));
+          C2 o;
+          o.x = acc[mb][2 * p];
+          o.y = acc[mb][2 * p + 1];
+          if (MB > 1 || n < Nn) st_stream(&C[bC + tb.offN[n] + tb.offRC[j]], o);
+        }
+      }
     }
   };
-  long long t = blockIdx.x;
-  if (t < nTiles) fetch(t);
   for (; t < nTiles; t += gridDim.x) {
     const long long bC = tile_base(tbb.chC, t);
     __syncthreads();  // every wave is done with the previous tile's planes
@@ -425,38 +470,14 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma(const StepDesc* __restrict__
     __syncthreads();
     // the next tile belongs to this workgroup only: its loads overlap this tile's products
     if (t + gridDim.x < nTiles) fetch(t + gridDim.x);
-    for (int nb = wave; nb < Nb; nb += NW) {
-      const int j = nb * 16 + l16;  // tile row supplied / produced by this lane
-      // k outermost: each A value is read from LDS once and used by all MB output blocks
-      typename M::acc_t acc[MB];
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[mb] = typename M::acc_t{0, 0, 0, 0};
-      const T* bt = sBt + l16;
-      if (TWO_TERM) {
-        for (int kk = 0; kk < K2; kk += 4) {
-          const int k = kk + g;
-          const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[K2 * M2 + k * M2 + 16 * mb], a, acc[mb]);
-        }
-      }
-      for (int kk = 0; kk < K2; kk += 4) {
-        const int k = kk + g;
-        const T a = ((k & 1) ? sAi : sAr)[(k >> 1) * R + j];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = M::op(bt[k * M2 + 16 * mb], a, acc[mb]);
-      }
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        for (int p = 0; p < 2; ++p) {
-          const int n = mb * 8 + M::n_of(M::row_of(g, 2 * p));
-          C2 o;
-          o.x = acc[mb][2 * p];
-          o.y = acc[mb][2 * p + 1];
-          if (MB > 1 || n < Nn) st_stream(&C[bC + tb.offN[n] + tb.offRC[j]], o);
-        }
-      }
-    }
+    if (MB >= 8 && want >= 8)
+      products(std::integral_constant<int, (MB >= 8 ? MB / 8 : 1)>{}, bC);
+    else if (MB >= 4 && want >= 4)
+      products(std::integral_constant<int, (MB >= 4 ? MB / 4 : 1)>{}, bC);
+    else if (MB >= 2 && want >= 2)
+      products(std::integral_constant<int, (MB >= 2 ? MB / 2 : 1)>{}, bC);
+    else
+      products(std::integral_constant<int, MB>{}, bC);
   }
 }
 
@@ -982,18 +1003,7 @@ __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, cons
     const int words = int(sizeof(ChainStepDesc) / sizeof(int)) * nsteps;
     for (int i = threadIdx.x; i < words; i += NT) dst[i] = src[i];
   }
-  for (int j = 0; j < nsteps; ++j) {
-    const int kS = d->st[j].kS, bo = d->st[j].boff;
-    if (SPLIT) {
-      copy_frags(static_cast<const uint4*>(ops.B[j]) + d->st[j].frag, reinterpret_cast<uint4*>(smem) + bo,
-                 576 * split_gauss_mb(kS), threadIdx.x, NT);
-    } else {
-      const float2* Bj = static_cast<const float2*>(ops.B[j]);
-      float2* sOp = reinterpret_cast<float2*>(smem);
-      for (int i = threadIdx.x; i < (1 << (2 * kS)); i += NT) sOp[bo + i] = Bj[i];
-    }
-  }
-  __syncthreads();  // tables and operators visible to every wave
+  __syncthreads();  // digit tables visible
   const int E = 1 << T;
   const int tid = threadIdx.x;
   const long long own = gd[tid & 15] + gd[16 + ((tid >> 4) & 15)];
@@ -1010,8 +1020,23 @@ __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, cons
     for (int k = 0; k < EPT; ++k)
       if (tid + NT * k < E) pre[k] = ld_stream(&A[b + gd[32 + ((tid + NT * k) >> 8)]]);
   };
+  // a workgroup with a single tile issues its loads before the operators' (see k_absorb_mfma)
   long long t = blockIdx.x;
-  if (t < nTiles) fetch(t);
+  const bool early = nTiles <= (long long)gridDim.x;
+  if (early && t < nTiles) fetch(t);
+  for (int j = 0; j < nsteps; ++j) {
+    const int kS = d->st[j].kS, bo = d->st[j].boff;
+    if (SPLIT) {
+      copy_frags(static_cast<const uint4*>(ops.B[j]) + d->st[j].frag, reinterpret_cast<uint4*>(smem) + bo,
+                 576 * split_gauss_mb(kS), threadIdx.x, NT);
+    } else {
+      const float2* Bj = static_cast<const float2*>(ops.B[j]);
+      float2* sOp = reinterpret_cast<float2*>(smem);
+      for (int i = threadIdx.x; i < (1 << (2 * kS)); i += NT) sOp[bo + i] = Bj[i];
+    }
+  }
+  if (!early && t < nTiles) fetch(t);
+  __syncthreads();  // operators visible to every wave
   for (; t < nTiles; t += gridDim.x) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
@@ -1161,6 +1186,7 @@ __device__ __forceinline__ double2 load_op(const void* B, int mode, int idx, int
 __global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ items, int n_items,
                                                     const LdsStep* __restrict__ steps) {
   __shared__ double2 buf[2][1 << LDS_RESIDENT_LOG2];
+  __shared__ double2 sB[DMAXK * DMAXK];  // the step's operator, in FP64 (read K times per output)
   __shared__ Tables tb;
   __shared__ double rh[256], rl[256];
   __shared__ double2 first;
@@ -1174,8 +1200,9 @@ __global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ 
       const StepDesc* d = st.desc;
       const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
       const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
-      __syncthreads();  // previous step complete before its tables are replaced
+      __syncthreads();  // previous step complete before its tables and operator are replaced
       load_tables(d, tb, K, Nn, R, nHi);
+      for (int i = threadIdx.x; i < K * Nn; i += blockDim.x) sB[i] = load_op(st.B, st.mode, i, K * Nn);
       __syncthreads();
       const int dst = cur == 0 ? 1 : 0;
       const long long total = d->nTiles << (kN + L);
@@ -1192,7 +1219,7 @@ __global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ 
         double2 acc = make_double2(0.0, 0.0);
         for (int s2 = 0; s2 < K; ++s2) {
           const double2 a = cur < 0 ? make_double2(1.0, 0.0) : buf[cur][bA + tb.offS[s2] + tb.offRA[r]];
-          acc = cfma(acc, a, load_op(st.B, st.mode, s2 * Nn + n, K * Nn));
+          acc = cfma(acc, a, sB[s2 * Nn + n]);
         }
         const long long oc = bC + tb.offN[n] + tb.offRC[r];
         if (st.final_step) {

@@ -1105,6 +1105,10 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
         int Lr = std::min<int>(int(F.size()), 8);
         while (Lr > 0 && ((1 << st.kS) * (1 << Lr) > 4096 || (1 << st.kS) * ((1 << st.kN) + (1 << Lr)) > 3840)) --Lr;
         while (Lr > 6 && (1 << st.kS) * (1 << (Lr - 1)) >= 2048) --Lr;
+        // a small intermediate: fewer rows per tile (16 at least, the MFMA block), so that there
+        // are 256 tiles, one per compute unit, where the tensor allows: a tile's products are
+        // then spread over more compute units instead of running one after another in a few
+        while (Lr > 4 && int(F.size()) - Lr < 8) --Lr;
         st.L = Lr;
         std::vector<int> rowsA, rowsC, hiA, hiC, sA, nC;
         for (int i = 0; i < Lr; ++i) {
