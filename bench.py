@@ -502,16 +502,30 @@ def main():
     value = terms / main_form["sec"]
     prof = main_form["prof"]
     flops, byts, kms = prof["flops"], prof["bytes"], prof["kernel_ms"]
-    intensity = flops / byts if byts else 0.0
-    ridge = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"] * 1e3 / PEAK_HBM_GBS
-    if intensity < ridge:
-        bound, achieved, peak, unit = "hbm", byts / (kms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+    mm = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
+    kv_names = {v: k for k, v in jf.KERNEL_VARIANTS.items()}
+    kv_names[jf.KV_CHAIN] = "chain"
+    # the dominant kernel: the step kernel with the largest share of the pass's device time (per-launch
+    # HIP events on the launch stream, jf_profile_steps); its roofline from its intensity: the
+    # algorithmic flops (a complex MAC = 8) and bytes (input read and output written once) per launch
+    groups = {}
+    for x in main_form["per_step"]:
+        g = groups.setdefault(kv_names[x["variant"]], {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        g["launches"] += 1
+        g["ms"] += x["ms"]
+        g["flops"] += x["flops"]
+        g["bytes"] += x["bytes"]
+    dom_name, dom = max(groups.items(), key=lambda kv: kv[1]["ms"])
+    dom_us = dom["ms"] * 1e3 / dom["launches"]
+    dom_fl, dom_b = dom["flops"] / dom["launches"], dom["bytes"] / dom["launches"]
+    ridge = mm * 1e3 / PEAK_HBM_GBS
+    if dom_fl / dom_b < ridge:
+        bound, achieved, peak, unit = "hbm", dom_b / (dom_us * 1e-6) / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
-        bound, unit = "mfma", "TFLOP/s"
-        achieved, peak = flops / (kms * 1e-3) / 1e12, PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
+        bound, achieved, peak, unit = "mfma", dom_fl / (dom_us * 1e-6) / 1e12, mm, "TFLOP/s"
+    symbol = {"chain": "k_chain_split<256>" if args.dtype == "bf16x6" else "k_chain<256>"}.get(dom_name, dom_name)
     # large contractions (complex GEMMs of K >= 16 summed and new extents, intensity >= 8 flop/B)
     # against the FP32 (c64) or FP64 (c128) MFMA peak, and the other steps against HBM
-    mm = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
     big = [x for x in main_form["per_step"] if x["flops"] >= 8 * x["bytes"]]
     rest = [x for x in main_form["per_step"] if x["flops"] < 8 * x["bytes"]]
     big_ms, rest_ms = sum(x["ms"] for x in big), sum(x["ms"] for x in rest)
@@ -527,15 +541,14 @@ def main():
                             "hbm_gbs": sum(x["bytes"] for x in rest) / (rest_ms * 1e-3) / 1e9 if rest_ms else 0,
                             "frac_of_hbm_peak": (sum(x["bytes"] for x in rest) / (rest_ms * 1e-3) / 1e9) / PEAK_HBM_GBS if rest_ms else 0},
     }
-    kv_names = {v: k for k, v in jf.KERNEL_VARIANTS.items()}
-    kv_names[jf.KV_CHAIN] = "chain"
     kernels_used = {}
     for x in main_form["per_step"]:
         kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
     ksha = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
     tag = {"c64": "cfg2", "c128": "cfg2_c128", "bf16x6": "cfg2_bf16x6"}[args.dtype]
     trec = counter_record("traffic_absorb_" + tag, ksha, prof["launches"], byts)
-    traffic = trec["traffic_bytes_per_launch"] if trec else None
+    tk = (trec or {}).get("by_kernel", {}).get(dom_name)
+    traffic = tk["traffic_bytes_per_launch"] if tk and tk["launches"] == dom["launches"] else None
     mrec = counter_record("mfma_absorb_" + tag, ksha, prof["launches"], byts)
     per_launch = [{"us": x["ms"] * 1e3, "kS": x["kS"], "kN": x["kN"], "L": x["L"], "mode": x["mode"],
                    "kernel": kv_names[x["variant"]], "steps": x["steps"], "bytes": x["bytes"], "flops": x["flops"],
@@ -576,13 +589,20 @@ def main():
         "kernels_used": kernels_used,
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                      "frac": achieved / peak, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch, average over one pass's launches (scaled FETCH_SIZE + "
-                                     "WRITE_SIZE from the committed counter record; null when the kernels changed)",
-                     "kernel": "contraction steps (k_absorb*, k_chain*)", "launches": prof["launches"],
-                     "algorithmic_bytes_per_launch": byts / max(1, prof["launches"]),
-                     "algorithmic_bytes_per_pass": byts, "flops_per_pass": flops, "kernel_ms_per_pass": kms,
-                     "avg_launch_us": kms * 1e3 / max(1, prof["launches"]),
-                     "frac_of_copy_ceiling": achieved / ceiling["gbs_16_bytes_per_lane"] if bound == "hbm" else None},
+                     "traffic_unit": "HBM bytes per launch of this kernel (scaled FETCH_SIZE + WRITE_SIZE of its "
+                                     "launches in the committed counter record; null when the kernels changed)",
+                     "kernel": symbol, "variant": dom_name, "launches_per_pass": dom["launches"],
+                     "avg_launch_us": dom_us, "share_of_step_time": dom["ms"] / kms if kms else None,
+                     "algorithmic_flops_per_launch": dom_fl, "algorithmic_bytes_per_launch": dom_b,
+                     "intensity_flop_per_byte": dom_fl / dom_b, "ridge_flop_per_byte": ridge,
+                     "algorithmic_tflops": dom_fl / (dom_us * 1e-6) / 1e12,
+                     "hbm_gbs_algorithmic": dom_b / (dom_us * 1e-6) / 1e9,
+                     "mfma_counters": (mrec.get("chains") if mrec and dom_name == "chain" else None),
+                     "pass": {"launches": prof["launches"], "algorithmic_bytes_per_pass": byts, "flops_per_pass": flops,
+                              "kernel_ms_per_pass": kms, "avg_launch_us": kms * 1e3 / max(1, prof["launches"]),
+                              "hbm_gbs": byts / (kms * 1e-3) / 1e9, "frac_of_hbm_peak": byts / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                              "frac_of_copy_ceiling": byts / (kms * 1e-3) / 1e9 / ceiling["gbs_16_bytes_per_lane"],
+                              "traffic_bytes_per_pass": trec["traffic_bytes_per_pass"] if trec else None}},
         "hbm_copy_ceiling": ceiling,
         "mfma_counters": ({k: mrec[k] for k in ("large_contractions", "chains", "all_step_launches", "source") if k in mrec}
                           if mrec else None),

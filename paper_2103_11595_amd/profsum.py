@@ -73,7 +73,7 @@ def last_passes(rows, per_pass: int, passes: int):
 
 def trace(args):
     b = bench_line(args.log)
-    n = int(b["roofline"]["launches"])
+    n, _ = pass_shape(b)
     rows = list(csv.DictReader(open(os.path.join(args.dir, "bench_kernel_trace.csv"))))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     sel = last_passes(rows, n, args.passes)
@@ -92,19 +92,31 @@ def trace(args):
     for k, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1]):
         out.append(f"| `{k}` | {c} | {t / c:.1f} | {t / 1e3:.3f} | {100 * t / total:.2f} |")
     avg = total / len(sel)
-    live = b["roofline"]["avg_launch_us"]
+    ps = b["roofline"].get("pass", b["roofline"])
+    live = ps["avg_launch_us"]
+    kms = ps.get("kernel_ms_per_pass", ps.get("kernel_ms"))
+    dom = b["roofline"].get("kernel")
+    dsel = [(c, t) for k, (c, t) in by.items() if dom and k.startswith(dom)]
+    dc, dt = sum(c for c, _ in dsel), sum(t for _, t in dsel)
     out += ["", f"All contraction-step launches: {len(sel)} launches, average **{avg:.1f} us** per launch, "
             f"{total / 1e3 / args.passes:.3f} ms of step kernels per program run.",
             f"bench.py in the profiled run (HIP events attached to every step dispatch of one program run, "
             f"perturbed by the profiler's own instrumentation): {live:.1f} us per launch, "
-            f"{b['roofline']['kernel_ms']:.3f} ms per run; value {b['value']:.0f} {b['unit']} "
-            f"({b['ms_per_step']:.3f} ms per pass)."]
+            f"{kms:.3f} ms per run; value {b['value']:.0f} {b['unit']} ({b['ms_per_step']:.3f} ms per pass)."]
+    if dc:
+        out += [f"Dominant kernel of the bench line (`roofline.kernel` = `{dom}`): {dc // args.passes} launches per run, "
+                f"average **{dt / dc:.1f} us** per launch in this trace; the profiled run's live events: "
+                f"{b['roofline']['avg_launch_us']:.1f} us."]
     if args.live_log:
         c = bench_line(args.live_log)
-        lv = c["roofline"]["avg_launch_us"]
+        cps = c["roofline"].get("pass", c["roofline"])
+        lv = cps["avg_launch_us"]
         out += [f"bench.py without the profiler (`{args.live_command}`): **{lv:.1f} us** per launch "
-                f"(`roofline.avg_launch_us`, {c['roofline']['kernel_ms']:.3f} ms per run; trace / live = {avg / lv:.3f}); "
+                f"({cps.get('kernel_ms_per_pass', cps.get('kernel_ms')):.3f} ms per run; trace / live = {avg / lv:.3f}); "
                 f"value {c['value']:.0f} {c['unit']} ({c['ms_per_step']:.3f} ms per pass)."]
+        if dc and c["roofline"].get("kernel") == dom:
+            out += [f"Dominant kernel `{dom}` without the profiler: **{c['roofline']['avg_launch_us']:.1f} us** per launch "
+                    f"(`roofline.avg_launch_us`; trace / live = {dt / dc / c['roofline']['avg_launch_us']:.3f})."]
     open(args.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -157,10 +169,21 @@ def counters(path, name):
     return rows
 
 
+def pass_shape(b: dict):
+    """(step launches per pass, algorithmic bytes per pass) of a bench.py line."""
+    r = b["roofline"]
+    ps = r.get("pass", r)
+    n = int(ps.get("launches", r.get("launches_per_pass", 0)))
+    alg = ps.get("algorithmic_bytes_per_pass", ps.get("algorithmic_bytes"))
+    return n, alg
+
+
 def traffic(args):
     b = bench_line(args.log)
-    n = int(b["roofline"]["launches"])
+    n, alg = pass_shape(b)
+    per = b.get("per_launch") or []
     res = {}
+    per_launch_bytes = [0.0] * n
     for key, d, cname in (("fetch", args.fetch, "FETCH_SIZE"), ("write", args.write, "WRITE_SIZE")):
         rows = counters(os.path.join(d, "bench_counter_collection.csv"), cname)
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1024]
@@ -169,14 +192,26 @@ def traffic(args):
         scale = args.copy_mib * 1024.0 / float(copies[0]["Counter_Value"])   # true KiB / counter KiB
         steps = last_passes(rows, n, 1)
         kib = sum(float(r["Counter_Value"]) for r in steps)
+        for i, r in enumerate(steps):
+            per_launch_bytes[i] += float(r["Counter_Value"]) * 1024.0 * scale
         res[key] = {"scale": scale, "bytes": kib * 1024.0 * scale, "raw_kib": kib}
-    alg = b["roofline"]["algorithmic_bytes"]
     tr = res["fetch"]["bytes"] + res["write"]["bytes"]
+    # per kernel of the per-launch table (launches in program order, as the step dispatches)
+    by_kernel = {}
+    if len(per) == n:
+        for x, t in zip(per, per_launch_bytes):
+            k = by_kernel.setdefault(x["kernel"], {"launches": 0, "traffic_bytes": 0.0, "algorithmic_bytes": 0.0})
+            k["launches"] += 1
+            k["traffic_bytes"] += t
+            k["algorithmic_bytes"] += x["bytes"]
+        for k in by_kernel.values():
+            k["traffic_bytes_per_launch"] = k["traffic_bytes"] / k["launches"]
+            k["algorithmic_bytes_per_launch"] = k["algorithmic_bytes"] / k["launches"]
     rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "dtype": b["dtype"], "launches": n,
            "traffic_bytes_per_pass": tr, "algorithmic_bytes_per_pass": alg,
            "traffic_bytes_per_launch": tr / n, "fetch_bytes_per_launch": res["fetch"]["bytes"] / n,
            "write_bytes_per_launch": res["write"]["bytes"] / n, "algorithmic_bytes_per_launch": alg / n,
-           "fetch_scale": res["fetch"]["scale"], "write_scale": res["write"]["scale"]}
+           "fetch_scale": res["fetch"]["scale"], "write_scale": res["write"]["scale"], "by_kernel": by_kernel}
     json.dump(rec, open(args.json, "w"), indent=1)
     out = [f"# {args.title}", "", "Commands (from the repository root, on one MI355X; one counter per run):", ""]
     out += ["    " + c for c in args.command.split(" ;; ")]
@@ -191,6 +226,13 @@ def traffic(args):
             f"| HBM traffic | {tr / 1e9:.3f} GB | {tr / n / 1e6:.1f} MB |",
             f"| algorithmic bytes (every launch reads its input and writes its output once; a chain counts one pass) | {alg / 1e9:.3f} GB | {alg / n / 1e6:.1f} MB |", "",
             f"Traffic / algorithmic = **{tr / alg:.4f}**."]
+    if by_kernel:
+        out += ["", "Per kernel (the launches of the per-launch table, in program order):", "",
+                "| kernel | launches | HBM traffic per launch | algorithmic bytes per launch | ratio |", "|---|---|---|---|---|"]
+        for name, k in sorted(by_kernel.items(), key=lambda kv: -kv[1]["traffic_bytes"]):
+            out.append(f"| {name} | {k['launches']} | {k['traffic_bytes_per_launch'] / 1e6:.1f} MB | "
+                       f"{k['algorithmic_bytes_per_launch'] / 1e6:.1f} MB | "
+                       f"{k['traffic_bytes'] / k['algorithmic_bytes']:.4f} |")
     open(args.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -201,7 +243,7 @@ MOPS = ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS
 
 def mfma(args):
     b = bench_line(args.log)
-    n = int(b["roofline"]["launches"])
+    n, alg = pass_shape(b)
     per = b["per_launch"]
     if len(per) != n:
         raise SystemExit("bench line without a per-launch table of the program run")
@@ -239,7 +281,6 @@ def mfma(args):
     classes = {"chains": summary([r for r in rows if r["kernel"] == "chain"]),
                "large_contractions": summary([r for r in rows if r["flops"] >= 8 * r["bytes"]]),
                "all_step_launches": summary(rows)}
-    alg = b["roofline"].get("algorithmic_bytes_per_pass", b["roofline"].get("algorithmic_bytes"))
     rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "dtype": b["dtype"], "launches": n,
            "algorithmic_bytes_per_launch": alg / n, "source": args.out, **classes}
     json.dump(rec, open(args.json, "w"), indent=1)
