@@ -1183,45 +1183,70 @@ __device__ __forceinline__ double2 load_op(const void* B, int mode, int idx, int
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ items, int n_items,
-                                                    const LdsStep* __restrict__ steps) {
+constexpr int PERSIST_NT = 1024;  // 16 waves: the FP64 products of one component hide each other's latency
+
+__global__ __launch_bounds__(PERSIST_NT) void k_persistent(const LdsItem* __restrict__ items, int n_items,
+                                                           const LdsStep* __restrict__ steps) {
   __shared__ double2 buf[2][1 << LDS_RESIDENT_LOG2];
   __shared__ double2 sB[DMAXK * DMAXK];  // the step's operator, in FP64 (read K times per output)
-  __shared__ Tables tb;
-  __shared__ double rh[256], rl[256];
+  // the step's offset tables; LDS-resident tensors have at most 2^LDS_RESIDENT_LOG2 elements
+  __shared__ int offS[DMAXK], offN[DMAXK], offRA[DMAXR], offRC[DMAXR], hiA[DMAXHI], hiC[DMAXHI];
+  __shared__ double rh[PERSIST_NT], rl[PERSIST_NT];
   __shared__ double2 first;
+  const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const LdsItem item = items[it];
     int cur = -1;  // -1: the scalar 1
     double hi = 0.0, lo = 0.0;
-    if (threadIdx.x == 0) first = make_double2(0.0, 0.0);
+    if (tid == 0) first = make_double2(0.0, 0.0);
     for (int q = 0; q < item.count; ++q) {
       const LdsStep st = steps[item.first + q];
       const StepDesc* d = st.desc;
       const int kS = d->kS, kN = d->kN, L = d->L, nHi = d->nHi;
       const int K = 1 << kS, Nn = 1 << kN, R = 1 << L;
       __syncthreads();  // previous step complete before its tables and operator are replaced
-      load_tables(d, tb, K, Nn, R, nHi);
-      for (int i = threadIdx.x; i < K * Nn; i += blockDim.x) sB[i] = load_op(st.B, st.mode, i, K * Nn);
+      for (int i = tid; i < K; i += PERSIST_NT) offS[i] = int(d->offS_A[i]);
+      for (int i = tid; i < Nn; i += PERSIST_NT) offN[i] = int(d->offN_C[i]);
+      for (int i = tid; i < R; i += PERSIST_NT) {
+        offRA[i] = int(d->offR_A[i]);
+        offRC[i] = int(d->offR_C[i]);
+      }
+      for (int i = tid; i < nHi; i += PERSIST_NT) {
+        hiA[i] = d->hiA[i];
+        hiC[i] = d->hiC[i];
+      }
+      for (int i = tid; i < K * Nn; i += PERSIST_NT) sB[i] = load_op(st.B, st.mode, i, K * Nn);
       __syncthreads();
       const int dst = cur == 0 ? 1 : 0;
-      const long long total = d->nTiles << (kN + L);
-      for (long long o = threadIdx.x; o < total; o += blockDim.x) {
-        const int r = int(o & (R - 1));
-        const int n = int((o >> L) & (Nn - 1));
-        const long long t = o >> (L + kN);
-        long long bA = 0, bC = 0;
+      const int total = int(d->nTiles << (kN + L));
+      const double2* A = cur < 0 ? nullptr : buf[cur];
+      for (int o = tid; o < total; o += PERSIST_NT) {
+        const int r = o & (R - 1);
+        const int n = (o >> L) & (Nn - 1);
+        const int t = o >> (L + kN);
+        int bA = 0, bC = 0;
         for (int b = 0; b < nHi; ++b)
           if ((t >> b) & 1) {
-            bA |= 1LL << tb.hiA[b];
-            bC |= 1LL << tb.hiC[b];
+            bA |= 1 << hiA[b];
+            bC |= 1 << hiC[b];
           }
-        double2 acc = make_double2(0.0, 0.0);
-        for (int s2 = 0; s2 < K; ++s2) {
-          const double2 a = cur < 0 ? make_double2(1.0, 0.0) : buf[cur][bA + tb.offS[s2] + tb.offRA[r]];
-          acc = cfma(acc, a, sB[s2 * Nn + n]);
+        double2 acc;
+        if (!A) {  // the input is the scalar 1 (a first step: K = 1)
+          acc = make_double2(0.0, 0.0);
+          for (int s2 = 0; s2 < K; ++s2) acc = make_double2(acc.x + sB[s2 * Nn + n].x, acc.y + sB[s2 * Nn + n].y);
+        } else {
+          // two independent running sums (even / odd s) keep two FMA chains in flight
+          const int a0 = bA + offRA[r];
+          double2 e = make_double2(0.0, 0.0), f = make_double2(0.0, 0.0);
+          int s2 = 0;
+          for (; s2 + 1 < K; s2 += 2) {
+            e = cfma(e, A[a0 + offS[s2]], sB[s2 * Nn + n]);
+            f = cfma(f, A[a0 + offS[s2 + 1]], sB[(s2 + 1) * Nn + n]);
+          }
+          if (s2 < K) e = cfma(e, A[a0 + offS[s2]], sB[s2 * Nn + n]);
+          acc = make_double2(e.x + f.x, e.y + f.y);
         }
-        const long long oc = bC + tb.offN[n] + tb.offRC[r];
+        const int oc = bC + offN[n] + offRC[r];
         if (st.final_step) {
           item.out[oc] = acc;
           const double p = fma(acc.x, acc.x, acc.y * acc.y);
@@ -1237,21 +1262,21 @@ __global__ __launch_bounds__(256) void k_persistent(const LdsItem* __restrict__ 
       cur = dst;
     }
     // double-double reduction of the |t|^2 partial sums (fixed tree)
-    rh[threadIdx.x] = hi;
-    rl[threadIdx.x] = lo;
+    rh[tid] = hi;
+    rl[tid] = lo;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
+    for (int w = PERSIST_NT / 2; w > 0; w >>= 1) {
+      if (tid < w) {
         double sum, err;
-        two_sum(rh[threadIdx.x], rh[threadIdx.x + w], sum, err);
-        err += rl[threadIdx.x] + rl[threadIdx.x + w];
+        two_sum(rh[tid], rh[tid + w], sum, err);
+        err += rl[tid] + rl[tid + w];
         const double h2 = sum + err;
-        rl[threadIdx.x] = err - (h2 - sum);
-        rh[threadIdx.x] = h2;
+        rl[tid] = err - (h2 - sum);
+        rh[tid] = h2;
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       item.sums[0] = rh[0];
       item.sums[1] = rl[0];
       item.sums[2] = first.x;
@@ -1630,7 +1655,7 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void*
 hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   const int grid = n_items < 2048 ? n_items : 2048;
-  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(256), 0, stream, items, n_items, steps);
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(PERSIST_NT), 0, stream, items, n_items, steps);
   return hipGetLastError();
 }
 
