@@ -684,13 +684,14 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
 // the step's untouched tile bits f; its outputs overwrite exactly the elements it read, after the
 // wave has read all of them (the products consume every read before any write), and the units of
 // different waves are disjoint.
-template <int NT, int KQ, int MB>
+// KS > 0 fixes the step's kS at compile time (then the padding tests fold away); KS = 0 reads it.
+template <int NT, int KQ, int MB, int KS>
 __device__ __forceinline__ void chain_step(float2* tile, const float2* __restrict__ B, const ChainStepDesc& sd,
                                            int T) {
   using M = Mfma<float>;
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15, wave = threadIdx.x >> 6;
-  const int K = 1 << sd.kS;
+  const int K = KS > 0 ? 1 << KS : 1 << sd.kS;
   const int units = 1 << (T - sd.kS - 4);
   for (int u = wave; u < units; u += NW) {
     const int f = (u << 4) + l16;
@@ -1051,10 +1052,10 @@ __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, cons
       } else {
         const float2* Bj = reinterpret_cast<const float2*>(smem) + sd[j].boff;
         switch (sd[j].kS) {
-          case 5: chain_step<NT, 8, 2>(tile, Bj, sd[j], T); break;
-          case 4: chain_step<NT, 4, 1>(tile, Bj, sd[j], T); break;
-          case 3: chain_step<NT, 2, 1>(tile, Bj, sd[j], T); break;
-          default: chain_step<NT, 1, 1>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+          case 5: chain_step<NT, 8, 2, 5>(tile, Bj, sd[j], T); break;
+          case 4: chain_step<NT, 4, 1, 4>(tile, Bj, sd[j], T); break;
+          case 3: chain_step<NT, 2, 1, 3>(tile, Bj, sd[j], T); break;
+          default: chain_step<NT, 1, 1, 0>(tile, Bj, sd[j], T); break;  // kS = 1, 2
         }
       }
       __syncthreads();  // step j complete on the whole tile

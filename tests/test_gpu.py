@@ -833,6 +833,33 @@ def test_graph_replays_match_eager_runs():
         assert abs(a["fj"] - want["fj"]) <= TOL[dtype]
 
 
+def test_small_components_beside_the_step_program():
+    """A plan with LDS-resident components and a step program (the 36-qubit chain: five small
+    components, one of 2^12 elements): the persistent launch runs on a forked stream beside the
+    steps, eagerly and inside the captured graph; every replay and every eager run agree bitwise,
+    and with the exact F_J of the Clifford twin."""
+    import torch
+    twin = gen.clifford_twin(gen.config5(), 5)
+    want = clifford.fidelity(twin)["fj"]
+    for dtype in ("c128", "c64"):
+        eager_plan = jf.plan(twin, 2, dtype)
+        lds = eager_plan.stats()["n_components"]
+        assert lds >= 2
+        ws = jf.workspace(eager_plan.info()["workspace_bytes"])
+        ref = jf.jf_fidelity_alg2(eager_plan, ws)
+        assert abs(ref["fj"] - want) <= TOL[dtype], (dtype, ref["fj"] - want)
+        p = jf.plan(twin, 2, dtype, flags=jf.JF_FLAG_GRAPH)
+        ws2 = jf.workspace(p.info()["workspace_bytes"])
+        side = torch.cuda.Stream()
+        for i in range(6):
+            say("side-stream persistent launch", dtype, "replay", i)
+            got = jf.jf_fidelity_alg2(p, ws2, side if i % 2 else None)
+            assert got["fj"] == ref["fj"], (dtype, i)
+            again = jf.jf_fidelity_alg2(eager_plan, ws)
+            assert again["fj"] == ref["fj"], (dtype, i)
+            torch.cuda.synchronize()
+
+
 def test_intermediates_beyond_2_31_elements():
     """A 2^32-element intermediate (32 GiB in complex64, 64 GiB in complex128: 64-bit offsets
     throughout): the Clifford twin of a 20-qubit member of the batch, planned with a 2^32 cap,
