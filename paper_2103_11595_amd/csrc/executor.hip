@@ -765,11 +765,10 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, unsigned char* bufs, 
 // The plan's side stream and its fork / join events (created on first use, default priority).
 jf_status side_of(jf_plan* p, hipStream_t* side) {
   DevState& S = state_of(p);
-  if (!S.side_stream) {
-    JF_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
-    JF_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
-    JF_HIP(hipStreamCreateWithFlags(&S.side_stream, hipStreamNonBlocking));
-  }
+  // each object once (a failure part-way leaves the ones made for the next call to keep)
+  if (!S.ev_fork) JF_HIP(hipEventCreateWithFlags(&S.ev_fork, hipEventDisableTiming));
+  if (!S.ev_join) JF_HIP(hipEventCreateWithFlags(&S.ev_join, hipEventDisableTiming));
+  if (!S.side_stream) JF_HIP(hipStreamCreateWithFlags(&S.side_stream, hipStreamNonBlocking));
   *side = S.side_stream;
   return JF_OK;
 }
