@@ -301,7 +301,9 @@ jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* s
  * and stores of bytes_per_lane per lane, a resident grid striding over the buffer -- and returns its
  * duration in *ms (HIP events attached to the dispatch).  2 bytes / ms is the HBM rate the step
  * kernels' access pattern can reach, the ceiling their per-launch rates are set against.
- * Synchronises the stream.  Errors: JF_E_ARG, JF_E_HIP.
+ * Synchronises the stream; bytes = 0 copies nothing and returns 0 ms.  Errors: JF_E_ARG (a NULL
+ * pointer, a buffer not 16-byte aligned, bytes_per_lane other than 8 or 16, bytes not a multiple of
+ * it: checked before anything is launched), JF_E_HIP.
  */
 jf_status jf_stream_copy(const void* src, void* dst, size_t bytes, int bytes_per_lane, void* stream, double* ms);
 

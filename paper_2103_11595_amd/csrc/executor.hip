@@ -1083,6 +1083,10 @@ extern "C" jf_status jf_fidelity_noalloc(jf_plan* p, void* stream_v, jf_result* 
 
 extern "C" jf_status jf_stream_copy(const void* src, void* dst, size_t bytes, int bytes_per_lane, void* stream_v,
                                     double* ms) {
+  if (ms && bytes == 0 && (bytes_per_lane == 8 || bytes_per_lane == 16)) {  // nothing to copy, no launch
+    *ms = 0.0;
+    return JF_OK;
+  }
   if (!src || !dst || !ms || (bytes_per_lane != 8 && bytes_per_lane != 16) || bytes % size_t(bytes_per_lane) ||
       (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16) {
     set_error("jf_stream_copy: bad argument (16-byte aligned buffers, bytes a multiple of 8 or 16 bytes per lane)");

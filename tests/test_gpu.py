@@ -833,6 +833,28 @@ def test_graph_replays_match_eager_runs():
         assert abs(a["fj"] - want["fj"]) <= TOL[dtype]
 
 
+def test_stream_copy_copies_exactly_and_checks_its_arguments():
+    # the HBM-ceiling measurement copies every byte, at 16 and 8 bytes per lane, over a size that
+    # is no multiple of the grid's stride; malformed requests are refused before any launch
+    import torch
+    n = 3 * 2**20 + 48
+    g = torch.Generator(device="cuda").manual_seed(11)
+    src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+    for bpl in (16, 8):
+        dst = torch.zeros_like(src)
+        ms = jf.jf_stream_copy(src, dst, bpl)
+        torch.cuda.synchronize()
+        assert ms > 0 and torch.equal(dst, src), bpl
+    empty = torch.empty(0, dtype=torch.uint8, device="cuda")
+    assert jf.jf_stream_copy(empty, empty, 16) == 0.0
+    for bad in (lambda: jf.jf_stream_copy(src[:24], torch.zeros(24, dtype=torch.uint8, device="cuda"), 16),
+                lambda: jf.jf_stream_copy(src, torch.zeros_like(src), 4),
+                lambda: jf.jf_stream_copy(src[8:8 + 1024], torch.zeros(1024, dtype=torch.uint8, device="cuda"), 8)):
+        with pytest.raises(jf.JfError) as e:
+            bad()
+        assert e.value.status == -1
+
+
 def test_small_components_beside_the_step_program():
     """A plan with LDS-resident components and a step program (the 36-qubit chain: five small
     components, one of 2^12 elements): the persistent launch runs on a forked stream beside the

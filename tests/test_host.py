@@ -111,6 +111,91 @@ def test_profile_summary_finds_the_pass_period():
         profsum.period(["a", "b", "c", "d", "e", "f", "g"])
 
 
+def _write_counters(d, name, rows):
+    import csv
+    import os
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "bench_counter_collection.csv"), "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (kernel, value) in enumerate(rows):
+            w.writerow([i + 1, kernel, name, value])
+
+
+def test_profile_summary_traffic_per_kernel(tmp_path):
+    # synthetic counter runs: a 4 MiB calibration copy whose FETCH_SIZE reads twice the bytes, an
+    # autotuner launch to be skipped, then one program run of three step launches; the summary
+    # scales every launch by the copy's factor and groups the launches by the per-launch table
+    import json
+    from argparse import Namespace
+    from paper_2103_11595_amd import profsum
+    per = [{"kernel": "gauss512", "bytes": 1000.0}, {"kernel": "chain", "bytes": 4000.0},
+           {"kernel": "gauss512", "bytes": 2000.0}]
+    line = {"value": 1.0, "unit": "u", "ms_per_step": 1.0, "dtype": "c64", "config": {"workload": "w"},
+            "roofline": {"kernel": "k_chain<256>", "pass": {"launches": 3, "algorithmic_bytes_per_pass": 7000.0}},
+            "per_launch": per}
+    log = tmp_path / "b.log"
+    log.write_text("noise\n" + json.dumps(line) + "\n")
+    steps = [("void jf::k_absorb_mfma_gauss<float>(...)", 0.5), ("void jf::k_chain<256>(...)", 2.0),
+             ("void jf::k_absorb_mfma_gauss<float>(...)", 1.0)]
+    _write_counters(str(tmp_path / "f"), "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 8192.0),
+                                                      ("void jf::k_absorb_mfma<tune>(...)", 99.0)] + steps)
+    _write_counters(str(tmp_path / "w"), "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 4096.0),
+                                                      ("void jf::k_absorb_mfma<tune>(...)", 99.0)] + steps)
+    out, js = tmp_path / "t.md", tmp_path / "t.json"
+    profsum.traffic(Namespace(fetch=str(tmp_path / "f"), write=str(tmp_path / "w"), log=str(log), copy_mib=4,
+                              out=str(out), json=str(js), title="t", command="c"))
+    rec = json.loads(js.read_text())
+    assert rec["fetch_scale"] == 0.5 and rec["write_scale"] == 1.0
+    # per launch: fetch KiB x 0.5 + write KiB x 1.0, times 1024
+    want = [1024 * (v * 0.5 + v) for _, v in steps]
+    assert abs(rec["traffic_bytes_per_pass"] - sum(want)) < 1e-6
+    assert rec["by_kernel"]["chain"] == {"launches": 1, "traffic_bytes": want[1], "algorithmic_bytes": 4000.0,
+                                         "traffic_bytes_per_launch": want[1], "algorithmic_bytes_per_launch": 4000.0}
+    g = rec["by_kernel"]["gauss512"]
+    assert g["launches"] == 2 and abs(g["traffic_bytes_per_launch"] - (want[0] + want[2]) / 2) < 1e-9
+    assert "| chain | 1 |" in out.read_text()
+
+
+def test_profile_summary_mfma_classes(tmp_path):
+    # one counted program run (an earlier autotuner dispatch skipped): executed matrix-core flops
+    # are 512 x the MOPS counters, MfmaUtil is weighted by each launch's time, and the live run's
+    # times are used when its launch sequence is the same
+    import csv
+    import json
+    from argparse import Namespace
+    from paper_2103_11595_amd import profsum
+    per = [{"kernel": "chain", "kS": 5, "kN": 5, "L": 12, "steps": 2, "bytes": 100.0, "flops": 4000.0, "us": 9.0},
+           {"kernel": "gauss512", "kS": 4, "kN": 6, "L": 7, "steps": 1, "bytes": 100.0, "flops": 900.0, "us": 9.0},
+           {"kernel": "fma", "kS": 2, "kN": 2, "L": 4, "steps": 1, "bytes": 100.0, "flops": 10.0, "us": 9.0}]
+    line = {"value": 1.0, "unit": "u", "ms_per_step": 1.0, "dtype": "c64", "config": {"workload": "w"},
+            "roofline": {"pass": {"launches": 3, "algorithmic_bytes_per_pass": 300.0}}, "per_launch": per}
+    live = dict(line, per_launch=[dict(x, us=u) for x, u in zip(per, (3.0, 1.0, 1.0))])
+    (tmp_path / "p.log").write_text(json.dumps(line) + "\n")
+    (tmp_path / "l.log").write_text(json.dumps(live) + "\n")
+    d = tmp_path / "m"
+    d.mkdir()
+    with open(d / "bench_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        rows = [(1, "void jf::k_absorb_mfma<tune>(...)", 50.0, 7.0),
+                (2, "void jf::k_chain<256>(...)", 60.0, 6.0),
+                (3, "void jf::k_absorb_mfma_gauss<float>(...)", 20.0, 1.0),
+                (4, "void jf::k_absorb<float>(...)", 0.0, 0.0)]
+        for i, k, util, mops in rows:
+            w.writerow([i, k, "MfmaUtil", util])
+            w.writerow([i, k, "SQ_INSTS_VALU_MFMA_MOPS_F32", mops])
+    profsum.mfma(Namespace(dir=str(d), log=str(tmp_path / "p.log"), live_log=str(tmp_path / "l.log"),
+                           out=str(tmp_path / "m.md"), json=str(tmp_path / "m.json"), title="t", command="c"))
+    rec = json.loads((tmp_path / "m.json").read_text())
+    ch = rec["chains"]
+    assert ch["launches"] == 1 and ch["us"] == 3.0
+    assert abs(ch["executed_mfma_tflops"] - 512 * 6.0 / 3.0 / 1e6) < 1e-15
+    big = rec["large_contractions"]   # flops >= 8 x bytes: the chain and the Gauss step
+    assert big["launches"] == 2 and abs(big["mfma_busy_pct_time_weighted"] - (60.0 * 3 + 20.0 * 1) / 4) < 1e-12
+    assert rec["all_step_launches"]["launches"] == 3
+
+
 def test_workspace_release_is_host_only():
     import ctypes as C
     L = jf.lib()
