@@ -78,6 +78,11 @@ struct DevState {
   // pinned host landing area of the component sums (4 doubles each): a pageable destination
   // costs the runtime a staging copy on every call, which small programs feel
   double* pinned_sums = nullptr;
+  // pinned host landing area of F_J, 1 - F_J, |Im| (4 doubles), written by the assembly kernel
+  // itself: allocated before the first enqueue of the allocating entry points, so every program
+  // enqueued or captured after that writes it
+  double* pinned_res = nullptr;
+  double* pinned_res_dev = nullptr;  // its device address (hipHostGetDevicePointer)
 };
 
 std::atomic<unsigned> g_variant_gen{1};
@@ -799,7 +804,7 @@ jf_status enqueue_assemble(jf_plan* p, unsigned char* ws, hipStream_t stream) {
   const cd v0 = s * P.scalar;
   JF_HIP(launch_assemble(reinterpret_cast<const double*>(ws + L.sums_off), int(P.comps.size()), P.opt.alg,
                          s * s * std::norm(P.scalar), v0.real(), v0.imag(), reinterpret_cast<double*>(ws + L.res_off),
-                         stream));
+                         state_of(p).pinned_res_dev, stream));
   return JF_OK;
 }
 
@@ -885,20 +890,37 @@ jf_status pinned_sums(jf_plan* p, double** out) {
   return JF_OK;
 }
 
-// Copy the component sums (and, with terms, the per-tuple outputs) back and assemble F_J.  The sums
-// land in the plan's pinned area unless pinned is false (then straight into pageable host memory:
-// no host allocation by the library, as the no-allocation entry point needs).
+// Coherent (fine-grained) pinned memory: the assembly kernel's four stores reach the host without
+// any cache flush, and the host reads them after the stream synchronisation.
+jf_status pinned_res_of(jf_plan* p) {
+  DevState& S = state_of(p);
+  if (!S.pinned_res) {
+    double* h = nullptr;
+    JF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h), 4 * sizeof(double), hipHostMallocCoherent));
+    void* d = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess || !d) {
+      (void)hipHostFree(h);
+      set_error(std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
+      return JF_E_HIP;
+    }
+    S.pinned_res = h;
+    S.pinned_res_dev = static_cast<double*>(d);
+  }
+  return JF_OK;
+}
+
+// Wait for the run and read F_J back (with terms, also the per-tuple outputs).  With pinned, the
+// assembly kernel has written the result into the plan's pinned landing area (pinned_res_of before
+// the enqueue), so only the terms need a copy; without (the no-allocation entry point: no host
+// allocation by the library), the result is copied into pageable host memory.
 jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_result* out, double* terms,
                        bool pinned = true) {
   const Program& P = p->prog;
   DevState& S = state_of(p);
   double res[4];
-  double* land = res;
-  if (pinned) {
-    const jf_status ps = pinned_sums(p, &land);
-    if (ps != JF_OK) return ps;
-  }
-  JF_HIP(hipMemcpyAsync(land, ws + S.lay.res_off, sizeof(res), hipMemcpyDeviceToHost, stream));
+  const bool on_host = pinned && S.pinned_res;
+  if (!on_host) JF_HIP(hipMemcpyAsync(res, ws + S.lay.res_off, sizeof(res), hipMemcpyDeviceToHost, stream));
   std::vector<std::vector<cd>> co;
   if (terms) {
     for (auto& cp : P.comps) {
@@ -909,7 +931,7 @@ jf_status read_results(jf_plan* p, unsigned char* ws, hipStream_t stream, jf_res
     }
   }
   JF_HIP(hipStreamSynchronize(stream));
-  if (pinned) std::memcpy(res, land, sizeof(res));
+  if (on_host) std::memcpy(res, S.pinned_res, sizeof(res));
   jf_result r;
   static_result(P, &r);
   r.fj = res[0];
@@ -928,6 +950,8 @@ jf_status run_one(jf_plan* p, void* ws, size_t ws_bytes, hipStream_t stream, jf_
   jf_status st = check_ws(p, ws, ws_bytes);
   if (st != JF_OK) return st;
   st = upload(p, ws, stream);
+  if (st != JF_OK) return st;
+  st = pinned_res_of(p);  // before any enqueue or capture: the assembly writes the result there
   if (st != JF_OK) return st;
   DevState& S = state_of(p);
   if (!S.ev0) {
@@ -1254,6 +1278,8 @@ extern "C" jf_status jf_decide_equivalence(jf_plan* p, double eps, void* ws, siz
         last = int(c);
       }
   if (last < 0) {  // one pass computes every term
+    st = pinned_res_of(p);
+    if (st != JF_OK) return st;
     st = enqueue_program(p, w, stream);
     if (st != JF_OK) return st;
     jf_result r;
@@ -1461,6 +1487,8 @@ extern "C" jf_status jf_fidelity_batch(jf_plan* const* plans, int n, void* ws, s
     if (st != JF_OK) return st;
     st = upload(plans[i], base[i], stream, state_of(plans[i]).lay.buf_off);
     if (st != JF_OK) return st;
+    st = pinned_res_of(plans[i]);  // before the capture: each member's assembly writes its result there
+    if (st != JF_OK) return st;
   }
   // every small component of every plan in one persistent launch
   std::vector<LdsItem> items;
@@ -1582,6 +1610,7 @@ extern "C" void jf_free_plan(jf_plan* p) {
     for (hipEvent_t e : {s->ev0, s->ev1, s->ev_order, s->ev_fork, s->ev_join})
       if (e) hipEventDestroy(e);
     if (s->pinned_sums) hipHostFree(s->pinned_sums);
+    if (s->pinned_res) hipHostFree(s->pinned_res);
     {
       std::lock_guard<std::mutex> g(g_upload_mu);
       for (auto it = g_last_upload.begin(); it != g_last_upload.end();)

@@ -153,9 +153,10 @@ hipError_t launch_zero(void* out, long long n_double2, hipStream_t stream);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bpl, hipStream_t stream, hipEvent_t ev0,
                               hipEvent_t ev1);
 // res[0..3] = F_J, 1 - F_J, |Im| (Algorithm II), 0 from the components' sums (4 doubles each:
-// double-double sum of |t|^2, first entry): the product over components on the device
+// double-double sum of |t|^2, first entry): the product over components on the device; host, if not
+// null, is pinned host memory that receives the same four values
 hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
-                           hipStream_t stream);
+                           double* host, hipStream_t stream);
 // out[i] += part[i] for i < n (double2 entries): a leaf's partial result of sliced wires
 hipError_t launch_accumulate(void* out, const void* part, long long n_double2, hipStream_t stream);
 

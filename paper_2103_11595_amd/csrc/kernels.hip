@@ -1138,6 +1138,28 @@ __global__ __launch_bounds__(256) void k_sumsq_part(const double2* x, long long 
   }
 }
 
+// The same sum over a small output in one block: the chunk loop of k_sumsq_part over everything,
+// the fixed tree, and the first entry beside it.
+__global__ __launch_bounds__(256) void k_sumsq_one(const double2* x, long long n, double* out) {
+  __shared__ double sh[256], sl[256];
+  double hi = 0.0, lo = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) {
+    const double2 v = ld_stream(&x[i]);
+    const double p = fma(v.x, v.x, v.y * v.y);
+    double s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo += e;
+  }
+  dd_tree256(sh, sl, hi, lo);
+  if (threadIdx.x == 0) {
+    out[0] = sh[0];
+    out[1] = sl[0];
+    out[2] = n > 0 ? x[0].x : 0.0;
+    out[3] = n > 0 ? x[0].y : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sumsq_final(const double* part, int G, const double2* x, long long n,
                                                      double* out) {
   __shared__ double sh[256], sl[256];
@@ -1705,7 +1727,8 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bpl,
 // squared modulus of the traced-out scalar), F_J = hi + lo and 1 - F_J = (1 - hi) - lo, where 1 - hi
 // is exact for hi in [0.5, 2] (Sterbenz).  Algorithm II: T / d^2 = v0 prod_c value_c (complex),
 // F_J = Re, 1 - F_J = 1 - Re (exact for Re in [0.5, 2]), |Im| the residual.  res[0..2].
-__global__ void k_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res) {
+__global__ void k_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
+                           double* host) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (alg == 1) {
     double hi = a, lo = 0.0;
@@ -1732,11 +1755,13 @@ __global__ void k_assemble(const double* sums, int ncomp, int alg, double a, dou
     res[2] = fabs(vi);
   }
   res[3] = 0.0;
+  if (host)  // the caller's pinned host landing area: the result needs no copy back
+    for (int i = 0; i < 4; ++i) host[i] = res[i];
 }
 
 hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
-                           hipStream_t stream) {
-  hipLaunchKernelGGL(k_assemble, dim3(1), dim3(64), 0, stream, sums, ncomp, alg, a, v0re, v0im, res);
+                           double* host, hipStream_t stream) {
+  hipLaunchKernelGGL(k_assemble, dim3(1), dim3(64), 0, stream, sums, ncomp, alg, a, v0re, v0im, res, host);
   return hipGetLastError();
 }
 
@@ -1764,9 +1789,13 @@ hipError_t launch_zero(void* out, long long n, hipStream_t stream) {
 }
 
 hipError_t launch_sumsq(const void* x, long long n, double* sums, double* scratch, hipStream_t stream) {
-  // at least 16K elements per block, at most SUMSQ_BLOCKS blocks
+  // at least 16K elements per block, at most SUMSQ_BLOCKS blocks; one block takes a small output
+  // whole, in one launch
   long long G = (n + 16383) / 16384;
-  if (G < 1) G = 1;
+  if (G <= 1) {
+    hipLaunchKernelGGL(k_sumsq_one, dim3(1), dim3(256), 0, stream, (const double2*)x, n, sums);
+    return hipGetLastError();
+  }
   if (G > SUMSQ_BLOCKS) G = SUMSQ_BLOCKS;
   const long long chunk = n > 0 ? (n + G - 1) / G : 0;
   hipLaunchKernelGGL(k_sumsq_part, dim3(unsigned(G)), dim3(256), 0, stream, (const double2*)x, n, chunk, scratch);
