@@ -39,6 +39,7 @@ struct DevLayout {
   size_t sumsq_off = 0;  // scratch of the two-pass sum of |t|^2 (2 SUMSQ_BLOCKS doubles)
   size_t res_off = 0;    // F_J, 1 - F_J, |Im|, written by the device
   size_t lds_items_off = 0, lds_steps_off = 0;
+  size_t ctr_off = 0;    // counter of the persistent launch's fused assembly (zero in the image)
   std::vector<size_t> leaf_off;                           // per component with sliced wires: its leaf buffer
   std::vector<int> lds_comps;                             // components run by the persistent kernel
   int lds_steps = 0;
@@ -299,6 +300,8 @@ void build_layout(const Program& P, DevState& S) {
   off += align256(L.lds_comps.size() * sizeof(LdsItem));
   L.lds_steps_off = off;
   off += align256(size_t(L.lds_steps) * sizeof(LdsStep));
+  L.ctr_off = off;
+  off += 256;
   L.image_end = off;
   L.out_off = off;
   long long outn = 0;
@@ -796,15 +799,29 @@ jf_status launch_persistent_beside(const LdsItem* items, int n, const LdsStep* s
 // Enqueue one whole pass of a plan.  side: a stream for the persistent launch of the small
 // components, which then overlaps the other components' steps (one workgroup per component, so
 // it leaves the rest of the device to them); null runs everything on `stream` in order.
-// The product over components and 1 - F_J of a plan, on the device (after all its components).
-jf_status enqueue_assemble(jf_plan* p, unsigned char* ws, hipStream_t stream) {
+// Arguments of the assembly of a plan's F_J from its component sums (device addresses in ws).
+AssembleArgs assemble_args(jf_plan* p, unsigned char* ws) {
   const Program& P = p->prog;
-  const DevLayout& L = state_of(p).lay;
+  const DevState& S = state_of(p);
   const double s = std::exp2(P.log2_scale);  // exact: an integer power of two
   const cd v0 = s * P.scalar;
-  JF_HIP(launch_assemble(reinterpret_cast<const double*>(ws + L.sums_off), int(P.comps.size()), P.opt.alg,
-                         s * s * std::norm(P.scalar), v0.real(), v0.imag(), reinterpret_cast<double*>(ws + L.res_off),
-                         state_of(p).pinned_res_dev, stream));
+  AssembleArgs a;
+  a.sums = reinterpret_cast<const double*>(ws + S.lay.sums_off);
+  a.ncomp = int(P.comps.size());
+  a.alg = P.opt.alg;
+  a.a = s * s * std::norm(P.scalar);
+  a.v0re = v0.real();
+  a.v0im = v0.imag();
+  a.res = reinterpret_cast<double*>(ws + S.lay.res_off);
+  a.host = S.pinned_res_dev;
+  a.counter = reinterpret_cast<unsigned*>(ws + S.lay.ctr_off);
+  return a;
+}
+
+// The product over components and 1 - F_J of a plan, on the device (after all its components).
+jf_status enqueue_assemble(jf_plan* p, unsigned char* ws, hipStream_t stream) {
+  const AssembleArgs a = assemble_args(p, ws);
+  JF_HIP(launch_assemble(a.sums, a.ncomp, a.alg, a.a, a.v0re, a.v0im, a.res, a.host, stream));
   return JF_OK;
 }
 
@@ -816,6 +833,14 @@ jf_status enqueue_program(jf_plan* p, unsigned char* ws, hipStream_t stream, Pro
   const DevLayout& L = S.lay;
   if (!bufs) bufs = ws + L.buf_off;
   const bool lds = !skip_lds && !L.lds_comps.empty();
+  if (lds && assemble && L.lds_comps.size() == P.comps.size()) {
+    // every component in the persistent launch, which also assembles: one launch per run
+    JF_HIP(launch_persistent_assemble(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off),
+                                      int(L.lds_comps.size()),
+                                      reinterpret_cast<const LdsStep*>(ws + L.lds_steps_off), assemble_args(p, ws),
+                                      stream));
+    return JF_OK;
+  }
   if (!lds) side = nullptr;
   if (lds) {
     const jf_status st = launch_persistent_beside(reinterpret_cast<const LdsItem*>(ws + L.lds_items_off),

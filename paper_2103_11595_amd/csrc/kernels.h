@@ -140,7 +140,21 @@ struct LdsItem {
   double* sums;       // 4 doubles
   long long out_len;
 };
+// The assembly of F_J from a plan's component sums (see launch_assemble), passed by value.
+struct AssembleArgs {
+  const double* sums;
+  int ncomp, alg;
+  double a, v0re, v0im;
+  double* res;
+  double* host;        // pinned host landing area or null
+  unsigned* counter;   // zero before the launch, zero again after it (the last workgroup resets it)
+};
 hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream);
+// The same launch, ending with the assembly: the last workgroup to finish (counted on *counter)
+// assembles F_J from every item's sums -- for plans whose components are all LDS-resident, one
+// launch per run.
+hipError_t launch_persistent_assemble(const LdsItem* items, int n_items, const LdsStep* steps,
+                                      const AssembleArgs& as, hipStream_t stream);
 
 // Attach a start / stop event pair to the step-kernel launches of this thread (nullptr, nullptr
 // to stop): the events then bracket the kernel execution itself.

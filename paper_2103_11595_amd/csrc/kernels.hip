@@ -1208,8 +1208,11 @@ __device__ __forceinline__ double2 load_op(const void* B, int mode, int idx, int
 
 constexpr int PERSIST_NT = 1024;  // 16 waves: the FP64 products of one component hide each other's latency
 
+__device__ void assemble_result(const double* sums, int ncomp, int alg, double a, double v0re, double v0im,
+                                double* res, double* host);
+
 __global__ __launch_bounds__(PERSIST_NT) void k_persistent(const LdsItem* __restrict__ items, int n_items,
-                                                           const LdsStep* __restrict__ steps) {
+                                                           const LdsStep* __restrict__ steps, AssembleArgs as) {
   __shared__ double2 buf[2][1 << LDS_RESIDENT_LOG2];
   __shared__ double2 sB[DMAXK * DMAXK];  // the step's operator, in FP64 (read K times per output)
   // the step's offset tables; LDS-resident tensors have at most 2^LDS_RESIDENT_LOG2 elements
@@ -1306,6 +1309,14 @@ __global__ __launch_bounds__(PERSIST_NT) void k_persistent(const LdsItem* __rest
       item.sums[3] = first.y;
     }
     __syncthreads();
+  }
+  if (as.counter && tid == 0) {
+    // release this workgroup's sums, count it; the last one acquires every sum and assembles
+    const unsigned done = __hip_atomic_fetch_add(as.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      assemble_result(as.sums, as.ncomp, as.alg, as.a, as.v0re, as.v0im, as.res, as.host);
+      __hip_atomic_store(as.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next run
+    }
   }
 }
 
@@ -1678,7 +1689,15 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void*
 hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   const int grid = n_items < 2048 ? n_items : 2048;
-  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(PERSIST_NT), 0, stream, items, n_items, steps);
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(PERSIST_NT), 0, stream, items, n_items, steps, AssembleArgs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent_assemble(const LdsItem* items, int n_items, const LdsStep* steps,
+                                      const AssembleArgs& as, hipStream_t stream) {
+  if (n_items <= 0 || !as.counter) return hipErrorInvalidValue;
+  const int grid = n_items < 2048 ? n_items : 2048;
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(PERSIST_NT), 0, stream, items, n_items, steps, as);
   return hipGetLastError();
 }
 
@@ -1727,9 +1746,8 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int bpl,
 // squared modulus of the traced-out scalar), F_J = hi + lo and 1 - F_J = (1 - hi) - lo, where 1 - hi
 // is exact for hi in [0.5, 2] (Sterbenz).  Algorithm II: T / d^2 = v0 prod_c value_c (complex),
 // F_J = Re, 1 - F_J = 1 - Re (exact for Re in [0.5, 2]), |Im| the residual.  res[0..2].
-__global__ void k_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
-                           double* host) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void assemble_result(const double* sums, int ncomp, int alg, double a, double v0re, double v0im,
+                                double* res, double* host) {
   if (alg == 1) {
     double hi = a, lo = 0.0;
     for (int c = 0; c < ncomp; ++c) {
@@ -1757,6 +1775,12 @@ __global__ void k_assemble(const double* sums, int ncomp, int alg, double a, dou
   res[3] = 0.0;
   if (host)  // the caller's pinned host landing area: the result needs no copy back
     for (int i = 0; i < 4; ++i) host[i] = res[i];
+}
+
+__global__ void k_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
+                           double* host) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  assemble_result(sums, ncomp, alg, a, v0re, v0im, res, host);
 }
 
 hipError_t launch_assemble(const double* sums, int ncomp, int alg, double a, double v0re, double v0im, double* res,
