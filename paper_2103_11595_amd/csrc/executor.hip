@@ -743,7 +743,15 @@ jf_status enqueue_component(jf_plan* p, unsigned char* ws, unsigned char* bufs, 
                             Tune* tune) {
   const ComponentProgram& cp = p->prog.comps[c];
   const DevLayout& L = state_of(p).lay;
-  JF_HIP(launch_zero(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len, stream));
+  // Every output entry is written by the final steps of the leaves, except where leaves add
+  // partial traces into it (sliced wires) or a site's Kraus count is no power of two (padded
+  // variants): only then is the output cleared first.
+  bool clear = cp.accumulate;
+  for (size_t site = 0; site < cp.out_bit.size() && site < p->prog.site_nk.size() && !clear; ++site) {
+    const int nk = p->prog.site_nk[site];
+    if (!cp.out_bit[site].empty() && (nk & (nk - 1))) clear = true;
+  }
+  if (clear) JF_HIP(launch_zero(ws + L.out_off + size_t(cp.out_off) * 16, cp.out_len, stream));
   struct Frame {
     int lv;
     int v;

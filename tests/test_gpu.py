@@ -833,6 +833,41 @@ def test_graph_replays_match_eager_runs():
         assert abs(a["fj"] - want["fj"]) <= TOL[dtype]
 
 
+def test_outputs_fully_written_on_a_poisoned_workspace():
+    # components whose outputs the final steps write whole skip clearing them: on a workspace
+    # filled with NaN bytes every term must still come out right -- open and sliced sites (power-of-
+    # two Kraus counts), Algorithm II, and a three-operator set (padded, so cleared)
+    import torch
+    cases = []
+    inst = gen.random_circuit(6, 90, 4, 1e-3, 0.1, 4242)
+    need = int(jf.plan(inst, 1, "c128").info()["max_log2_intermediate"])
+    cases.append((inst, 1, 0))
+    cases.append((inst, 1, need - 2))            # sliced sites
+    cases.append((inst, 2, 0))
+    pad = gen.random_circuit(4, 50, 2, 0.05, 0.2, 4243)
+    three = [k.tolist() for k in dense.kraus_set("bit_phase_flip", 0.3)] + [[[0, 0], [0, 0]]]
+    pad["noise"] = [dict(site, kraus=three) for site in pad["noise"]]
+    cases.append((pad, 1, 0))
+    for inst, alg, cap in cases:
+        for dtype in ("c128", "c64"):
+            p = jf.plan(inst, alg, dtype, max_log2=cap)
+            ws = jf.workspace(p.info()["workspace_bytes"])
+            ws.fill_(255)                          # NaN in every double
+            torch.cuda.synchronize()
+            jf.jf_workspace_release(ws)
+            say("poisoned workspace", inst["n"], "alg", alg, "cap", cap, dtype)
+            if alg == 1:
+                ref = dense.fidelity_alg1(inst, want_terms=True)
+                got = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+                assert np.all(np.isfinite(got["terms"]))
+                if dtype == "c128":
+                    assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-12
+            else:
+                ref = dense.fidelity_alg2(inst)
+                got = jf.jf_fidelity_alg2(p, ws)
+            assert abs(got["fj"] - ref["fj"]) <= TOL[dtype], (alg, cap, dtype)
+
+
 def test_stream_copy_copies_exactly_and_checks_its_arguments():
     # the HBM-ceiling measurement copies every byte, at 16 and 8 bytes per lane, over a size that
     # is no multiple of the grid's stride; malformed requests are refused before any launch
