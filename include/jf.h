@@ -211,7 +211,11 @@ long long jf_plan_describe(const jf_plan* plan, char* buf, long long len);
  * (workspace, stream, kernel choice) and replay it in later calls; with the NULL stream such a
  * plan uses a stream of its own, ordered after the work already on the NULL stream.  (On MI355X
  * replay gains a few percent on a non-default stream, since the cost per step is on the GPU side,
- * and the NULL-stream hand-off adds ~40 us.)  The call synchronises before returning.
+ * and the NULL-stream hand-off adds ~40 us.)  A plan with both LDS-resident and larger
+ * components runs the former's persistent launch on a second stream of the plan's own, forked
+ * from and joined back to the run's stream by events (inside the graph too).  The first call
+ * allocates a small pinned host landing area per plan (held until jf_free_plan), into which the
+ * device writes F_J; the call synchronises before returning.
  * Errors: JF_E_ARG (not an Alg I plan), JF_E_OOM (workspace too small), JF_E_HIP.
  */
 jf_status jf_fidelity_alg1(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream,
@@ -224,9 +228,10 @@ jf_status jf_fidelity_alg2(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* s
 
 /*
  * jf_fidelity_batch -- run n plans (Alg I or Alg II, any mix, one dtype per plan) as one
- * batched submission (the networks are independent, Section IV-A): small networks execute
- * LDS-resident, one workgroup per slice, in a single persistent launch; larger ones run their
- * step programs back to back; the whole submission is captured once into a hipGraph (cached on
+ * batched submission (the networks are independent, Section IV-A): small components execute
+ * LDS-resident, one workgroup each, in a single persistent launch on a second stream (forked from
+ * and joined back to the caller's stream by events) beside the larger ones' step programs, which
+ * run back to back; the whole submission is captured once into a hipGraph (cached on
  * the first plan, keyed by the plans, the workspace and the stream) and replayed.  Each plan keeps
  * its tables, outputs and sums in a region of its own; since the programs run one after another,
  * their level buffers share one region sized for the largest, so the workspace is the sum of the

@@ -15,9 +15,13 @@
 //                        piece products) on BF16 matrix cores, register-direct
 //   k_chain, k_chain_split  several in-place FP32 / split-form steps applied to one LDS tile
 //                        per HBM pass
-//   k_persistent         whole small components in one workgroup's LDS
-//   k_sumsq_part/_final  the FP64 double-double sum of |t|^2 (two fixed-tree passes)
-//   k_zero               a graph-safe fill
+//   k_persistent         whole small components in one workgroup's LDS (and, for a plan made
+//                        of them only, the assembly of F_J by the last workgroup)
+//   k_sumsq_part/_final  the FP64 double-double sum of |t|^2 (two fixed-tree passes); k_sumsq_one
+//                        the same for a small output in one launch
+//   k_assemble           F_J and 1 - F_J from the components' sums (device and pinned host)
+//   k_accumulate, k_zero a wire-sliced leaf's partial traces into the output; a graph-safe fill
+//   k_stream_copy        the streaming copy that measures the HBM ceiling
 // launch_step picks the kernel of a step (its variant, or the fixed rule).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
