@@ -318,7 +318,7 @@ jf_status jf_stream_copy(const void* src, void* dst, size_t bytes, int bytes_per
  * straight into registers; FMA multiplies on the vector units; the Gauss kernels are direct
  * kernels that form each complex product from three real ones (Re.Re, Im.Im and (Re+Im).(Re+Im)),
  * a quarter fewer matrix-core products, with the imaginary part's rounding error relative to the
- * largest of the three (not used on noise-carrying FP32 blocks).  AUTO is a fixed rule measured
+ * largest of the three (two-term FP32 blocks: the residual's products first).  AUTO is a fixed rule measured
  * on MI355X.  Not every kernel takes every shape: a step keeps the AUTO rule where its choice
  * does not apply.
  */

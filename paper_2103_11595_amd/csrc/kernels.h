@@ -42,7 +42,7 @@ enum KernelVariant {
   KV_DIRECT_256 = 3,  // MFMA, A operands loaded straight into registers, 256 threads
   KV_DIRECT_512 = 4,  // the same, 512 threads
   KV_FMA = 5,         // plain FMA on LDS tiles
-  KV_GAUSS_256 = 6,   // register-direct, three real products per complex one (not for two-term steps)
+  KV_GAUSS_256 = 6,   // register-direct, three real products per complex one (two-term: residual first)
   KV_GAUSS_512 = 7,   // the same, 512 threads
   KV_COUNT = 8,
   KV_CHAIN = 8,       // (profiles only) a chain of steps in one launch, k_chain

@@ -597,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_rd(const StepDesc* __restric
 // The operator sits in LDS as [t][lane][x][mb] (x = Re, Im, Re + Im), so that every lane reads
 // its 3 MB values of a k-step from consecutive addresses.  Units, prefetch and in-place safety as
 // in k_absorb_mfma_rd.
-template <typename T, int NT, int MB, int KQ>
+template <typename T, int NT, int MB, int KQ, bool TWO_TERM = false>
 __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __restrict__ d,
                                                           const typename Mfma<T>::c2* A,
                                                           typename Mfma<T>::c2* C,
@@ -614,15 +614,17 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
   const long long nUnits = d->nTiles << rbits;
   load_tables(d, tb, K, Nn, R, nHi);
   load_tile_bases(d, tbb, nHi);
-  T* sB = reinterpret_cast<T*>(smem);
-  for (int idx = threadIdx.x; idx < KQ * 64 * W; idx += NT) {
-    const int t = idx / (64 * W), rem = idx - t * 64 * W;
+  T* sB = reinterpret_cast<T*>(smem);  // [t][lane][x][mb] (hi), then the same for lo (TWO_TERM)
+  constexpr int BT = KQ * 64 * W;
+  for (int idx = threadIdx.x; idx < (TWO_TERM ? 2 : 1) * BT; idx += NT) {
+    const int part = idx >= BT, i2 = idx - part * BT;
+    const int t = i2 / (64 * W), rem = i2 - t * 64 * W;
     const int ln = rem / W, e = rem - ln * W;
     const int x = e / MB, mb = e - x * MB;
     const int s = 4 * t + (ln >> 4), n = mb * 16 + (ln & 15);
     T v = 0;
     if (s < K && n < Nn) {
-      const C2 bv = B[s * Nn + n];
+      const C2 bv = B[part * K * Nn + s * Nn + n];
       v = x == 0 ? bv.x : x == 1 ? bv.y : bv.x + bv.y;
     }
     sB[idx] = v;
@@ -653,18 +655,23 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
     for (int x = 0; x < 3; ++x)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[x][mb] = typename M::acc_t{0, 0, 0, 0};
+    // two-term operators: the residual's products first, so that the correction survives the
+    // FP32 roundings of the running sums (as in the other two-term kernels)
+#pragma unroll 1
+    for (int part = TWO_TERM ? 1 : 0; part >= 0; --part) {
 #pragma unroll
-    for (int t = 0; t < KQ; ++t) {
-      const T ar = cur[t].x, ai = cur[t].y, as = ar + ai;
-      const T* bp = sB + (t * 64 + lane) * W;
-      T bv[W];
+      for (int t = 0; t < KQ; ++t) {
+        const T ar = cur[t].x, ai = cur[t].y, as = ar + ai;
+        const T* bp = sB + part * BT + (t * 64 + lane) * W;
+        T bv[W];
 #pragma unroll
-      for (int e = 0; e < W; ++e) bv[e] = bp[e];
+        for (int e = 0; e < W; ++e) bv[e] = bp[e];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        acc[0][mb] = M::op(bv[mb], ar, acc[0][mb]);
-        acc[1][mb] = M::op(bv[MB + mb], ai, acc[1][mb]);
-        acc[2][mb] = M::op(bv[2 * MB + mb], as, acc[2][mb]);
+        for (int mb = 0; mb < MB; ++mb) {
+          acc[0][mb] = M::op(bv[mb], ar, acc[0][mb]);
+          acc[1][mb] = M::op(bv[MB + mb], ai, acc[1][mb]);
+          acc[2][mb] = M::op(bv[2 * MB + mb], as, acc[2][mb]);
+        }
       }
     }
     const long long bC = tile_base(tbb.chC, v >> rbits) + tb.offRC[row_of_unit(v)];
@@ -1440,7 +1447,7 @@ void launch_direct(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc
   else launch_direct_mb<T, TWO_TERM, NT, 4>(h, stream, d_desc, A, C, B);
 }
 
-template <typename T, int NT, int MB>
+template <typename T, int NT, int MB, bool TWO_TERM>
 void launch_gauss_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
                      const void* B) {
   using C2 = typename Mfma<T>::c2;
@@ -1450,22 +1457,22 @@ void launch_gauss_mb(const StepDesc& h, hipStream_t stream, const StepDesc* d_de
   const int KQ = ((1 << h.kS) + 3) / 4;
   const long long units = h.nTiles << (h.L - 4);
   const long long wgs = (units + NT / 64 - 1) / (NT / 64);
-  const size_t sm = size_t(KQ * 64 * 3 * MB) * sizeof(T);
+  const size_t sm = size_t((TWO_TERM ? 2 : 1) * KQ * 64 * 3 * MB) * sizeof(T);
   switch (KQ) {
-    case 1: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 1>), wgs); break;
-    case 2: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 2>), wgs); break;
-    case 4: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 4>), wgs); break;
-    case 8: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 8>), wgs); break;
-    default: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 16>), wgs); break;
+    case 1: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 1, TWO_TERM>), wgs); break;
+    case 2: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 2, TWO_TERM>), wgs); break;
+    case 4: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 4, TWO_TERM>), wgs); break;
+    case 8: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 8, TWO_TERM>), wgs); break;
+    default: JF_LAUNCH_RESIDENT((k_absorb_mfma_gauss<T, NT, MB, 16, TWO_TERM>), wgs); break;
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool TWO_TERM = false>
 void launch_gauss(const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A, void* C,
                   const void* B) {
-  if (h.kN <= 4) launch_gauss_mb<T, NT, 1>(h, stream, d_desc, A, C, B);
-  else if (h.kN == 5) launch_gauss_mb<T, NT, 2>(h, stream, d_desc, A, C, B);
-  else launch_gauss_mb<T, NT, 4>(h, stream, d_desc, A, C, B);
+  if (h.kN <= 4) launch_gauss_mb<T, NT, 1, TWO_TERM>(h, stream, d_desc, A, C, B);
+  else if (h.kN == 5) launch_gauss_mb<T, NT, 2, TWO_TERM>(h, stream, d_desc, A, C, B);
+  else launch_gauss_mb<T, NT, 4, TWO_TERM>(h, stream, d_desc, A, C, B);
 }
 
 // Split-form launches with the operator block counts fixed at compile time.
@@ -1524,7 +1531,7 @@ static bool staged_ok(const StepDesc& h) {
 static bool direct_ok(const StepDesc& h) { return h.L >= 4 && h.kS <= 5 && h.kN <= 5; }
 // (kS + kN <= 10: the larger blocks would spill registers)
 static bool gauss_ok(const StepDesc& h) {
-  return h.L >= 4 && h.kS <= 6 && h.kN <= 6 && h.kS + h.kN <= 10 && h.mode != KM_F32X2;
+  return h.L >= 4 && h.kS <= 6 && h.kN <= 6 && h.kS + h.kN <= 10;
 }
 // split form: Gauss products for single-term operators; the real embedding for any operator with
 // at most 8 blocks x chunks of fragments (<= 32 KB of LDS, registers within budget)
@@ -1591,9 +1598,9 @@ int resolve_variant(const StepDesc& h) {
 template <typename T, bool TWO_TERM>
 static void launch_mfma_variant(int v, const StepDesc& h, hipStream_t stream, const StepDesc* d_desc, const void* A,
                                 void* C, const void* B) {
-  if constexpr (!TWO_TERM) {
-    if (v == KV_GAUSS_256) return launch_gauss<T, 256>(h, stream, d_desc, A, C, B);
-    if (v == KV_GAUSS_512) return launch_gauss<T, 512>(h, stream, d_desc, A, C, B);
+  if constexpr (!TWO_TERM || std::is_same<T, float>::value) {  // two-term operators exist in FP32 only
+    if (v == KV_GAUSS_256) return launch_gauss<T, 256, TWO_TERM>(h, stream, d_desc, A, C, B);
+    if (v == KV_GAUSS_512) return launch_gauss<T, 512, TWO_TERM>(h, stream, d_desc, A, C, B);
   }
   switch (v) {
     case KV_STAGED_256: launch_staged<T, TWO_TERM, 256>(h, stream, d_desc, A, C, B); break;
