@@ -18,9 +18,10 @@ bool validate_program(const Program& P, std::string& why) {
     for (size_t s = 0; s < cp.steps.size(); ++s) {
       const Step& st = cp.steps[s];
       const int K = 1 << st.kS, Nn = 1 << st.kN, R = 1 << st.L;
+      const size_t entry = st.compute == C_F64 ? 16 : 8;  // LDS bytes per operator / tile entry
       if (K > MAXK || Nn > MAXK || R > MAXR || (int)st.hiA.size() > MAXHI || (int)st.offS_A.size() != K ||
           (int)st.offN_C.size() != Nn || (int)st.offR_A.size() != R || st.nTiles != (1LL << st.hiA.size()) ||
-          size_t(K) * (Nn + R) * 16 > 61440) {
+          size_t(K) * (Nn + R) * entry > 61440) {
         why = "step table sizes out of range";
         return false;
       }
