@@ -83,7 +83,7 @@ bool validate_program(const Program& P, std::string& why) {
         const Step& st = cp.steps[s];
         ok = chainable(st) && st.chain == int(q) && st.rA == rA && ch.T - st.kS >= 4;
         for (int b : step_s_positions(st)) ok = ok && std::count(ch.P.begin(), ch.P.end(), b) == 1;
-        ops += chain_step_ops(st.kS, st.compute == C_SPLIT);
+        ops += chain_step_ops(st.kS, st.compute == C_SPLIT, st.two_term);
         for (size_t l = 0; l < cp.levels.size(); ++l)
           if (s >= cp.levels[l].first && s < cp.levels[l].last) {
             if (lvl < 0) lvl = int(l);

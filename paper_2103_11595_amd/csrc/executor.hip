@@ -431,7 +431,8 @@ void build_layout(const Program& P, DevState& S) {
         d.st[j].kS = st.kS;
         d.st[j].boff = boff;
         d.st[j].frag = d.split ? int(split_layout(st).gauss) : 0;
-        boff += chain_step_ops(st.kS, d.split != 0);
+        d.st[j].two = st.two_term ? 1 : 0;
+        boff += chain_step_ops(st.kS, d.split != 0, st.two_term);
         for (size_t i = 0; i < tb.sOff[j].size(); ++i) d.st[j].sOff[i] = tb.sOff[j][i];
         for (int i = 0; i < 48; ++i) d.st[j].fDig[i] = tb.fDig[j][i];
       }

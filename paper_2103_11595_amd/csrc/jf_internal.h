@@ -130,10 +130,12 @@ struct Step {
 constexpr int CHAIN_MAX_STEPS = 8;   // steps per chain
 constexpr int CHAIN_MAX_T = 12;      // log2 elements of a tile (32 KB of complex64)
 constexpr int CHAIN_MAX_U = 10;      // contracted positions of a chain
-constexpr int CHAIN_MAX_OPS = 4096;        // FP32 chains: sum of K^2 over the steps (operators in LDS)
+constexpr int CHAIN_MAX_OPS = 4096;        // FP32 chains: K^2 per step (2 K^2 for an FP32 pair), summed
 constexpr int CHAIN_MAX_OPS_SPLIT = 2304;  // split chains: 16-byte operator fragments in LDS (36 KB)
 // LDS entries the operator of a chain step takes, against the budget of its kind above
-inline int chain_step_ops(int kS, bool split) { return split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : 1 << (2 * kS); }
+inline int chain_step_ops(int kS, bool split, bool two_term = false) {
+  return split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : (two_term ? 2 : 1) << (2 * kS);
+}
 struct Chain {
   int first = 0, last = 0;       // steps of the component
   int T = 0;                     // tile bits

@@ -93,8 +93,9 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h_desc, const voi
 // indices s at tile-local sOff[s] against the remaining tile bits f at
 //   fDig[f & 15] + fDig[16 + ((f >> 4) & 15)] + fDig[32 + (f >> 8)],
 // and writes n at the same places (sOff[n]).  Its operator (K x K, row-major [s][n]: float2, or
-// the split-form pieces) is ops.B[j]; in LDS it sits at entry boff (float2 entries for FP32 steps,
-// 16-byte BF16 fragments for split steps: 576 max(1, K / 16) of them per step).
+// the split-form pieces) is ops.B[j]; in LDS it sits at entry boff (float2 entries for FP32 steps:
+// K^2, or 2 K^2 for an FP32 pair, the residual block after the leading one; 16-byte BF16
+// fragments for split steps: 576 max(1, K / 16) of them per step).
 constexpr int CHAIN_STEPS = 8;
 constexpr int CHAIN_T = 12;
 constexpr int CHAIN_OPS = 4096;        // float2 entries of all operators of an FP32 chain
@@ -102,7 +103,7 @@ constexpr int CHAIN_OPS_SPLIT = 2304;  // 16-byte fragments of all operators of 
 struct ChainStepDesc {
   int kS, boff;
   int frag;  // split chains: offset (16-byte units) of the Gauss-form fragments in the operator block
-  int pad;
+  int two;   // FP32 chains: 1 when the operator is an FP32 pair (K x K leading part, then the residual)
   unsigned short sOff[32];
   unsigned short fDig[48];
 };

@@ -13,8 +13,8 @@
 //   k_absorb_mfma_gauss  matrix cores, three real products per complex one, register-direct
 //   k_absorb_split_gauss, k_absorb_split_embed  the split form (three-way BF16 splits, six
 //                        piece products) on BF16 matrix cores, register-direct
-//   k_chain, k_chain_split  several in-place FP32 / split-form steps applied to one LDS tile
-//                        per HBM pass
+//   k_chain, k_chain_pairs, k_chain_split  several in-place FP32 (single or FP32-pair operators)
+//                        / split-form steps applied to one LDS tile per HBM pass
 //   k_persistent         whole small components in one workgroup's LDS (and, for a plan made
 //                        of them only, the assembly of F_J by the last workgroup)
 //   k_sumsq_part/_final  the FP64 double-double sum of |t|^2 (two fixed-tree passes); k_sumsq_one
@@ -696,7 +696,9 @@ __global__ __launch_bounds__(NT) void k_absorb_mfma_gauss(const StepDesc* __rest
 // wave has read all of them (the products consume every read before any write), and the units of
 // different waves are disjoint.
 // KS > 0 fixes the step's kS at compile time (then the padding tests fold away); KS = 0 reads it.
-template <int NT, int KQ, int MB, int KS>
+// TWO: the operator is an FP32 pair, the leading K x K block followed by the residual one; the
+// residual's products go into the accumulators first, as in k_absorb_mfma_gauss.
+template <int NT, int KQ, int MB, int KS, bool TWO>
 __device__ __forceinline__ void chain_step(float2* tile, const float2* __restrict__ B, const ChainStepDesc& sd,
                                            int T) {
   using M = Mfma<float>;
@@ -719,17 +721,21 @@ __device__ __forceinline__ void chain_step(float2* tile, const float2* __restric
     for (int x = 0; x < 3; ++x)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) acc[x][mb] = M::acc_t{0, 0, 0, 0};
+#pragma unroll 1
+    for (int part = TWO ? 1 : 0; part >= 0; --part) {
+      const float2* Bp = B + part * K * K;
 #pragma unroll
-    for (int t = 0; t < KQ; ++t) {
-      const float ar = a[t].x, ai = a[t].y, as = ar + ai;
-      const int s = 4 * t + g;
+      for (int t = 0; t < KQ; ++t) {
+        const float ar = a[t].x, ai = a[t].y, as = ar + ai;
+        const int s = 4 * t + g;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int n = mb * 16 + l16;
-        const float2 bv = (s < K && n < K) ? B[s * K + n] : float2{0.f, 0.f};
-        acc[0][mb] = M::op(bv.x, ar, acc[0][mb]);
-        acc[1][mb] = M::op(bv.y, ai, acc[1][mb]);
-        acc[2][mb] = M::op(bv.x + bv.y, as, acc[2][mb]);
+        for (int mb = 0; mb < MB; ++mb) {
+          const int n = mb * 16 + l16;
+          const float2 bv = (s < K && n < K) ? Bp[s * K + n] : float2{0.f, 0.f};
+          acc[0][mb] = M::op(bv.x, ar, acc[0][mb]);
+          acc[1][mb] = M::op(bv.y, ai, acc[1][mb]);
+          acc[2][mb] = M::op(bv.x + bv.y, as, acc[2][mb]);
+        }
       }
     }
 #pragma unroll
@@ -989,7 +995,7 @@ __device__ __forceinline__ void chain_step_split(float2* tile, const uint4* __re
 // and the stores, so the store phase and the next fill need no barrier between them.  SPLIT: the
 // steps compute the split form (operators as BF16 fragments in LDS), else FP32 (complex operators
 // in LDS).
-template <int NT, bool SPLIT>
+template <int NT, bool SPLIT, bool PAIRS = false>
 __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, const float2* A, float2* C,
                                            const ChainOps& ops) {
   static_assert(NT % 256 == 0 && NT <= 1024, "digits 0 and 1 of a thread's elements are its own");
@@ -1044,7 +1050,8 @@ __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, cons
     } else {
       const float2* Bj = static_cast<const float2*>(ops.B[j]);
       float2* sOp = reinterpret_cast<float2*>(smem);
-      for (int i = threadIdx.x; i < (1 << (2 * kS)); i += NT) sOp[bo + i] = Bj[i];
+      const int n = (d->st[j].two ? 2 : 1) << (2 * kS);
+      for (int i = threadIdx.x; i < n; i += NT) sOp[bo + i] = Bj[i];
     }
   }
   if (!early && t < nTiles) fetch(t);
@@ -1062,11 +1069,20 @@ __device__ __forceinline__ void chain_body(const ChainDesc* __restrict__ d, cons
         else chain_step_split<NT, 1>(tile, fr, sd[j], T);  // kS = 1 .. 4
       } else {
         const float2* Bj = reinterpret_cast<const float2*>(smem) + sd[j].boff;
-        switch (sd[j].kS) {
-          case 5: chain_step<NT, 8, 2, 5>(tile, Bj, sd[j], T); break;
-          case 4: chain_step<NT, 4, 1, 4>(tile, Bj, sd[j], T); break;
-          case 3: chain_step<NT, 2, 1, 3>(tile, Bj, sd[j], T); break;
-          default: chain_step<NT, 1, 1, 0>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+        if (PAIRS && sd[j].two) {
+          switch (sd[j].kS) {
+            case 5: chain_step<NT, 8, 2, 5, true>(tile, Bj, sd[j], T); break;
+            case 4: chain_step<NT, 4, 1, 4, true>(tile, Bj, sd[j], T); break;
+            case 3: chain_step<NT, 2, 1, 3, true>(tile, Bj, sd[j], T); break;
+            default: chain_step<NT, 1, 1, 0, true>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+          }
+        } else {
+          switch (sd[j].kS) {
+            case 5: chain_step<NT, 8, 2, 5, false>(tile, Bj, sd[j], T); break;
+            case 4: chain_step<NT, 4, 1, 4, false>(tile, Bj, sd[j], T); break;
+            case 3: chain_step<NT, 2, 1, 3, false>(tile, Bj, sd[j], T); break;
+            default: chain_step<NT, 1, 1, 0, false>(tile, Bj, sd[j], T); break;  // kS = 1, 2
+          }
         }
       }
       __syncthreads();  // step j complete on the whole tile
@@ -1088,6 +1104,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                                                     const float2* A, float2* C,
                                                                                     ChainOps ops) {
   chain_body<NT, false>(d, A, C, ops);
+}
+// Chains with FP32-pair steps: their own kernel, so that the pair path's registers do not weigh
+// on the single-term chains (in one kernel they made the compiler spill the prefetched tile).
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_chain_pairs(
+    const ChainDesc* __restrict__ d, const float2* A, float2* C, ChainOps ops) {
+  chain_body<NT, false, true>(d, A, C, ops);
 }
 template <int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_chain_split(
@@ -1680,12 +1703,20 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void*
       h.ops > (h.split ? CHAIN_OPS_SPLIT : CHAIN_OPS))
     return hipErrorInvalidValue;
   for (int j = 0; j < h.nsteps; ++j) {
-    const int kS = h.st[j].kS;
-    const int need = h.split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : 1 << (2 * kS);
-    if (kS < 1 || kS > 5 || h.T - kS < 4 || h.st[j].boff + need > h.ops) return hipErrorInvalidValue;
+    const int kS = h.st[j].kS, two = h.st[j].two;
+    const int need = h.split ? 576 * (kS > 4 ? 1 << (kS - 4) : 1) : (two ? 2 : 1) << (2 * kS);
+    if (kS < 1 || kS > 5 || h.T - kS < 4 || (two != 0 && (two != 1 || h.split)) || h.st[j].boff < 0 ||
+        h.st[j].boff + need > h.ops)
+      return hipErrorInvalidValue;
   }
   constexpr int NT = 256;
-  if (h.split) {
+  bool pairs = false;
+  for (int j = 0; j < h.nsteps; ++j) pairs = pairs || h.st[j].two;
+  if (pairs) {
+    const size_t sm = size_t(h.ops) * sizeof(float2);
+    JF_LAUNCH(k_chain_pairs<NT>, dim3(JF_RESIDENT(k_chain_pairs<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream,
+              d_desc, (const float2*)A, (float2*)C, ops);
+  } else if (h.split) {
     const size_t sm = size_t(h.ops) * sizeof(uint4);
     JF_LAUNCH(k_chain_split<NT>, dim3(JF_RESIDENT(k_chain_split<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
               (const float2*)A, (float2*)C, ops);

@@ -682,6 +682,34 @@ def test_alg2_chains_against_oracle():
         assert abs(got["fj"] - dense.fidelity_alg2(inst)["fj"]) <= TOL["c64"]
 
 
+def test_chains_with_fp32_pair_operators_against_oracle():
+    # blocks that carry a noise operator keep it as an FP32 pair (leading part + residual) and
+    # still join chains: K = 16 and 32 pair steps (fused blocks, Algorithm II) and K = 4 ones
+    # (unfused single gates, both algorithms).  F_J is one quantity whichever algorithm computes
+    # it, so the oracle's Algorithm I routine (dense, fast at n = 7) supplies it for both.
+    small = jf.JF_FLAG_NO_FUSE | jf.JF_FLAG_NO_CANCEL
+    cases = [((7, 130, 6, 0.01, 0.3, 5115), 2, 0), ((7, 178, 6, 0.01, 0.3, 5123), 2, 0),
+             ((7, 39, 6, 0.01, 0.3, 5303), 1, small), ((7, 39, 6, 0.01, 0.3, 5303), 2, small)]
+    for args, alg, flags in cases:
+        inst = gen.random_circuit(*args)
+        p = jf.plan(inst, alg, "c64", flags=flags)
+        pair = [x for x in p.describe() if x["chain"] >= 0 and x["compute"] == "f32x2"]
+        assert pair, (args, alg)
+        q = jf.plan(inst, alg, "c64", flags=flags | jf.JF_FLAG_NO_CHAIN)
+        say("pair chains", args[-1], "alg", alg, "K", sorted({1 << x["kS"] for x in pair}))
+        ref = dense.fidelity_alg1(inst, want_terms=True)
+        ws = jf.workspace(max(p.info()["workspace_bytes"], q.info()["workspace_bytes"]))
+        run = jf.jf_fidelity_alg1 if alg == 1 else jf.jf_fidelity_alg2
+        kw = {"want_terms": True} if alg == 1 else {}
+        a = run(p, ws, **kw)
+        assert any(r["variant"] == jf.KV_CHAIN for r in jf.jf_profile_steps(p, ws))
+        b = run(q, ws, **kw)
+        assert abs(a["fj"] - ref["fj"]) <= TOL["c64"] and abs(b["fj"] - ref["fj"]) <= TOL["c64"]
+        assert abs(a["fj"] - b["fj"]) <= TOL["c64"]
+        if alg == 1:
+            assert np.max(np.abs(a["terms"] - _terms(ref))) <= 1e-6
+
+
 def test_chains_of_single_gate_steps_against_oracle():
     # one step per tensor and no cancellation: chains of 2 x 2 and 4 x 4 operators (the lane groups
     # past K of the kernel's k-steps supply zeros, the rows past K are not stored)

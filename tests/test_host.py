@@ -445,7 +445,7 @@ def test_chains_group_consecutive_in_place_steps():
             assert len({x["level"] for x in steps}) == 1                     # one level
             union = set()
             for x in steps:
-                assert x["compute"] == "f32" and x["kS"] == x["kN"] <= 5       # single-term FP32
+                assert x["compute"] in ("f32", "f32x2") and x["kS"] == x["kN"] <= 5  # FP32 (single or pair)
                 assert x["sA"] == x["nC"] and x["rowsA"] == x["rowsC"] and x["rA"] == x["rC"]
                 union |= set(x["sA"])
             assert len(union) <= 10
@@ -455,6 +455,9 @@ def test_chains_group_consecutive_in_place_steps():
     split = jf.plan(gen.config2(), 1, "bf16x6").describe()
     assert any(x["chain"] >= 0 for x in split)
     assert all(x["compute"] == "split" for x in split if x["chain"] >= 0)
+    # noise-carrying blocks (FP32 pair operators) join chains in complex64: the n=25 chain workload
+    d = jf.plan(gen.config3(), 2, "c64").describe()
+    assert any(x["chain"] >= 0 and x["compute"] == "f32x2" for x in d)
 
 
 def test_emulated_chains_match_oracle_and_unchained_program():
