@@ -1712,10 +1712,21 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void*
   constexpr int NT = 256;
   bool pairs = false;
   for (int j = 0; j < h.nsteps; ++j) pairs = pairs || h.st[j].two;
-  if (pairs) {
-    const size_t sm = size_t(h.ops) * sizeof(float2);
-    JF_LAUNCH(k_chain_pairs<NT>, dim3(JF_RESIDENT(k_chain_pairs<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream,
+  // A chain with at most one tile per compute unit keeps most of the device idle while each
+  // workgroup runs the steps one after another: there 512-thread workgroups (one unit of a K = 32
+  // step per wave on a 2^12 tile) shorten each step (measured on MI355X: the n=25 chain pass
+  // 505 -> 495 us; with 512 tiles of 2^9 elements, one unit per step, 9.3 -> 12.4 us a launch).
+  const bool wide = !h.split && h.nTiles <= 256;
+  const size_t smf = size_t(h.ops) * sizeof(float2);
+  if (pairs && wide) {
+    JF_LAUNCH(k_chain_pairs<512>, dim3(JF_RESIDENT(k_chain_pairs<512>, 512, smf, h.nTiles)), dim3(512), smf, stream,
               d_desc, (const float2*)A, (float2*)C, ops);
+  } else if (pairs) {
+    JF_LAUNCH(k_chain_pairs<NT>, dim3(JF_RESIDENT(k_chain_pairs<NT>, NT, smf, h.nTiles)), dim3(NT), smf, stream,
+              d_desc, (const float2*)A, (float2*)C, ops);
+  } else if (wide) {
+    JF_LAUNCH(k_chain<512>, dim3(JF_RESIDENT(k_chain<512>, 512, smf, h.nTiles)), dim3(512), smf, stream, d_desc,
+              (const float2*)A, (float2*)C, ops);
   } else if (h.split) {
     const size_t sm = size_t(h.ops) * sizeof(uint4);
     JF_LAUNCH(k_chain_split<NT>, dim3(JF_RESIDENT(k_chain_split<NT>, NT, sm, h.nTiles)), dim3(NT), sm, stream, d_desc,
