@@ -505,12 +505,22 @@ def main():
     mm = PEAK["c64" if args.dtype != "c128" else "c128"]["mfma"]
     kv_names = {v: k for k, v in jf.KERNEL_VARIANTS.items()}
     kv_names[jf.KV_CHAIN] = "chain"
+
+    def label(x):
+        # the kernel a launch ran: its variant, and for chains the kind and workgroup size
+        # (k_chain, k_chain_pairs with FP32-pair steps, k_chain_split; 256 or 512 threads)
+        n = kv_names[x["variant"]]
+        if n == "chain":
+            n = "chain_split" if x["mode"] == 3 else "chain_pairs" if x["mode"] == 4 else "chain"
+            if x["threads"] != 256:
+                n += str(x["threads"])
+        return n
     # the dominant kernel: the step kernel with the largest share of the pass's device time (per-launch
     # HIP events on the launch stream, jf_profile_steps); its roofline from its intensity: the
     # algorithmic flops (a complex MAC = 8) and bytes (input read and output written once) per launch
     groups = {}
     for x in main_form["per_step"]:
-        g = groups.setdefault(kv_names[x["variant"]], {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        g = groups.setdefault(label(x), {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
         g["launches"] += 1
         g["ms"] += x["ms"]
         g["flops"] += x["flops"]
@@ -523,7 +533,11 @@ def main():
         bound, achieved, peak, unit = "hbm", dom_b / (dom_us * 1e-6) / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
         bound, achieved, peak, unit = "mfma", dom_fl / (dom_us * 1e-6) / 1e12, mm, "TFLOP/s"
-    symbol = {"chain": "k_chain_split<256>" if args.dtype == "bf16x6" else "k_chain<256>"}.get(dom_name, dom_name)
+    if dom_name.startswith("chain"):
+        kind, nt = dom_name.rstrip("0123456789"), dom_name[len(dom_name.rstrip("0123456789")):] or "256"
+        symbol = f"k_{kind}<{nt}>"
+    else:
+        symbol = dom_name
     # large contractions (complex GEMMs of K >= 16 summed and new extents, intensity >= 8 flop/B)
     # against the FP32 (c64) or FP64 (c128) MFMA peak, and the other steps against HBM
     big = [x for x in main_form["per_step"] if x["flops"] >= 8 * x["bytes"]]
@@ -543,7 +557,7 @@ def main():
     }
     kernels_used = {}
     for x in main_form["per_step"]:
-        kernels_used[kv_names[x["variant"]]] = kernels_used.get(kv_names[x["variant"]], 0) + 1
+        kernels_used[label(x)] = kernels_used.get(label(x), 0) + 1
     ksha = hashlib.sha256(open(os.path.join(ROOT, "paper_2103_11595_amd", "csrc", "kernels.hip"), "rb").read()).hexdigest()[:16]
     tag = {"c64": "cfg2", "c128": "cfg2_c128", "bf16x6": "cfg2_bf16x6"}[args.dtype]
     trec = counter_record("traffic_absorb_" + tag, ksha, prof["launches"], byts)
@@ -551,7 +565,7 @@ def main():
     traffic = tk["traffic_bytes_per_launch"] if tk and tk["launches"] == dom["launches"] else None
     mrec = counter_record("mfma_absorb_" + tag, ksha, prof["launches"], byts)
     per_launch = [{"us": x["ms"] * 1e3, "kS": x["kS"], "kN": x["kN"], "L": x["L"], "mode": x["mode"],
-                   "kernel": kv_names[x["variant"]], "steps": x["steps"], "bytes": x["bytes"], "flops": x["flops"],
+                   "kernel": label(x), "steps": x["steps"], "threads": x["threads"], "bytes": x["bytes"], "flops": x["flops"],
                    "gbs": x["bytes"] / (x["ms"] * 1e-3) / 1e9 if x["ms"] else None,
                    "tflops": x["flops"] / (x["ms"] * 1e-3) / 1e12 if x["ms"] else None}
                   for x in main_form["per_step"]]
@@ -597,7 +611,7 @@ def main():
                      "intensity_flop_per_byte": dom_fl / dom_b, "ridge_flop_per_byte": ridge,
                      "algorithmic_tflops": dom_fl / (dom_us * 1e-6) / 1e12,
                      "hbm_gbs_algorithmic": dom_b / (dom_us * 1e-6) / 1e9,
-                     "mfma_counters": (mrec.get("chains") if mrec and dom_name == "chain" else None),
+                     "mfma_counters": ((mrec.get("by_kernel") or {}).get(dom_name) if mrec else None),
                      "pass": {"launches": prof["launches"], "algorithmic_bytes_per_pass": byts, "flops_per_pass": flops,
                               "kernel_ms_per_pass": kms, "avg_launch_us": kms * 1e3 / max(1, prof["launches"]),
                               "hbm_gbs": byts / (kms * 1e-3) / 1e9, "frac_of_hbm_peak": byts / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,

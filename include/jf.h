@@ -286,8 +286,9 @@ jf_status jf_profile_run(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* str
  * 5 split form with a fourth operator piece);
  * variant the kernel that ran it (jf_kernel_variant, never AUTO); steps the number of program
  * steps the launch ran (1, or the length of a chain: variant JF_KV_CHAIN, kS = kN the largest
- * summed extent of its steps, L the log2 of its LDS tile, flops the chain's, bytes one read and
- * one write of the intermediate).
+ * summed extent of its steps, L the log2 of its LDS tile, mode 4 if it holds a step with a
+ * two-term operator, flops the chain's, bytes one read and one write of the intermediate);
+ * threads the workgroup size of the launch (with variant and mode, it names the kernel).
  */
 typedef struct {
   double ms;     /* event-measured duration */
@@ -296,6 +297,7 @@ typedef struct {
   int kS, kN, L; /* log2 of summed, new and per-tile row extents */
   int mode, variant, component;
   int steps;     /* program steps run by this launch */
+  int threads;   /* workgroup size */
 } jf_step_profile;
 jf_status jf_profile_steps(jf_plan* plan, void* dev_ws, size_t ws_bytes, void* stream, jf_step_profile* out,
                            int cap, int* n_launches);

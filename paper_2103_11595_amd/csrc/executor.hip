@@ -673,10 +673,13 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, unsigned char* bufs, hipS
           for (const StepDesc* h : shd) r.kS = std::max(r.kS, h->kS);
           r.kN = r.kS;
           r.L = ch.T;
-          r.mode = hd.split ? KM_SPLIT : KM_F32;
+          bool pairs = false;
+          for (int j = 0; j < hd.nsteps; ++j) pairs = pairs || hd.st[j].two;
+          r.mode = hd.split ? KM_SPLIT : pairs ? KM_F32X2 : KM_F32;
           r.variant = KV_CHAIN;
           r.component = int(c);
           r.steps = ch.last - ch.first;
+          r.threads = chain_threads(hd);
           prof->rec.push_back(r);
         } else {
           JF_HIP(launch_chain(dd, hd, cur, dst, ops, stream));
@@ -726,6 +729,7 @@ jf_status enqueue_level(jf_plan* p, unsigned char* ws, unsigned char* bufs, hipS
       r.variant = resolve_variant(*hd);
       r.component = int(c);
       r.steps = 1;
+      r.threads = step_threads(*hd);
       prof->rec.push_back(r);
     } else {
       JF_HIP(launch_step(dd, *hd, cur, dst, B, stream));

@@ -151,6 +151,9 @@ struct AssembleArgs {
   unsigned* counter;   // zero before the launch, zero again after it (the last workgroup resets it)
 };
 hipError_t launch_persistent(const LdsItem* items, int n_items, const LdsStep* steps, hipStream_t stream);
+// Workgroup sizes launch_step and launch_chain use for a step / a chain.
+int step_threads(const StepDesc& h);
+int chain_threads(const ChainDesc& h);
 // The same launch, ending with the assembly: the last workgroup to finish (counted on *counter)
 // assembles F_J from every item's sums -- for plans whose components are all LDS-resident, one
 // launch per run.

@@ -1697,6 +1697,13 @@ hipError_t launch_step(const StepDesc* d_desc, const StepDesc& h, const void* A,
   return hipGetLastError();
 }
 
+int step_threads(const StepDesc& h) {
+  const int v = resolve_variant(h);
+  return (v == KV_STAGED_512 || v == KV_DIRECT_512 || v == KV_GAUSS_512) ? 512 : 256;
+}
+
+int chain_threads(const ChainDesc& h) { return !h.split && h.nTiles <= 256 ? 512 : 256; }
+
 hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void* A, void* C, const ChainOps& ops,
                         hipStream_t stream) {
   if (h.nsteps < 1 || h.nsteps > CHAIN_STEPS || h.T < 4 || h.T > CHAIN_T || h.nHi > DMAXHI ||
@@ -1716,7 +1723,7 @@ hipError_t launch_chain(const ChainDesc* d_desc, const ChainDesc& h, const void*
   // workgroup runs the steps one after another: there 512-thread workgroups (one unit of a K = 32
   // step per wave on a 2^12 tile) shorten each step (measured on MI355X: the n=25 chain pass
   // 505 -> 495 us; with 512 tiles of 2^9 elements, one unit per step, 9.3 -> 12.4 us a launch).
-  const bool wide = !h.split && h.nTiles <= 256;
+  const bool wide = chain_threads(h) == 512;
   const size_t smf = size_t(h.ops) * sizeof(float2);
   if (pairs && wide) {
     JF_LAUNCH(k_chain_pairs<512>, dim3(JF_RESIDENT(k_chain_pairs<512>, 512, smf, h.nTiles)), dim3(512), smf, stream,

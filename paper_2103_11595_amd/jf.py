@@ -86,7 +86,7 @@ class jf_profile(C.Structure):
 class jf_step_profile(C.Structure):
     _fields_ = [("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double), ("kS", C.c_int),
                 ("kN", C.c_int), ("L", C.c_int), ("mode", C.c_int), ("variant", C.c_int), ("component", C.c_int),
-                ("steps", C.c_int)]
+                ("steps", C.c_int), ("threads", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

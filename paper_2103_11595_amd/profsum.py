@@ -278,9 +278,11 @@ def mfma(args):
         return {"launches": len(sel), "us": us, "algorithmic_tflops": sum(r["flops"] for r in sel) / us / 1e6,
                 "executed_mfma_tflops": sum(r["executed_mfma_flops"] for r in sel) / us / 1e6,
                 "mfma_busy_pct_time_weighted": util}
-    classes = {"chains": summary([r for r in rows if r["kernel"] == "chain"]),
+    classes = {"chains": summary([r for r in rows if r["kernel"].startswith("chain")]),
                "large_contractions": summary([r for r in rows if r["flops"] >= 8 * r["bytes"]]),
-               "all_step_launches": summary(rows)}
+               "all_step_launches": summary(rows),
+               "by_kernel": {k: summary([r for r in rows if r["kernel"] == k])
+                             for k in sorted({r["kernel"] for r in rows})}}
     rec = {"kernels_sha": kernels_sha(), "workload": b["config"]["workload"], "dtype": b["dtype"], "launches": n,
            "algorithmic_bytes_per_launch": alg / n, "source": args.out, **classes}
     json.dump(rec, open(args.json, "w"), indent=1)
@@ -303,7 +305,9 @@ def mfma(args):
                    + (f"{r['mfma_util_pct']:.1f}" if r["mfma_util_pct"] is not None else "-") + " |")
     out += ["", "| class | launches | us per pass | alg. TFLOP/s | executed MFMA TFLOP/s | MFMA busy % (time-weighted) |",
             "|---|---|---|---|---|---|"]
-    for k, v in classes.items():
+    named = [(k, v) for k, v in classes.items() if k != "by_kernel"]
+    named += [(f"kernel {k}", v) for k, v in classes["by_kernel"].items()]
+    for k, v in named:
         if v:
             out.append(f"| {k} | {v['launches']} | {v['us']:.1f} | {v['algorithmic_tflops']:.1f} | "
                        f"{v['executed_mfma_tflops']:.1f} | {v['mfma_busy_pct_time_weighted']:.1f} |")

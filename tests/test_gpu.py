@@ -702,7 +702,9 @@ def test_chains_with_fp32_pair_operators_against_oracle():
         run = jf.jf_fidelity_alg1 if alg == 1 else jf.jf_fidelity_alg2
         kw = {"want_terms": True} if alg == 1 else {}
         a = run(p, ws, **kw)
-        assert any(r["variant"] == jf.KV_CHAIN for r in jf.jf_profile_steps(p, ws))
+        prof = jf.jf_profile_steps(p, ws)
+        assert any(r["variant"] == jf.KV_CHAIN and r["mode"] == 4 for r in prof)  # a chain with pair steps
+        assert all(r["threads"] in (256, 512) for r in prof)
         b = run(q, ws, **kw)
         assert abs(a["fj"] - ref["fj"]) <= TOL["c64"] and abs(b["fj"] - ref["fj"]) <= TOL["c64"]
         assert abs(a["fj"] - b["fj"]) <= TOL["c64"]

@@ -194,6 +194,7 @@ def test_profile_summary_mfma_classes(tmp_path):
     big = rec["large_contractions"]   # flops >= 8 x bytes: the chain and the Gauss step
     assert big["launches"] == 2 and abs(big["mfma_busy_pct_time_weighted"] - (60.0 * 3 + 20.0 * 1) / 4) < 1e-12
     assert rec["all_step_launches"]["launches"] == 3
+    assert rec["by_kernel"]["chain"] == ch and rec["by_kernel"]["fma"]["launches"] == 1
 
 
 def test_workspace_release_is_host_only():
