@@ -537,6 +537,25 @@ def test_every_kernel_variant_against_oracle(seed, dtype):
     jf.jf_set_kernel_variant(p, "auto")
 
 
+def test_expanding_steps_with_wide_tiles_every_variant_against_oracle():
+    # a complex64 step that expands its tensor (K = 16 -> Nn = 64) takes 256-row tiles, its LDS
+    # entries counted at 8 bytes; here with an FP32-pair operator (a noise-carrying block), so the
+    # staged kernel holds both operator blocks beside the 4096-element tile (the largest LDS the
+    # wider rule admits for it); every kernel that can run it against the oracle
+    inst = gen.random_circuit(10, 376, 3, 0.01, 0.3, 7074)
+    p = jf.plan(inst, 1, "c64")
+    assert any(x["kS"] == 4 and x["kN"] == 6 and x["L"] == 8 and x["compute"] == "f32x2" for x in p.describe())
+    ref = dense.fidelity_alg1(inst, want_terms=True)
+    ws = jf.workspace(p.info()["workspace_bytes"])
+    for name in jf.KERNEL_VARIANTS:
+        say("wide tiles, variant", name)
+        jf.jf_set_kernel_variant(p, name)
+        got = jf.jf_fidelity_alg1(p, ws, want_terms=True)
+        assert abs(got["fj"] - ref["fj"]) <= TOL["c64"], (name, got["fj"] - ref["fj"])
+        assert np.max(np.abs(got["terms"] - _terms(ref))) <= 1e-6, name
+    jf.jf_set_kernel_variant(p, "auto")
+
+
 def test_autotune_parity_and_bitwise_replay():
     inst = _variant_instance(5)
     ref = dense.fidelity_alg1(inst, want_terms=True)
