@@ -389,13 +389,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       break;
     }
 
-  const bool low = opt.dtype != JF_C128;
-  const int elem_lo = low ? 8 : 16;
-  CostModel cm;
-  if (opt.dtype == JF_C64) cm.flops = 70e12;  // FP32 MFMA contraction rate measured at K = 32 to 64
+  const bool low_form = opt.dtype != JF_C128;  // complex64 or split form requested
+  CostModel cm_form;  // the requested form's model (complex128: the defaults)
+  if (opt.dtype == JF_C64) cm_form.flops = 70e12;  // FP32 MFMA contraction rate measured at K = 32 to 64
   if (opt.dtype == JF_C64_BF16X6) {
-    cm.flops = 200e12;        // split form on BF16 matrix cores: the steps stay HBM-bound
-    cm.chain_flops = 120e12;  // split-form chains: measured 80-137 TFLOP/s (2^24 to 2^26 elements)
+    cm_form.flops = 200e12;        // split form on BF16 matrix cores: the steps stay HBM-bound
+    cm_form.chain_flops = 120e12;  // split-form chains: measured 80-137 TFLOP/s (2^24 to 2^26 elements)
   }
 
   auto comps = components(net);
@@ -406,6 +405,11 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
   for (auto& comp : comps) {
     LocalNet L = make_local(net, comp);
     const int N = int(L.ts.size());
+    // this component runs in the requested low form (FP32 storage up to the precision switch);
+    // cleared below for a component that is all closing part
+    bool low = low_form;
+    int elem_lo = low ? 8 : 16;
+    CostModel cm = cm_form;
     // ---- site bookkeeping: open legs of this component, output bit offsets
     ComponentProgram cp;
     cp.n_tensors = N;
@@ -539,9 +543,12 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
     // fusion below, decided on leg sets only (no tensor data), each step priced like the real
     // lowering prices it.  Used only to rank candidate paths; the lowering itself decides again.
     // Legs are the component's local ids.
-    auto fused_estimate = [&](const Path& p) -> double {
+    // maxr (optional): receives the largest intermediate of that program, log2 elements
+    auto fused_estimate = [&](const Path& p, int* maxr = nullptr) -> double {
+      if (maxr) *maxr = 1 << 20;
       Slices S;
       if (!decide_slices(p, S)) return 1e300;
+      int mr = 0;
       const std::vector<int> pos = positions(p);
       // legs the slicing removes, and the levels' starts (the factor each multiplies the work by)
       std::vector<char> gone(L.nl, 0);
@@ -639,6 +646,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           const bool final_step = (e == N);
           const int out_e = low ? (((k >= sw) || final_step) ? 16 : 8) : 16;
           const int rC = rA - kS + kN;
+          mr = std::max({mr, rA, final_step ? 0 : rC});
           const double by = std::ldexp(double(in_e), rA) + std::ldexp(double(out_e), rC);
           const double fl = 8.0 * std::ldexp(1.0, rA + kN);
           const double t_step = std::max(by / cm.bw, fl / cm.flops) + cm.launch;
@@ -650,7 +658,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
           std::sort(Sv.begin(), Sv.end(), [&](int a, int b) { return posT[a] < posT[b]; });
           std::sort(Nv.begin(), Nv.end(), [&](int a, int b) { return L.glob[a] < L.glob[b]; });
           ChainCand cc;
-          if (opt.dtype != JF_C128 && k < sw && !final_step && kS == kN && kS >= 1 && kS <= 5) {
+          if (low && k < sw && !final_step && kS == kN && kS >= 1 && kS <= 5) {
             // a block with a noise operator keeps it as an FP32 pair; the lowering chains such
             // steps in complex64, but the estimate leaves them out: counted in, they drew the
             // path search to longer chains over small intermediates, whose few tiles leave most
@@ -703,6 +711,7 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       }
       // with sliced wires every leaf adds its output into the component's
       if (!S.wires.empty()) est += mult * (cm.launch + 32.0 * std::ldexp(1.0, cp.n_open_bits - sliced_bits) / cm.bw);
+      if (maxr) *maxr = mr;
       return est;
     };
     // tier 0: Kraus slicing suffices; 1: wire slices too; 2: beyond kMaxWireSlices.  A path that
@@ -740,99 +749,124 @@ Program plan_program(const jf_circuit& c, const PlanOptions& opt) {
       if (L.ts[i]->site >= 0) starts.push_back(i);
     if (N <= 24)
       for (int i = 0; i < N; ++i) starts.push_back(i);
-    for (int s : starts) {
-      Path p = greedy(L, s, rng, 0.0);
-      evaluate(p, have && best.tier == 0);
-      consider(p);
-    }
-    // The default search is also sized to the stakes: when the deterministic starts already give a
-    // program estimated under 200 us of device time, seconds of host search could save only
-    // microseconds, so it takes 512 restarts (an explicit effort is kept as given).
-    const int tries_total = (opt.restarts <= 0 && N > 24 && have && best.tier == 0 && best.est < 2e-4)
-                                ? std::min(restarts_total, 512)
-                                : restarts_total;
-    {
-      // Randomised restarts on a thread pool.  Each worker draws its starts and Boltzmann noise
-      // from its own seeded generator and keeps its best path; the winner is chosen by the same
-      // rule in worker order, so the plan does not depend on timing (the time cap only guards
-      // pathological inputs).
-      const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
-      std::vector<Path> wbest(workers);
-      std::vector<int> whave(workers, 0);
-      auto work = [&](int w) {
-        std::mt19937_64 wr(opt.seed * 7919u + 104729u * unsigned(w + 1) + unsigned(N));
-        std::uniform_int_distribution<int> pick(0, N - 1);
-        const int mine = tries_total / workers + (w < tries_total % workers ? 1 : 0);
-        Path bestw;
-        bool hv = false;
-        for (int tries = 0; tries < mine; ++tries) {
-          double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-          if (el > opt.time_budget_s && tries >= 8) break;
-          int s = (tries % 2 == 0 && !starts.empty()) ? starts[(tries / 2 + w) % starts.size()] : pick(wr);
-          Path p = greedy(L, s, wr, 0.5 + ((tries + w) % 5) * 0.5);
-          evaluate(p, hv && bestw.tier == 0);
-          if (!hv || better_path(p, bestw)) {
-            bestw = std::move(p);
-            hv = true;
-          }
-        }
-        wbest[w] = std::move(bestw);
-        whave[w] = hv;
-      };
-      std::vector<std::thread> pool;
-      for (int w = 1; w < workers; ++w) pool.emplace_back(work, w);
-      work(0);
-      for (auto& th : pool) th.join();
-      for (int w = 0; w < workers; ++w)
-        if (whave[w]) consider(wbest[w]);
-    }
-
-    // ---- local search on the winner: move single absorptions by up to four places while the
-    // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
-    // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
-    // Part of a thorough search only (>= 2^12 restarts): its sweeps cost O(tensors^2).
-    if (have && best.tier <= 1 && (tries_total >= 4096 || N <= 24)) {
-      auto recompute = [&](Path& p) {
-        std::vector<char> inT(L.nl, 0);
-        int width = 0;
-        p.width.clear();
-        p.uni.clear();
-        p.cost = 0;
-        p.maxw = 0;
-        for (int ci : p.order) {
-          int shared = 0;
-          for (int l : L.legs[ci]) shared += inT[l];
-          const int nnew = int(L.legs[ci].size()) - shared;
-          const int uni = width + nnew;
-          for (int l : L.legs[ci]) inT[l] ^= 1;
-          width = width - shared + nnew;
-          p.width.push_back(width);
-          p.uni.push_back(uni);
-          p.cost += std::ldexp(1.0, uni);
-          p.maxw = std::max(p.maxw, width);
-        }
-      };
-      bool improved = true;
-      for (int sweep = 0; improved && sweep < 8; ++sweep) {
-        improved = false;
-        for (int i = 0; i < N; ++i)
-          for (int d = -4; d <= 4; ++d) {  // move absorption i by up to four places
-            const int j = i + d;
-            if (d == 0 || j < 0 || j >= N) continue;
-            Path q = best;
-            const int v = q.order[i];
-            q.order.erase(q.order.begin() + i);
-            q.order.insert(q.order.begin() + j, v);
-            recompute(q);
-            if (best.tier == 0 && base_width(q) > opt.cap_log2) continue;
-            evaluate(q, best.tier == 0);
-            if (q.tier < best.tier || (q.tier == best.tier && q.est < best.est * (1 - 1e-9))) {
-              best = std::move(q);
-              improved = true;
+    const std::mt19937_64 rng_at_search = rng;
+    std::mt19937_64 rng_after_search = rng;
+    for (int attempt = 0;; ++attempt) {
+      best = Path();
+      best.cost = 1e300;
+      have = false;
+      for (int s : starts) {
+        Path p = greedy(L, s, rng, 0.0);
+        evaluate(p, have && best.tier == 0);
+        consider(p);
+      }
+      // The default search is also sized to the stakes: when the deterministic starts already give a
+      // program estimated under 200 us of device time, seconds of host search could save only
+      // microseconds, so it takes 512 restarts (an explicit effort is kept as given).
+      const int tries_total = (opt.restarts <= 0 && N > 24 && have && best.tier == 0 && best.est < 2e-4)
+                                  ? std::min(restarts_total, 512)
+                                  : restarts_total;
+      {
+        // Randomised restarts on a thread pool.  Each worker draws its starts and Boltzmann noise
+        // from its own seeded generator and keeps its best path; the winner is chosen by the same
+        // rule in worker order, so the plan does not depend on timing (the time cap only guards
+        // pathological inputs).
+        const int workers = std::max(1, std::min(opt.threads, int(std::thread::hardware_concurrency())));
+        std::vector<Path> wbest(workers);
+        std::vector<int> whave(workers, 0);
+        auto work = [&](int w) {
+          std::mt19937_64 wr(opt.seed * 7919u + 104729u * unsigned(w + 1) + unsigned(N));
+          std::uniform_int_distribution<int> pick(0, N - 1);
+          const int mine = tries_total / workers + (w < tries_total % workers ? 1 : 0);
+          Path bestw;
+          bool hv = false;
+          for (int tries = 0; tries < mine; ++tries) {
+            double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > opt.time_budget_s && tries >= 8) break;
+            int s = (tries % 2 == 0 && !starts.empty()) ? starts[(tries / 2 + w) % starts.size()] : pick(wr);
+            Path p = greedy(L, s, wr, 0.5 + ((tries + w) % 5) * 0.5);
+            evaluate(p, hv && bestw.tier == 0);
+            if (!hv || better_path(p, bestw)) {
+              bestw = std::move(p);
+              hv = true;
             }
           }
+          wbest[w] = std::move(bestw);
+          whave[w] = hv;
+        };
+        std::vector<std::thread> pool;
+        for (int w = 1; w < workers; ++w) pool.emplace_back(work, w);
+        work(0);
+        for (auto& th : pool) th.join();
+        for (int w = 0; w < workers; ++w)
+          if (whave[w]) consider(wbest[w]);
       }
-    }
+
+      // ---- local search on the winner: move single absorptions by up to four places while the
+      // fused estimate drops (the greedy choice is made one absorption at a time; a move can undo
+      // a locally narrow but globally costly choice).  Deterministic; converges in a few sweeps.
+      // Part of a thorough search only (>= 2^12 restarts): its sweeps cost O(tensors^2).
+      if (have && best.tier <= 1 && (tries_total >= 4096 || N <= 24)) {
+        auto recompute = [&](Path& p) {
+          std::vector<char> inT(L.nl, 0);
+          int width = 0;
+          p.width.clear();
+          p.uni.clear();
+          p.cost = 0;
+          p.maxw = 0;
+          for (int ci : p.order) {
+            int shared = 0;
+            for (int l : L.legs[ci]) shared += inT[l];
+            const int nnew = int(L.legs[ci].size()) - shared;
+            const int uni = width + nnew;
+            for (int l : L.legs[ci]) inT[l] ^= 1;
+            width = width - shared + nnew;
+            p.width.push_back(width);
+            p.uni.push_back(uni);
+            p.cost += std::ldexp(1.0, uni);
+            p.maxw = std::max(p.maxw, width);
+          }
+        };
+        bool improved = true;
+        for (int sweep = 0; improved && sweep < 8; ++sweep) {
+          improved = false;
+          for (int i = 0; i < N; ++i)
+            for (int d = -4; d <= 4; ++d) {  // move absorption i by up to four places
+              const int j = i + d;
+              if (d == 0 || j < 0 || j >= N) continue;
+              Path q = best;
+              const int v = q.order[i];
+              q.order.erase(q.order.begin() + i);
+              q.order.insert(q.order.begin() + j, v);
+              recompute(q);
+              if (best.tier == 0 && base_width(q) > opt.cap_log2) continue;
+              evaluate(q, best.tier == 0);
+              if (q.tier < best.tier || (q.tier == best.tier && q.est < best.est * (1 - 1e-9))) {
+                best = std::move(q);
+                improved = true;
+              }
+            }
+        }
+      }
+
+      // A component whose program keeps every intermediate within the FP64 closing size
+      // (2^switch_log2 elements) is closing part from its first tensor: in the low forms it is
+      // planned again as complex128 (FP64 storage and arithmetic, the complex128 path), since its
+      // launches are latency-bound and a complex64 start would only add FP32 steps and rounding.
+      // The generator continues as after a single search, so later components plan as before.
+      int best_maxr = 1 << 20;
+      if (attempt == 0 && low && have && best.tier == 0) fused_estimate(best, &best_maxr);
+      if (attempt == 0 && low && best_maxr <= opt.switch_log2) {
+        low = false;
+        elem_lo = 16;
+        cm = CostModel();
+        rng_after_search = rng;
+        rng = rng_at_search;
+        continue;
+      }
+      if (attempt > 0) rng = rng_after_search;
+      break;
+    }  // attempt
 
     // ---- slicing of the chosen path
     const Path& pth = best;

@@ -412,6 +412,27 @@ def test_describe_bit_positions_are_consistent():
             assert d["compute"] in ("f64", "f32", "f32x2", "split", "split4")
 
 
+def test_components_within_the_closing_size_plan_as_complex128():
+    # a component whose program never holds more than 2^12 elements is closing part from its first
+    # tensor: the low forms plan it as complex128 (the 36-qubit chain: all six components), while
+    # a component with larger intermediates keeps its FP32 steps (the n=16 workload)
+    inst = gen.config5()
+    shape = ("comp", "step", "kS", "kN", "L", "rA", "rC", "tiles", "in_prec", "out_prec", "compute")
+    ref = [tuple(x[k] for k in shape) for x in jf.plan(inst, 2, "c128").describe()]
+    for dt in ("c64", "bf16x6"):
+        p = jf.plan(inst, 2, dt)
+        assert p.info()["max_log2_intermediate"] <= 12
+        assert [tuple(x[k] for k in shape) for x in p.describe()] == ref, dt
+    d = jf.plan(gen.config2(), 1, "c64").describe()
+    assert any(x["compute"] == "f32" and x["rA"] > 12 for x in d)
+    # small Algorithm I circuits too: the complex64 plan runs the complex128 program
+    small = gen.random_circuit(5, 60, 2, 1e-3, 0.05, 11)
+    p64, p128 = jf.plan(small, 1, "c64"), jf.plan(small, 1, "c128")
+    assert p64.info()["max_log2_intermediate"] <= 12
+    assert [tuple(x[k] for k in shape) for x in p64.describe()] == [tuple(x[k] for k in shape) for x in p128.describe()]
+    assert np.array_equal(p64.emulate(), p128.emulate())
+
+
 def test_estimated_time_grows_with_the_work():
     small = jf.plan(gen.random_circuit(6, 80, 2, 1e-3, 0.05, 5), 1, "c64").stats()["est_seconds"]
     large = jf.plan(gen.config2(), 1, "c64").stats()["est_seconds"]
