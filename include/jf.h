@@ -61,8 +61,10 @@ typedef enum {
                         (the three dropped ones are below 2^-24 of the product); noise-carrying
                         operators keep a fourth piece, the BF16 residual of the FP64 operator */
 } jf_dtype;
-/* In every dtype the closing (small) contractions, the traces t_k, sum_k |t_k|^2 (Kahan-
- * compensated) and 1 - F_J are evaluated in FP64 on the GPU. */
+/* In every dtype the closing contractions (the steps after which every intermediate stays within
+ * 2^12 elements; a component whose whole program stays within that size runs the complex128
+ * program), the traces t_k, sum_k |t_k|^2 (double-double over fixed reduction trees) and 1 - F_J
+ * are evaluated in FP64 on the GPU. */
 
 typedef enum {
   JF_GATE_H = 0, JF_GATE_S, JF_GATE_SDG, JF_GATE_T, JF_GATE_TDG, JF_GATE_X, JF_GATE_Y, JF_GATE_Z,
